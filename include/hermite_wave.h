@@ -1,0 +1,168 @@
+/*
+ * hermite_wave.h -- C ABI of libhermite_wave.so: the staggered half-step of the
+ * dissipative (order 2m-1) and conservative (order 2m) Hermite methods for
+ * u_tt = c^2 Lap u (Appelo, Hagstrom & Vargas, "Hermite Methods for the Scalar
+ * Wave Equation"), on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sec. 2.1, Sec. 3, Sec. 4):
+ *   domain prod_i [xl_i, xr_i], n_i cells, h_i = (xr_i - xl_i)/n_i;
+ *   constant speed c, time step dt with c dt <= min_i h_i (Sec. 1);
+ *   walls per dimension: periodic, homogeneous Dirichlet or homogeneous Neumann
+ *   (Sec. 3.1.3: ghost polynomials by odd / even extension);
+ *   nodal degree m: (m+1)^d coefficients of u per node, m^d of v (dissipative).
+ *
+ * Grids (Sec. 2.1).  Primal nodes x_i = xl + i h, dual nodes x_{i+1/2}.  Periodic
+ * dimensions carry n_i nodes on both grids; other dimensions carry n_i + 1 primal
+ * nodes (i = 0..n_i) and n_i dual nodes.  A half step maps the data of one grid at
+ * time t to the other grid at t + dt/2 (dissipative), or updates one grid from
+ * t - dt/2 to t + dt/2 using the other grid at t (conservative, Sec. 4.1).
+ *
+ * Array layout at this boundary.  Every state array is FP64, node-major with the
+ * node index i0 + n0*(i1 + n1*i2) (x fastest), coefficient-minor with the
+ * coefficient index l0 + M*(l1 + M*l2) (l_x fastest), M = m+1 for u and M = m for
+ * v.  Values are the scaled Taylor coefficients h^l/l! d^l f of Sec. 2.2 (v is
+ * scaled in space only).  All array pointers passed in are DEVICE pointers owned
+ * by the caller; the library copies from / into them on the given stream and
+ * keeps no reference after the call returns.  Internally the state may be held in
+ * FP32 (HW_FP32); conversion happens at set/get time.
+ *
+ * Errors.  Every call returns a status; none aborts or throws across the ABI.
+ * hw_last_error() gives a thread-local message for the last failure.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ * asynchronous on that stream except hw_energy, which synchronises it.
+ */
+#ifndef HERMITE_WAVE_H
+#define HERMITE_WAVE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HW_OK = 0,
+    HW_EINVAL = -1,       /* bad argument (null pointer, d, m, n, bc, method...) */
+    HW_ECFL = -2,         /* c dt > min_i h_i (1 + 1e-12): outside the stability bound */
+    HW_ENOMEM = -3,       /* device allocation failed */
+    HW_EUNSUPPORTED = -4, /* no kernel for this (d, m, method, precision, kernel) */
+    HW_EHIP = -5,         /* a HIP runtime call failed */
+    HW_ESTATE = -6        /* call out of order (e.g. stepping before set_state) */
+} hw_status;
+
+typedef enum {
+    HW_DISS_FULL = 0,    /* dissipative, modified first step for d >= 2 (Sec. 3.3) */
+    HW_DISS_SIMPLE = 1,  /* dissipative, straightforward tensor extension (Sec. 3.3) */
+    HW_CONSERVATIVE = 2  /* conservative (Sec. 4.1, Sec. 4.3) */
+} hw_method;
+
+typedef enum { HW_PERIODIC = 0, HW_DIRICHLET = 1, HW_NEUMANN = 2 } hw_bc;
+
+typedef enum {
+    HW_FP64 = 0, /* FP64 storage and arithmetic */
+    HW_FP32 = 1, /* FP32 storage; FP32 MFMA contractions where a tiled kernel exists */
+    HW_BF16 = 2  /* FP32 storage, BF16 MFMA operands with FP32 accumulation (tiled only) */
+} hw_precision;
+
+typedef enum {
+    HW_KERNEL_AUTO = 0,    /* tiled MFMA kernel when one exists for the problem, else generic */
+    HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
+    HW_KERNEL_TILED = 2    /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
+} hw_kernel;
+
+typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;
+
+typedef struct {
+    int d;            /* space dimension, 1..3 */
+    int m;            /* nodal degree: dissipative 1..6, conservative 0..6 */
+    int n[3];         /* cells per dimension (>= 2); entries beyond d ignored */
+    double xl[3];     /* lower domain bound per dimension */
+    double xr[3];     /* upper domain bound per dimension (> xl) */
+    double c;         /* wave speed (> 0) */
+    double dt;        /* time step (> 0), c dt <= min h_i */
+    int bc[3];        /* hw_bc per dimension */
+    int method;       /* hw_method */
+    int precision;    /* hw_precision */
+    int taylor_stages;/* 0: exact (terminating) Taylor series in time; s > 0: keep
+                         stages 0..s only (the truncated series of Sec. 6.1), dissipative */
+    int kernel;       /* hw_kernel */
+} hw_problem;
+
+typedef struct hw_solver hw_solver;
+
+/* Validate the problem and allocate the state buffers on the current device.
+ * Sec. 2.1 (grids), Sec. 1 (c dt <= h).  *out is set only on HW_OK. */
+hw_status hw_create(const hw_problem* p, hw_solver** out);
+
+/* Free everything the solver owns (NULL is accepted). */
+void hw_destroy(hw_solver* s);
+
+/* Node count of `grid` and the number of u and v coefficients per node
+ * (v count is 0 for the conservative method).  Any output pointer may be NULL. */
+hw_status hw_layout(const hw_solver* s, int grid, int64_t* n_nodes, int* n_u_coef,
+                    int* n_v_coef);
+
+/* Set the state at time t0 = 0.
+ * Dissipative: u_primal, v_or_u_dual = u and v on the primal grid (Sec. 3.1.1).
+ * Conservative: u_primal = u on the primal grid at t0, v_or_u_dual = u on the dual
+ * grid at t0 + dt/2 (the two time levels of Sec. 4.1). */
+hw_status hw_set_state(hw_solver* s, const double* u_primal, const double* v_or_u_dual,
+                       void* stream);
+
+/* Conservative only: build both levels from u0 (and v0, or NULL for v0 = 0), both
+ * primal arrays of (m+1)^d coefficients; the dual level at t0 + dt/2 is the exact
+ * Taylor evolution of the degree-m cell interpolants (start-up step). */
+hw_status hw_cons_startup(hw_solver* s, const double* u0, const double* v0_or_null,
+                          void* stream);
+
+/* Advance n full steps (2n half steps, Sec. 3.1.2 / Sec. 4.1).  The step loop is
+ * captured once per (n, buffer parity) in a hipGraph and replayed on `stream`.
+ * Dissipative: requires the state on the primal grid. */
+hw_status hw_advance(hw_solver* s, int n_full_steps, void* stream);
+
+/* Advance n half steps with plain kernel launches (no graph). */
+hw_status hw_half_steps(hw_solver* s, int n_half, void* stream);
+
+/* Copy the state out (device pointers, FP64, layouts as above).
+ * Dissipative: u and v of the grid that holds the state (hw_state_grid).
+ * Conservative: u on the primal grid and u on the dual grid (newest levels). */
+hw_status hw_get_state(const hw_solver* s, double* u, double* v_or_u_dual, void* stream);
+
+/* Grid that holds the dissipative state (HW_PRIMAL after whole steps); for the
+ * conservative method, the grid updated last.  -1 on a NULL solver. */
+int hw_state_grid(const hw_solver* s);
+
+/* Conservative only: the discrete energy 2(|p_A|^2 - <p_B^new, p_B^old>) in the
+ * |.|_{m+1} seminorm (Sec. 4.2 eq. (Vconst), Sec. 5.2), A = the grid not updated
+ * last, B = the grid updated last with its new and previous levels.  Cells
+ * straddling a non-periodic wall weigh 1/2 per such dimension.  FP64 accumulation,
+ * deterministic order.  Synchronises `stream`.  HW_ESTATE before the first step. */
+hw_status hw_energy(hw_solver* s, double* e_out, void* stream);
+
+/* Simulated time of the primal level: t0 + (half steps applied)/2 * dt for the
+ * dissipative method; the primal level's time for the conservative method. */
+double hw_time(const hw_solver* s);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char* hw_last_error(void);
+
+/* ---- batches: independent problems advanced together --------------------------
+ * All problems of a batch share d and precision; n, m, c, dt, walls and method may
+ * differ.  Each half step of the whole batch is one launch of a grid-stride kernel
+ * over a work list of (problem, cell); hw_batch_advance captures the step loop in a
+ * hipGraph. */
+hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out);
+hw_status hw_batch_layout(const hw_solver* b, int i, int grid, int64_t* n_nodes, int* n_u_coef,
+                          int* n_v_coef);
+hw_status hw_batch_set_state(hw_solver* b, int i, const double* u_primal,
+                             const double* v_or_u_dual, void* stream);
+hw_status hw_batch_cons_startup(hw_solver* b, int i, const double* u0, const double* v0_or_null,
+                                void* stream);
+hw_status hw_batch_advance(hw_solver* b, int n_full_steps, void* stream);
+hw_status hw_batch_get_state(const hw_solver* b, int i, double* u, double* v_or_u_dual,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,691 @@
+// Host side of libhermite_wave: validation, state buffers, per-problem weight
+// tables, the half-step sequence and its hipGraph capture, the energy reduction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hermite_wave.h"
+#include "hermite_tables.h"
+#include "hw_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hw_status fail(hw_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(HW_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));          \
+    } while (0)
+
+double fact(int n)
+{
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+int ipow(int b, int e)
+{
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+struct Prob {
+    hw_problem p{};
+    int ext[2][3]{};      // node extents [grid][dim]
+    int64_t nodes[2]{};
+    int Mu = 0, Mv = 0;   // coefficients per node of u and v
+    void* u[2][2]{};      // [grid][slot]
+    void* v[2]{};         // dissipative: [grid]
+    void* v0tmp = nullptr;
+    double h[3]{};
+};
+
+} // namespace
+
+struct hw_solver {
+    std::vector<Prob> probs;
+    int d = 0;
+    bool fp64 = true;
+    int precision = HW_FP64;
+    bool use_tiled = false;
+    bool state_set = false;
+    int64_t half_steps = 0;
+    size_t elem = 8;
+    // device-side tables
+    void* ops = nullptr;          // operator pool in the state precision
+    double* dops = nullptr;       // FP64 pool for the energy kernel
+    std::vector<OpOffsets> op_off; // per m
+    std::vector<int> hi_off, gram_off;
+    ProblemDesc* descs = nullptr; // [phase 0..1][slot parity 0..1][nprob]
+    ProblemDesc* startup_desc = nullptr;
+    int64_t* startup_prefix = nullptr;
+    int64_t* prefix = nullptr;
+    std::vector<int64_t> h_prefix;
+    int64_t total_cells[2]{};     // per phase
+    size_t lds = 0;
+    int grid = 0;
+    double* partials = nullptr;
+    int energy_grid = 0;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<ProblemDesc> h_descs;
+};
+
+namespace {
+
+hw_status validate(const hw_problem* p)
+{
+    if (!p) return fail(HW_EINVAL, "null problem");
+    if (p->d < 1 || p->d > 3) return fail(HW_EINVAL, "d = %d outside 1..3", p->d);
+    if (p->method < HW_DISS_FULL || p->method > HW_CONSERVATIVE)
+        return fail(HW_EINVAL, "unknown method %d", p->method);
+    const int mlo = (p->method == HW_CONSERVATIVE) ? 0 : 1;
+    if (p->m < mlo || p->m > HW_MAXM)
+        return fail(HW_EINVAL, "m = %d outside %d..%d for this method", p->m, mlo, HW_MAXM);
+    if (p->precision < HW_FP64 || p->precision > HW_BF16)
+        return fail(HW_EINVAL, "unknown precision %d", p->precision);
+    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_TILED)
+        return fail(HW_EINVAL, "unknown kernel selector %d", p->kernel);
+    if (!(p->c > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->c) || !std::isfinite(p->dt))
+        return fail(HW_EINVAL, "c and dt must be positive and finite");
+    if (p->taylor_stages < 0) return fail(HW_EINVAL, "taylor_stages must be >= 0");
+    double hmin = 1e300;
+    for (int i = 0; i < p->d; ++i) {
+        if (p->n[i] < 2) return fail(HW_EINVAL, "n[%d] = %d < 2", i, p->n[i]);
+        if (!(p->xr[i] > p->xl[i])) return fail(HW_EINVAL, "xr[%d] <= xl[%d]", i, i);
+        if (p->bc[i] < HW_PERIODIC || p->bc[i] > HW_NEUMANN)
+            return fail(HW_EINVAL, "unknown boundary condition %d in dim %d", p->bc[i], i);
+        hmin = std::fmin(hmin, (p->xr[i] - p->xl[i]) / p->n[i]);
+    }
+    int64_t nodes = 1;
+    for (int i = 0; i < p->d; ++i) nodes *= (int64_t)p->n[i] + 1;
+    if (nodes * ipow(p->m + 1, p->d) > ((int64_t)1 << 40))
+        return fail(HW_EINVAL, "problem too large");
+    if (nodes > INT32_MAX) return fail(HW_EINVAL, "more than 2^31 nodes per grid");
+    if (p->c * p->dt > hmin * (1.0 + 1e-12))
+        return fail(HW_ECFL, "c*dt = %.17g exceeds min h = %.17g (stability needs c dt <= h)",
+                    p->c * p->dt, hmin);
+    return HW_OK;
+}
+
+void fill_geometry(Prob& P)
+{
+    const hw_problem& p = P.p;
+    for (int g = 0; g < 2; ++g) {
+        P.nodes[g] = 1;
+        for (int i = 0; i < 3; ++i) {
+            int e = 1;
+            if (i < p.d) e = (p.bc[i] == HW_PERIODIC) ? p.n[i] : (g == 0 ? p.n[i] + 1 : p.n[i]);
+            P.ext[g][i] = e;
+            P.nodes[g] *= e;
+        }
+    }
+    P.Mu = ipow(p.m + 1, p.d);
+    P.Mv = (p.method == HW_CONSERVATIVE) ? 0 : ipow(p.m, p.d);
+    for (int i = 0; i < 3; ++i) P.h[i] = i < p.d ? (p.xr[i] - p.xl[i]) / p.n[i] : 1.0;
+}
+
+// Operator pools: per m, H_m (full), its scaled second-derivative rows, H_{m-1} on
+// the u inputs and H_{m-1} on the v inputs; FP64 pool adds the energy operators.
+void build_ops(hw_solver* s, std::vector<double>& pool, std::vector<double>& dpool)
+{
+    s->op_off.assign(HW_MAXM + 1, OpOffsets{0, 0, 0, 0});
+    s->hi_off.assign(HW_MAXM + 1, 0);
+    s->gram_off.assign(HW_MAXM + 1, 0);
+    for (int m = 0; m <= HW_MAXM; ++m) {
+        const int M = m + 1, P = 2 * m + 2, K = 2 * M;
+        const double* Hm = kHermiteAll + kHermiteOffset[m];
+        OpOffsets o;
+        o.full = (int)pool.size();
+        for (int r = 0; r < P; ++r)
+            for (int k = 0; k < K; ++k) pool.push_back(Hm[r * P + k]);
+        o.d2 = (int)pool.size();
+        for (int r = 0; r < 2 * m; ++r)
+            for (int k = 0; k < K; ++k) pool.push_back(Hm[(r + 2) * P + k] * (r + 2) * (r + 1));
+        o.trunc = (int)pool.size();
+        o.vop = o.trunc;
+        if (m >= 1) {
+            const double* Hv = kHermiteAll + kHermiteOffset[m - 1];
+            const int Pv = 2 * m;
+            for (int r = 0; r < Pv; ++r)
+                for (int k = 0; k < K; ++k) {
+                    const int sd = k / M, l = k % M;
+                    pool.push_back(l < m ? Hv[r * Pv + sd * m + l] : 0.0);
+                }
+            o.vop = (int)pool.size();
+            for (int r = 0; r < Pv; ++r)
+                for (int k = 0; k < Pv; ++k) pool.push_back(Hv[r * Pv + k]);
+        }
+        s->op_off[m] = o;
+        // energy: rows m+1..P-1 of H_m, and the Gram block of the (m+1)-th derivative
+        s->hi_off[m] = (int)dpool.size();
+        for (int r = M; r < P; ++r)
+            for (int k = 0; k < K; ++k) dpool.push_back(Hm[r * P + k]);
+        s->gram_off[m] = (int)dpool.size();
+        const int q = m + 1;
+        for (int a = q; a < P; ++a)
+            for (int b = q; b < P; ++b) {
+                const int e = a + b - 2 * q;
+                const double integral = (e % 2) ? 0.0 : 2.0 * std::pow(0.5, e + 1) / (e + 1);
+                dpool.push_back(fact(a) / fact(a - q) * fact(b) / fact(b - q) * integral);
+            }
+    }
+}
+
+void fill_weights(const Prob& P, ProblemDesc& D)
+{
+    const hw_problem& p = P.p;
+    const double tau = 0.5 * p.dt;
+    D.tau = tau;
+    std::memset(D.F, 0, sizeof D.F);
+    for (int i = 0; i < 3; ++i) {
+        const double lam = (i < p.d) ? p.c * p.dt / P.h[i] : 0.0;
+        const double q = 0.25 * lam * lam; // (lambda/2)^2
+        D.lam2[i] = q;
+        for (int a = 0; a <= HW_MAXM + 1; ++a)
+            for (int b = 0; b <= HW_MAXM + 1; ++b)
+                D.F[i][a][b] = fact(a + 2 * b) / fact(a) * std::pow(q, b) / fact(b);
+    }
+    const int S = p.taylor_stages;
+    auto keep = [S](int s) { return S <= 0 || s <= S; };
+    for (int j = 0; j < HW_MAXJ; ++j) {
+        const double jf = fact(j);
+        if (p.method == HW_CONSERVATIVE) {
+            D.cuQ[j] = jf / fact(2 * j);
+            D.cuR[j] = tau * jf / fact(2 * j + 1);
+            D.cvQ[j] = D.cvR[j] = 0.0;
+        } else {
+            D.cuQ[j] = keep(2 * j + 1) ? tau * jf / fact(2 * j + 1) : 0.0;
+            D.cuR[j] = keep(2 * j + 2) ? jf / fact(2 * j + 2) : 0.0;
+            D.cvQ[j] = keep(2 * j) ? jf / fact(2 * j) : 0.0;
+            D.cvR[j] = keep(2 * j + 1) ? jf / (tau * fact(2 * j + 1)) : 0.0;
+        }
+    }
+}
+
+// descriptor of problem P for half step `phase` (0: first half of a full step) with
+// conservative slot parity q
+ProblemDesc make_desc(const hw_solver* s, const Prob& P, int phase, int q)
+{
+    ProblemDesc D;
+    std::memset(&D, 0, sizeof D);
+    const hw_problem& p = P.p;
+    D.d = p.d;
+    D.m = p.m;
+    for (int i = 0; i < 3; ++i) D.bc[i] = (i < p.d) ? p.bc[i] : HW_PERIODIC;
+    D.op = s->op_off[p.m];
+    fill_weights(P, D);
+    if (p.method == HW_CONSERVATIVE) {
+        D.variant = HWV_CONS;
+        const int to = phase == 0 ? HW_PRIMAL : HW_DUAL;
+        const int from = 1 - to;
+        // phase 0 reads the dual at slot q, phase 1 the primal just written (slot 1-q)
+        const int from_slot = (phase == 0) ? q : 1 - q;
+        D.to_grid = to;
+        D.u_in = P.u[from][from_slot];
+        D.u_old = P.u[to][q];
+        D.u_out = P.u[to][1 - q];
+        for (int i = 0; i < 3; ++i) {
+            D.ext_from[i] = P.ext[from][i];
+            D.ext_to[i] = P.ext[to][i];
+        }
+        D.n_out = (int)P.nodes[to];
+    } else {
+        D.variant = (p.method == HW_DISS_SIMPLE) ? HWV_DISS_SIMPLE : HWV_DISS_FULL;
+        const int from = phase == 0 ? HW_PRIMAL : HW_DUAL;
+        const int to = 1 - from;
+        D.to_grid = to;
+        D.u_in = P.u[from][0];
+        D.v_in = P.v[from];
+        D.u_out = P.u[to][0];
+        D.v_out = P.v[to];
+        for (int i = 0; i < 3; ++i) {
+            D.ext_from[i] = P.ext[from][i];
+            D.ext_to[i] = P.ext[to][i];
+        }
+        D.n_out = (int)P.nodes[to];
+    }
+    return D;
+}
+
+hw_status check_solver(const hw_solver* s)
+{
+    if (!s) return fail(HW_EINVAL, "null solver");
+    return HW_OK;
+}
+
+hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
+{
+    const int np = (int)s->probs.size();
+    if (s->use_tiled) {
+        const Prob& P = s->probs[0];
+        const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np];
+        TiledArgs a;
+        for (int i = 0; i < 3; ++i) {
+            a.ext_from[i] = D.ext_from[i];
+            a.ext_to[i] = D.ext_to[i];
+            a.bc[i] = D.bc[i];
+            a.lam2[i] = D.lam2[i];
+        }
+        a.to_grid = D.to_grid;
+        a.u_in = D.u_in;
+        a.v_in = D.v_in;
+        a.u_out = D.u_out;
+        a.v_out = D.v_out;
+        a.tau = D.tau;
+        (void)P;
+        HIP_TRY(hw_launch_tiled(a, s->precision, st));
+        return HW_OK;
+    }
+    const ProblemDesc* descs = s->descs + (size_t)(phase * 2 + q) * np;
+    const int64_t* prefix = s->prefix + (size_t)phase * (np + 1);
+    HIP_TRY(hw_launch_generic(s->d, s->fp64, descs, prefix, np, s->total_cells[phase], s->ops, s->lds,
+                              s->grid, st));
+    return HW_OK;
+}
+
+hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
+{
+    if (!out) return fail(HW_EINVAL, "null output pointer");
+    if (!ps || count < 1) return fail(HW_EINVAL, "need at least one problem");
+    for (int i = 0; i < count; ++i) {
+        hw_status st = validate(&ps[i]);
+        if (st != HW_OK) {
+            std::string msg = g_err;
+            return fail(st, "problem %d: %s", i, msg.c_str());
+        }
+        if (ps[i].d != ps[0].d) return fail(HW_EINVAL, "batch problems must share d");
+        if ((ps[i].precision == HW_FP64) != (ps[0].precision == HW_FP64))
+            return fail(HW_EINVAL, "batch problems must share the precision");
+    }
+    const hw_problem& p0 = ps[0];
+    const bool tiled_ok = count == 1 && hw_tiled_supported(p0.d, p0.m, p0.method, p0.precision);
+    if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
+        return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
+                    p0.m, p0.method, p0.precision);
+    if (p0.precision == HW_BF16 && !tiled_ok)
+        return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel");
+    for (int i = 0; i < count; ++i)
+        if (ps[i].taylor_stages > 0 && ps[i].method == HW_CONSERVATIVE)
+            return fail(HW_EINVAL, "taylor_stages applies to the dissipative method only");
+
+    hw_solver* s = new hw_solver();
+    s->d = p0.d;
+    s->precision = p0.precision;
+    s->fp64 = (p0.precision == HW_FP64);
+    s->elem = s->fp64 ? 8 : 4;
+    s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.taylor_stages == 0;
+    s->probs.resize(count);
+    auto cleanup = [&](hw_status st) {
+        hw_destroy(s);
+        return st;
+    };
+    for (int i = 0; i < count; ++i) {
+        Prob& P = s->probs[i];
+        P.p = ps[i];
+        fill_geometry(P);
+        const bool cons = P.p.method == HW_CONSERVATIVE;
+        for (int g = 0; g < 2; ++g) {
+            for (int sl = 0; sl < (cons ? 2 : 1); ++sl)
+                if (hipMalloc(&P.u[g][sl], (size_t)P.nodes[g] * P.Mu * s->elem) != hipSuccess)
+                    return cleanup(fail(HW_ENOMEM, "state allocation failed (problem %d)", i));
+            if (!cons && hipMalloc(&P.v[g], (size_t)P.nodes[g] * P.Mv * s->elem) != hipSuccess)
+                return cleanup(fail(HW_ENOMEM, "state allocation failed (problem %d)", i));
+        }
+    }
+    // operator pools
+    std::vector<double> pool, dpool;
+    build_ops(s, pool, dpool);
+    if (hipMalloc(&s->ops, pool.size() * s->elem) != hipSuccess ||
+        hipMalloc(&s->dops, dpool.size() * sizeof(double)) != hipSuccess)
+        return cleanup(fail(HW_ENOMEM, "table allocation failed"));
+    if (s->fp64) {
+        if (hipMemcpy(s->ops, pool.data(), pool.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "table upload failed"));
+    } else {
+        std::vector<float> fp(pool.begin(), pool.end());
+        if (hipMemcpy(s->ops, fp.data(), fp.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "table upload failed"));
+    }
+    if (hipMemcpy(s->dops, dpool.data(), dpool.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(HW_EHIP, "table upload failed"));
+    // descriptors [phase][q][problem] and per-phase prefix sums of output nodes
+    s->h_descs.resize((size_t)4 * count);
+    for (int ph = 0; ph < 2; ++ph)
+        for (int q = 0; q < 2; ++q)
+            for (int i = 0; i < count; ++i)
+                s->h_descs[(size_t)(ph * 2 + q) * count + i] = make_desc(s, s->probs[i], ph, q);
+    s->h_prefix.assign((size_t)2 * (count + 1), 0);
+    size_t lds = 0;
+    for (int ph = 0; ph < 2; ++ph) {
+        for (int i = 0; i < count; ++i) {
+            const ProblemDesc& D = s->h_descs[(size_t)(ph * 2) * count + i];
+            s->h_prefix[ph * (count + 1) + i + 1] = s->h_prefix[ph * (count + 1) + i] + D.n_out;
+            const int variant = (D.variant == HWV_CONS) ? HWV_CONS_STARTUP : D.variant;
+            size_t b = hw_generic_lds_bytes(s->d, D.m, variant, (int)s->elem);
+            if (b > lds) lds = b;
+        }
+        s->total_cells[ph] = s->h_prefix[ph * (count + 1) + count];
+    }
+    if (lds > 160 * 1024) return cleanup(fail(HW_EUNSUPPORTED, "LDS need %zu B exceeds 160 KiB", lds));
+    s->lds = lds;
+    int resident = (int)((160 * 1024) / lds);
+    if (resident > 16) resident = 16;
+    if (resident < 1) resident = 1;
+    int64_t g = 256LL * resident * 2;
+    const int64_t tmax = s->total_cells[0] > s->total_cells[1] ? s->total_cells[0] : s->total_cells[1];
+    if (g > tmax) g = tmax;
+    s->grid = (int)(g > 0 ? g : 1);
+    if (hipMalloc((void**)&s->descs, s->h_descs.size() * sizeof(ProblemDesc)) != hipSuccess ||
+        hipMalloc((void**)&s->prefix, s->h_prefix.size() * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void**)&s->startup_desc, sizeof(ProblemDesc)) != hipSuccess ||
+        hipMalloc((void**)&s->startup_prefix, 2 * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void**)&s->partials, 4096 * sizeof(double)) != hipSuccess)
+        return cleanup(fail(HW_ENOMEM, "descriptor allocation failed"));
+    if (hipMemcpy(s->descs, s->h_descs.data(), s->h_descs.size() * sizeof(ProblemDesc),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->prefix, s->h_prefix.data(), s->h_prefix.size() * sizeof(int64_t),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(HW_EHIP, "descriptor upload failed"));
+    if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(HW_EHIP, "stream creation failed"));
+    *out = s;
+    return HW_OK;
+}
+
+hw_status set_state_impl(hw_solver* s, int i, const double* u, const double* w, hipStream_t st)
+{
+    if (!s || i < 0 || i >= (int)s->probs.size()) return fail(HW_EINVAL, "bad solver or index");
+    if (!u || !w) return fail(HW_EINVAL, "null state pointer");
+    Prob& P = s->probs[i];
+    HIP_TRY(hw_launch_convert(u, true, P.u[HW_PRIMAL][0], s->fp64, P.nodes[0] * P.Mu, st));
+    if (P.p.method == HW_CONSERVATIVE)
+        HIP_TRY(hw_launch_convert(w, true, P.u[HW_DUAL][0], s->fp64, P.nodes[1] * P.Mu, st));
+    else
+        HIP_TRY(hw_launch_convert(w, true, P.v[HW_PRIMAL], s->fp64, P.nodes[0] * P.Mv, st));
+    return HW_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char* hw_last_error(void) { return g_err.c_str(); }
+
+hw_status hw_create(const hw_problem* p, hw_solver** out) { return create_impl(p, 1, out); }
+
+hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out)
+{
+    return create_impl(ps, count, out);
+}
+
+void hw_destroy(hw_solver* s)
+{
+    if (!s) return;
+    for (auto& kv : s->graphs) hipGraphExecDestroy(kv.second);
+    for (Prob& P : s->probs) {
+        for (int g = 0; g < 2; ++g) {
+            for (int sl = 0; sl < 2; ++sl)
+                if (P.u[g][sl]) hipFree(P.u[g][sl]);
+            if (P.v[g]) hipFree(P.v[g]);
+        }
+        if (P.v0tmp) hipFree(P.v0tmp);
+    }
+    if (s->ops) hipFree(s->ops);
+    if (s->dops) hipFree(s->dops);
+    if (s->descs) hipFree(s->descs);
+    if (s->startup_desc) hipFree(s->startup_desc);
+    if (s->startup_prefix) hipFree(s->startup_prefix);
+    if (s->prefix) hipFree(s->prefix);
+    if (s->partials) hipFree(s->partials);
+    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+    delete s;
+}
+
+hw_status hw_batch_layout(const hw_solver* s, int i, int grid, int64_t* n_nodes, int* n_u, int* n_v)
+{
+    if (!s || i < 0 || i >= (int)s->probs.size()) return fail(HW_EINVAL, "bad solver or index");
+    if (grid != HW_PRIMAL && grid != HW_DUAL) return fail(HW_EINVAL, "bad grid %d", grid);
+    const Prob& P = s->probs[i];
+    if (n_nodes) *n_nodes = P.nodes[grid];
+    if (n_u) *n_u = P.Mu;
+    if (n_v) *n_v = P.Mv;
+    return HW_OK;
+}
+
+hw_status hw_layout(const hw_solver* s, int grid, int64_t* n_nodes, int* n_u, int* n_v)
+{
+    return hw_batch_layout(s, 0, grid, n_nodes, n_u, n_v);
+}
+
+hw_status hw_batch_set_state(hw_solver* s, int i, const double* u, const double* w, void* stream)
+{
+    hw_status st = set_state_impl(s, i, u, w, (hipStream_t)stream);
+    if (st != HW_OK) return st;
+    s->half_steps = 0;
+    s->state_set = true;
+    return HW_OK;
+}
+
+hw_status hw_set_state(hw_solver* s, const double* u, const double* w, void* stream)
+{
+    return hw_batch_set_state(s, 0, u, w, stream);
+}
+
+hw_status hw_batch_cons_startup(hw_solver* s, int i, const double* u0, const double* v0, void* stream)
+{
+    if (!s || i < 0 || i >= (int)s->probs.size()) return fail(HW_EINVAL, "bad solver or index");
+    if (!u0) return fail(HW_EINVAL, "null u0");
+    Prob& P = s->probs[i];
+    if (P.p.method != HW_CONSERVATIVE) return fail(HW_EINVAL, "start-up is for the conservative method");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hw_launch_convert(u0, true, P.u[HW_PRIMAL][0], s->fp64, P.nodes[0] * P.Mu, st));
+    if (v0) {
+        if (!P.v0tmp && hipMalloc(&P.v0tmp, (size_t)P.nodes[0] * P.Mu * s->elem) != hipSuccess)
+            return fail(HW_ENOMEM, "v0 staging allocation failed");
+        HIP_TRY(hw_launch_convert(v0, true, P.v0tmp, s->fp64, P.nodes[0] * P.Mu, st));
+    }
+    ProblemDesc D = make_desc(s, P, 1, 0);
+    D.variant = HWV_CONS_STARTUP;
+    D.u_in = P.u[HW_PRIMAL][0];
+    D.v_in = v0 ? P.v0tmp : nullptr;
+    D.u_old = nullptr;
+    D.u_out = P.u[HW_DUAL][0];
+    int64_t h_pre[2] = {0, D.n_out};
+    HIP_TRY(hipMemcpyAsync(s->startup_desc, &D, sizeof D, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->startup_prefix, h_pre, sizeof h_pre, hipMemcpyHostToDevice, st));
+    const size_t lds = hw_generic_lds_bytes(s->d, P.p.m, HWV_CONS_STARTUP, (int)s->elem);
+    const int grid = (int)(D.n_out < 4096 ? D.n_out : 4096);
+    HIP_TRY(hw_launch_generic(s->d, s->fp64, s->startup_desc, s->startup_prefix, 1, D.n_out, s->ops,
+                              lds, grid, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s->half_steps = 0;
+    s->state_set = true;
+    return HW_OK;
+}
+
+hw_status hw_cons_startup(hw_solver* s, const double* u0, const double* v0, void* stream)
+{
+    return hw_batch_cons_startup(s, 0, u0, v0, stream);
+}
+
+hw_status hw_half_steps(hw_solver* s, int n, void* stream)
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (n < 0) return fail(HW_EINVAL, "negative step count");
+    if (!s->state_set) return fail(HW_ESTATE, "state not set");
+    hipStream_t st = (hipStream_t)stream;
+    for (int k = 0; k < n; ++k) {
+        const int phase = (int)(s->half_steps & 1);
+        const int q = (int)((s->half_steps >> 1) & 1);
+        hw_status r = launch_half(s, phase, q, st);
+        if (r != HW_OK) return r;
+        s->half_steps++;
+    }
+    return HW_OK;
+}
+
+hw_status hw_batch_advance(hw_solver* s, int n, void* stream)
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (n < 0) return fail(HW_EINVAL, "negative step count");
+    if (!s->state_set) return fail(HW_ESTATE, "state not set");
+    if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
+    if (n == 0) return HW_OK;
+    const int q = (int)((s->half_steps >> 1) & 1);
+    auto key = std::make_pair(n, q);
+    auto it = s->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == s->graphs.end()) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+        hw_status r = HW_OK;
+        int64_t hs = s->half_steps;
+        for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
+            r = launch_half(s, (int)(hs & 1), (int)((hs >> 1) & 1), s->cap_stream);
+        hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+        if (r != HW_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess) return fail(HW_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(HW_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        s->graphs[key] = exec;
+    } else {
+        exec = it->second;
+    }
+    HIP_TRY(hipGraphLaunch(exec, (hipStream_t)stream));
+    s->half_steps += 2 * (int64_t)n;
+    return HW_OK;
+}
+
+hw_status hw_advance(hw_solver* s, int n, void* stream) { return hw_batch_advance(s, n, stream); }
+
+hw_status hw_batch_get_state(const hw_solver* s, int i, double* u, double* w, void* stream)
+{
+    if (!s || i < 0 || i >= (int)s->probs.size()) return fail(HW_EINVAL, "bad solver or index");
+    if (!u || !w) return fail(HW_EINVAL, "null output pointer");
+    if (!s->state_set) return fail(HW_ESTATE, "state not set");
+    const Prob& P = s->probs[i];
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t h = s->half_steps;
+    if (P.p.method == HW_CONSERVATIVE) {
+        const int sp = (int)(((h + 1) / 2) & 1), sd = (int)((h / 2) & 1);
+        HIP_TRY(hw_launch_convert(P.u[HW_PRIMAL][sp], s->fp64, u, true, P.nodes[0] * P.Mu, st));
+        HIP_TRY(hw_launch_convert(P.u[HW_DUAL][sd], s->fp64, w, true, P.nodes[1] * P.Mu, st));
+    } else {
+        const int g = (int)(h & 1);
+        HIP_TRY(hw_launch_convert(P.u[g][0], s->fp64, u, true, P.nodes[g] * P.Mu, st));
+        HIP_TRY(hw_launch_convert(P.v[g], s->fp64, w, true, P.nodes[g] * P.Mv, st));
+    }
+    return HW_OK;
+}
+
+hw_status hw_get_state(const hw_solver* s, double* u, double* w, void* stream)
+{
+    return hw_batch_get_state(s, 0, u, w, stream);
+}
+
+int hw_state_grid(const hw_solver* s)
+{
+    if (!s) return -1;
+    const int64_t h = s->half_steps;
+    if (s->probs[0].p.method != HW_CONSERVATIVE) return (int)(h & 1);
+    // conservative: the first half step of each full step updates the primal grid
+    if (h == 0) return HW_DUAL;
+    return (h & 1) ? HW_PRIMAL : HW_DUAL;
+}
+
+double hw_time(const hw_solver* s)
+{
+    if (!s) return NAN;
+    const Prob& P = s->probs[0];
+    if (P.p.method == HW_CONSERVATIVE) return (double)((s->half_steps + 1) / 2) * P.p.dt;
+    return 0.5 * (double)s->half_steps * P.p.dt;
+}
+
+hw_status hw_energy(hw_solver* s, double* e_out, void* stream)
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (!e_out) return fail(HW_EINVAL, "null output");
+    if (s->probs.size() != 1) return fail(HW_EINVAL, "energy is per single-problem solver");
+    const Prob& P = s->probs[0];
+    if (P.p.method != HW_CONSERVATIVE) return fail(HW_EINVAL, "energy is defined for the conservative method");
+    if (!s->state_set || s->half_steps < 1) return fail(HW_ESTATE, "energy needs at least one half step");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t h = s->half_steps;
+    // last update: primal if h is odd, dual if h is even
+    const int B = (h & 1) ? HW_PRIMAL : HW_DUAL;
+    const int A = 1 - B;
+    const int sp = (int)(((h + 1) / 2) & 1), sd = (int)((h / 2) & 1);
+    const int slotA = (A == HW_PRIMAL) ? sp : sd;
+    const int slotB = (B == HW_PRIMAL) ? sp : sd;
+    const void* fa = P.u[A][slotA];
+    const void* fb_new = P.u[B][slotB];
+    const void* fb_old = P.u[B][1 - slotB];
+    const int m = P.p.m;
+    double hfac = 1.0;
+    for (int i = 0; i < P.p.d; ++i) hfac *= std::pow(P.h[i], 1.0 - 2.0 * (m + 1));
+    const int grid = 2048;
+    double total[2];
+    for (int t = 0; t < 2; ++t) {
+        EnergyDesc E;
+        std::memset(&E, 0, sizeof E);
+        E.d = P.p.d;
+        E.m = m;
+        const int data_grid = t == 0 ? A : B;
+        E.center_grid = 1 - data_grid;
+        for (int i = 0; i < 3; ++i) {
+            E.bc[i] = (i < P.p.d) ? P.p.bc[i] : HW_PERIODIC;
+            E.ext_from[i] = P.ext[data_grid][i];
+            E.ext_to[i] = P.ext[E.center_grid][i];
+        }
+        E.n_cells = (int)P.nodes[E.center_grid];
+        E.f = t == 0 ? fa : fb_new;
+        E.g = t == 0 ? fa : fb_old;
+        E.hfac = hfac;
+        E.hi_off = s->hi_off[m];
+        E.gram_off = s->gram_off[m];
+        const int gsz = E.n_cells < grid ? E.n_cells : grid;
+        HIP_TRY(hw_launch_energy(P.p.d, s->fp64, E, s->dops, s->partials, gsz, st));
+        std::vector<double> part(gsz);
+        HIP_TRY(hipMemcpyAsync(part.data(), s->partials, gsz * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double sum = 0.0, comp = 0.0;
+        for (int k = 0; k < gsz; ++k) {
+            const double y = part[k] - comp;
+            const double tt = sum + y;
+            comp = (tt - sum) - y;
+            sum = tt;
+        }
+        total[t] = sum;
+    }
+    *e_out = 2.0 * (total[0] - total[1]);
+    return HW_OK;
+}
+
+} // extern "C"

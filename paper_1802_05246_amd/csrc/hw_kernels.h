@@ -1,0 +1,31 @@
+// Host-side declarations of the kernel launchers of libhermite_wave.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hw_device.h"
+
+size_t hw_generic_lds_bytes(int d, int m, int variant, int elem_size);
+size_t hw_energy_lds_bytes(int d, int m);
+
+hipError_t hw_launch_generic(int d, bool fp64, const ProblemDesc* descs, const int64_t* prefix,
+                             int nprob, int64_t total, const void* ops, size_t lds, int grid,
+                             hipStream_t st);
+hipError_t hw_launch_energy(int d, bool fp64, const EnergyDesc& E, const double* dops,
+                            double* partials, int grid, hipStream_t st);
+hipError_t hw_launch_convert(const void* src, bool src64, void* dst, bool dst64, int64_t n,
+                             hipStream_t st);
+
+// LDS-tiled MFMA kernel for the 3-D dissipative full method with m = 3 (periodic or
+// not).  Returns hipErrorInvalidValue when the problem is outside its scope.
+struct TiledArgs {
+    int ext_from[3], ext_to[3], bc[3], to_grid;
+    const void* u_in;
+    const void* v_in;
+    void* u_out;
+    void* v_out;
+    double tau, lam2[3];
+};
+bool hw_tiled_supported(int d, int m, int method, int precision);
+hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st);

@@ -126,29 +126,42 @@ def poly_derivs(coeffs, x, L, h):
     return np.stack(out) * _scale(L, h)[:, None]
 
 
-def tensor_nodal(tables: Sequence[np.ndarray], M: int) -> np.ndarray:
+def tensor_nodal(tables: Sequence[np.ndarray], M: int, device=None):
     """Combine per-dimension tables D_i[l_i, j_i] (l_i < M) into the node-major array
-    prod_i D_i[l_i, j_i] with x fastest in both node and coefficient index."""
+    prod_i D_i[l_i, j_i] with x fastest in both node and coefficient index.  With a
+    torch `device` the product is formed there (returns a float64 tensor)."""
     d = len(tables)
-    T = [np.asarray(t)[:M] for t in tables]
-    if d == 1:
-        return T[0].T.copy()
-    if d == 2:
-        a = np.einsum("aj,bk->kjba", T[0], T[1])  # (j1, j0, l1, l0)
+    if device is not None:
+        import torch
+        T = [torch.as_tensor(np.asarray(t)[:M], dtype=torch.float64, device=device) for t in tables]
+        ein = torch.einsum
     else:
-        a = np.einsum("aj,bk,cl->lkjcba", T[0], T[1], T[2])
+        T = [np.asarray(t)[:M] for t in tables]
+        ein = np.einsum
+    if d == 1:
+        return T[0].T.contiguous() if device is not None else T[0].T.copy()
+    if d == 2:
+        a = ein("aj,bk->kjba", T[0], T[1])  # (j1, j0, l1, l0)
+    else:
+        a = ein("aj,bk,cl->lkjcba", T[0], T[1], T[2])
     n_nodes = int(np.prod([t.shape[1] for t in T]))
+    if device is not None:
+        return a.reshape(n_nodes, M ** d).contiguous()
     return np.ascontiguousarray(a.reshape(n_nodes, M ** d))
 
 
-def separable_nodal(spec: Spec, grid: int, M: int, factors: List[Callable]) -> np.ndarray:
+def separable_nodal(spec: Spec, grid: int, M: int, factors: List[Callable], device=None):
     """sum over terms of prod_i f_i(x_i): `factors` is a list of terms, each a
     callable (dim, x, L, h) -> table."""
     total = None
     for term in factors:
         tabs = [term(i, spec.coords(grid, i), M - 1, spec.h(i)) for i in range(spec.d)]
-        a = tensor_nodal(tabs, M)
-        total = a if total is None else total + a
+        a = tensor_nodal(tabs, M, device)
+        if total is None:
+            total = a
+        else:
+            total += a
+            del a
     return total
 
 
@@ -167,7 +180,7 @@ def plane_wave_nodal(spec: Spec, grid: int, M: int, kvec, phase, amp=1.0) -> np.
     return out
 
 
-def pulses_nodal(spec: Spec, grid: int, M: int, centres, amps, sigma) -> np.ndarray:
+def pulses_nodal(spec: Spec, grid: int, M: int, centres, amps, sigma, device=None):
     """Sum of Gaussian pulses A exp(-|x-x_p|^2/(2 sigma^2)) (minimum image per
     dimension on periodic domains)."""
     terms = []
@@ -177,7 +190,7 @@ def pulses_nodal(spec: Spec, grid: int, M: int, centres, amps, sigma) -> np.ndar
             t = gaussian_derivs(x, x0[i], sigma, L, h, per)
             return t * A if i == 0 else t
         terms.append(term)
-    return separable_nodal(spec, grid, M, terms)
+    return separable_nodal(spec, grid, M, terms, device)
 
 
 # ----------------------------------------------------------------------------
@@ -294,13 +307,18 @@ def c3_2d(n=2048, m=4, cfl=1.0, steps=2000, seed=1805) -> Workload:
                     meta={"k1": k1, "k2": k2, "level": level})
 
 
-def c4_3d(n=256, m=3, cfl=0.9, steps=200, seed=1806, sigma=0.05) -> Workload:
-    """3-D dissipative, periodic unit cube, 8 Gaussian pulses (sigma 0.05), v0 = 0."""
+def c4_3d(n=256, m=3, cfl=0.9, steps=200, seed=1806, sigma=0.05, device=None) -> Workload:
+    """3-D dissipative, periodic unit cube, 8 Gaussian pulses (sigma 0.05), v0 = 0.
+    With a torch `device` the nodal arrays are built there."""
     rng = np.random.default_rng(seed)
     centres, amps = _pulse_draw(rng, 8, 3)
     spec = make_spec(3, m, n, 0.0, 1.0, 1.0, cfl=cfl, bc=PERIODIC, method=DISS_FULL)
-    u0 = pulses_nodal(spec, PRIMAL, m + 1, centres, amps, sigma)
-    v0 = np.zeros((spec.nodes(PRIMAL), m ** 3))
+    u0 = pulses_nodal(spec, PRIMAL, m + 1, centres, amps, sigma, device)
+    if device is not None:
+        import torch
+        v0 = torch.zeros((spec.nodes(PRIMAL), m ** 3), dtype=torch.float64, device=device)
+    else:
+        v0 = np.zeros((spec.nodes(PRIMAL), m ** 3))
 
     def exact(t, grid=PRIMAL, points=None, xp=np):
         pts = spec.points(grid) if points is None else points

@@ -1,0 +1,137 @@
+"""Shared test helpers: oracle problems from specs, relative L2, and single-cell
+oracle evaluation for sampled parity on large grids."""
+import numpy as np
+
+import oracle
+from paper_1802_05246_amd import workloads as W
+
+
+def oracle_problem(spec, **over):
+    d = dict(d=spec.d, m=spec.m, n=spec.n, xl=spec.xl, xr=spec.xr, c=spec.c, dt=spec.dt,
+             bc=spec.bc, method=spec.method, taylor_stages=spec.taylor_stages)
+    d.update(over)
+    return oracle.make_problem(**d)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def oracle_reference_run(spec, u, w, n_half):
+    """n_half half steps of the oracle from the set_state data (u, w)."""
+    p = oracle_problem(spec)
+    if spec.method == W.CONSERVATIVE:
+        up, ud = np.asarray(u), np.asarray(w)
+        for k in range(n_half):
+            if k % 2 == 0:
+                up = oracle.cons_half(p, oracle.PRIMAL, ud, up)
+            else:
+                ud = oracle.cons_half(p, oracle.DUAL, up, ud)
+        return up, ud
+    grid = W.PRIMAL
+    for _ in range(n_half):
+        grid = 1 - grid
+        u, w = oracle.diss_half(p, grid, u, w)
+    return u, w
+
+
+def corner_nodes(spec, to_grid, out_idx):
+    """Input-grid node indices (per dimension, two per dimension) of one output node,
+    and the matching indices inside a small oracle box reproducing that cell."""
+    per_dim = []
+    for i in range(spec.d):
+        oi = out_idx[i]
+        ext = spec.extent(1 - to_grid, i)
+        if to_grid == W.DUAL:
+            js = [oi, oi + 1]
+            if spec.bc[i] == W.PERIODIC:
+                js = [j % ext for j in js]
+        else:
+            js = [oi - 1, oi]
+            if spec.bc[i] == W.PERIODIC:
+                js = [j % ext for j in js]
+        per_dim.append(js)
+    return per_dim
+
+
+def sampled_oracle(spec, to_grid, u_in, v_in, samples, u_old=None):
+    """Oracle output at the sampled output nodes (list of flat indices), each computed
+    on a 2-cell box whose input nodes are copies of the cell's corners.  u_in/v_in are
+    callables mapping an array of flat input-node indices to (k, ncoef) numpy arrays.
+    Walls: a sampled node on a non-periodic wall keeps that wall in its box."""
+    d = spec.d
+    out_u, out_v = [], []
+    ext_to = [spec.extent(to_grid, i) for i in range(d)]
+    ext_from = [spec.extent(1 - to_grid, i) for i in range(d)]
+    for s in samples:
+        idx, r = [], s
+        for i in range(d):
+            idx.append(r % ext_to[i])
+            r //= ext_to[i]
+        # box: per dimension choose the box geometry and the box-local output index
+        bn, bbc, local, src = [], [], [], []
+        for i in range(d):
+            oi = idx[i]
+            if to_grid == W.DUAL:
+                # box of 1 cell, walls irrelevant (no ghosts in this direction)
+                bn.append(1)
+                bbc.append(W.DIRICHLET)
+                local.append(0)
+                js = [oi, oi + 1]
+                if spec.bc[i] == W.PERIODIC:
+                    js = [j % ext_from[i] for j in js]
+                src.append(js)
+            else:
+                # box of 2 cells: dual nodes 0, 1 -> primal nodes 0, 1, 2
+                bn.append(2)
+                if spec.bc[i] != W.PERIODIC and oi == 0:
+                    bbc.append(spec.bc[i]); local.append(0); src.append([0, 0])
+                elif spec.bc[i] != W.PERIODIC and oi == ext_to[i] - 1:
+                    bbc.append(spec.bc[i]); local.append(2); src.append([ext_from[i] - 1, ext_from[i] - 1])
+                else:
+                    bbc.append(W.DIRICHLET); local.append(1)
+                    js = [oi - 1, oi]
+                    if spec.bc[i] == W.PERIODIC:
+                        js = [j % ext_from[i] for j in js]
+                    src.append(js)
+        h = [spec.h(i) for i in range(d)]
+        bp = oracle_problem(spec, n=bn, xl=[0.0] * d, xr=[bn[i] * h[i] for i in range(d)], bc=bbc)
+        box = W.Spec(d, spec.m, bn, [0.0] * d, [bn[i] * h[i] for i in range(d)], spec.c, spec.dt,
+                     bbc, spec.method, spec.taylor_stages)
+        nb_from = [box.extent(1 - to_grid, i) for i in range(d)]
+        # box input node list -> global input node
+        nbox = int(np.prod(nb_from))
+        gidx = np.zeros(nbox, dtype=np.int64)
+        for b in range(nbox):
+            r, g, st = b, 0, 1
+            for i in range(d):
+                bi = r % nb_from[i]
+                r //= nb_from[i]
+                if to_grid == W.DUAL:
+                    gi = src[i][bi]
+                else:
+                    gi = src[i][min(bi, 1)] if nb_from[i] == 2 else src[i][0]
+                g += gi * st
+                st *= ext_from[i]
+            gidx[b] = g
+        ub = u_in(gidx)
+        lsel = 0
+        st = 1
+        nb_to = [box.extent(to_grid, i) for i in range(d)]
+        for i in range(d):
+            lsel += local[i] * st
+            st *= nb_to[i]
+        if spec.method == W.CONSERVATIVE:
+            old = np.zeros((box.nodes(to_grid), (spec.m + 1) ** d))
+            old[lsel] = u_old(np.array([s]))[0]
+            res = oracle.cons_half(bp, to_grid, ub, old, sel=[lsel])
+            out_u.append(res[0])
+        else:
+            vb = v_in(gidx)
+            ru, rv = oracle.diss_half(bp, to_grid, ub, vb, sel=[lsel])
+            out_u.append(ru[0])
+            out_v.append(rv[0])
+    return np.array(out_u), (np.array(out_v) if out_v else None)

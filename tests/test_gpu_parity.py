@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 form rel-L2 <= 1e-10 over every coefficient of every node (the
+expected level is 1e-13..1e-11; cond(H_6) ~ 1.4e5 sets the ceiling);  FP32 form
+rel-L2 <= 2e-5 for a few steps (single-precision round-off times the operator
+condition numbers, cond(H_3) ~ 273).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1802_05246_amd import workloads as W
+
+from helpers import oracle_reference_run, rel_l2, sampled_oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _B():
+    from paper_1802_05246_amd import binding as B
+    return B
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _B().lib()  # fail loudly if the HIP library is missing
+    yield
+
+
+def _state(spec, seed):
+    rng = np.random.default_rng(seed)
+    M = spec.m + 1
+    u = rng.uniform(-1, 1, (spec.nodes(W.PRIMAL), M ** spec.d))
+    if spec.method == W.CONSERVATIVE:
+        w = rng.uniform(-1, 1, (spec.nodes(W.DUAL), M ** spec.d))
+    else:
+        w = rng.uniform(-1, 1, (spec.nodes(W.PRIMAL), spec.m ** spec.d))
+    return u, w
+
+
+CASES = [
+    # (d, m, n, bc, method, taylor_stages)
+    (1, 1, [9], [W.PERIODIC], W.DISS_FULL, 0),
+    (1, 3, [11], [W.DIRICHLET], W.DISS_FULL, 0),
+    (1, 6, [7], [W.NEUMANN], W.DISS_FULL, 0),
+    (2, 2, [7, 5], [W.PERIODIC, W.DIRICHLET], W.DISS_FULL, 0),
+    (2, 3, [9, 6], [W.PERIODIC, W.PERIODIC], W.DISS_FULL, 0),
+    (2, 3, [5, 7], [W.NEUMANN, W.DIRICHLET], W.DISS_SIMPLE, 0),
+    (2, 5, [4, 5], [W.DIRICHLET, W.PERIODIC], W.DISS_FULL, 0),
+    (2, 2, [6, 6], [W.PERIODIC, W.PERIODIC], W.DISS_FULL, 6),
+    (3, 1, [5, 4, 3], [W.PERIODIC, W.DIRICHLET, W.NEUMANN], W.DISS_FULL, 0),
+    (3, 3, [5, 4, 6], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 0),
+    (3, 3, [4, 3, 5], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], W.DISS_FULL, 0),
+    (3, 2, [4, 4, 3], [W.PERIODIC, W.PERIODIC, W.DIRICHLET], W.DISS_SIMPLE, 0),
+    (1, 0, [8], [W.PERIODIC], W.CONSERVATIVE, 0),
+    (1, 4, [9], [W.DIRICHLET], W.CONSERVATIVE, 0),
+    (2, 4, [7, 6], [W.DIRICHLET, W.DIRICHLET], W.CONSERVATIVE, 0),
+    (2, 2, [5, 8], [W.NEUMANN, W.PERIODIC], W.CONSERVATIVE, 0),
+    (3, 2, [4, 5, 3], [W.PERIODIC, W.NEUMANN, W.DIRICHLET], W.CONSERVATIVE, 0),
+]
+
+
+def _case_id(c):
+    d, m, n, bc, meth, st = c
+    return f"d{d}-m{m}-n{'x'.join(map(str, n))}-bc{''.join(map(str, bc))}-meth{meth}-st{st}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_case_id(c) for c in CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_grids_match_oracle(case, prec):
+    B = _B()
+    d, m, n, bc, meth, stages = case
+    _log(f"[parity] {_case_id(case)} {prec}")
+    spec = W.make_spec(d, m, n, 0.0, [1.0, 0.9, 0.8][:d], 1.1, cfl=0.9, bc=bc, method=meth,
+                       taylor_stages=stages)
+    u, w = _state(spec, 17 + d + m)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_GENERIC)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    n_half = 6
+    s.half_steps(n_half)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
+    err = max(rel_l2(gu, ou), rel_l2(gw, ow))
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
+    assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_advance_equals_plain_launches_bitwise(prec):
+    B = _B()
+    spec = W.make_spec(2, 3, [12, 10], 0.0, 1.0, 1.0, cfl=0.9, bc=[W.PERIODIC, W.DIRICHLET])
+    u, w = _state(spec, 5)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    a = B.Solver(spec, precision=precision)
+    b = B.Solver(spec, precision=precision)
+    a.set_state(u, w)
+    b.set_state(u, w)
+    a.advance(3)
+    a.advance(2)
+    b.half_steps(10)
+    ua, wa = a.get_state()
+    ub, wb = b.get_state()
+    assert torch.equal(ua, ub) and torch.equal(wa, wb)
+    # resume: get_state -> set_state on a fresh solver continues bitwise
+    c = B.Solver(spec, precision=B.HW_FP64)
+    d_ = B.Solver(spec, precision=B.HW_FP64)
+    c.set_state(u, w)
+    c.advance(4)
+    d_.set_state(u, w)
+    d_.advance(2)
+    mid_u, mid_w = d_.get_state()
+    e = B.Solver(spec, precision=B.HW_FP64)
+    e.set_state(mid_u, mid_w)
+    e.advance(2)
+    assert torch.equal(c.get_state()[0], e.get_state()[0])
+    for x in (a, b, c, d_, e):
+        x.close()
+
+
+@pytest.mark.parametrize("d,m,bc", [(2, 2, W.PERIODIC), (2, 3, W.DIRICHLET), (1, 4, W.NEUMANN),
+                                    (3, 1, W.PERIODIC)])
+def test_energy_matches_oracle_and_is_conserved(d, m, bc):
+    import oracle
+    from helpers import oracle_problem
+    B = _B()
+    spec = W.make_spec(d, m, [6, 5, 4][:d], 0.0, [1.0, 0.7, 0.6][:d], 1.0, cfl=1.0, bc=bc,
+                       method=W.CONSERVATIVE)
+    rng = np.random.default_rng(3)
+    M = m + 1
+    up = rng.uniform(0, 1, (spec.nodes(W.PRIMAL), M ** d))
+    if bc != W.PERIODIC:
+        from test_oracle_pins import _wall_compatible
+        up = _wall_compatible(spec, up)
+    s = B.Solver(spec, precision=B.HW_FP64)
+    s.cons_startup(up)
+    energies = []
+    for k in range(8):
+        s.half_steps(1)
+        energies.append(s.energy())
+    gp, gd = (x.cpu().numpy() for x in s.get_state())
+    # oracle energy on the GPU's own last three levels
+    p = oracle_problem(spec)
+    s2 = B.Solver(spec, precision=B.HW_FP64)
+    s2.cons_startup(up)
+    s2.half_steps(7)
+    gp7, gd7 = (x.cpu().numpy() for x in s2.get_state())
+    # after 8 half steps the dual grid was updated last: A = primal, B = dual
+    e_or = oracle.cons_energy(p, oracle.PRIMAL, gp, gd, gd7)
+    assert energies[-1] == pytest.approx(e_or, rel=1e-12)
+    e = np.array(energies)
+    assert np.abs(e - e[0]).max() <= 1e-11 * abs(e[0])
+    s.close()
+    s2.close()
+
+
+def test_cons_startup_matches_oracle():
+    import oracle
+    from helpers import oracle_problem
+    B = _B()
+    for d, m, bc in [(2, 3, W.DIRICHLET), (3, 2, W.PERIODIC), (1, 5, W.NEUMANN)]:
+        spec = W.make_spec(d, m, [6, 5, 4][:d], 0.0, 1.0, 1.3, cfl=0.8, bc=bc, method=W.CONSERVATIVE)
+        rng = np.random.default_rng(d * m)
+        u0 = rng.uniform(-1, 1, (spec.nodes(W.PRIMAL), (m + 1) ** d))
+        v0 = rng.uniform(-1, 1, (spec.nodes(W.PRIMAL), (m + 1) ** d))
+        for vv in (None, v0):
+            s = B.Solver(spec, precision=B.HW_FP64)
+            s.cons_startup(u0, vv)
+            _, gd = s.get_state()
+            od = oracle.cons_startup(oracle_problem(spec), u0, vv)
+            assert rel_l2(gd.cpu().numpy(), od) < 1e-12
+            s.close()
+
+
+def test_batch_matches_oracle_per_problem():
+    B = _B()
+    specs, states = [], []
+    mix = [(2, [9, 7], W.PERIODIC, W.DISS_FULL), (3, [6, 5], W.DIRICHLET, W.DISS_FULL),
+           (4, [5, 5], W.NEUMANN, W.CONSERVATIVE), (2, [11, 4], W.DIRICHLET, W.CONSERVATIVE),
+           (5, [4, 6], W.PERIODIC, W.DISS_FULL), (6, [3, 4], W.PERIODIC, W.CONSERVATIVE)]
+    for k, (m, n, bc, meth) in enumerate(mix):
+        spec = W.make_spec(2, m, n, 0.0, 1.0, 0.5 + 0.3 * k, cfl=0.8, bc=bc, method=meth)
+        specs.append(spec)
+        states.append(_state(spec, 100 + k))
+    for prec, tol in ((B.HW_FP64, 1e-10), (B.HW_FP32, 5e-5)):
+        s = B.Solver(problems=specs, precision=prec)
+        ins = []
+        for i, (u, w) in enumerate(states):
+            s.set_state(u, w, i=i)
+        for i in range(len(specs)):
+            ins.append([x.cpu().numpy() for x in s.get_state(i)])
+        s.advance(3)
+        for i, spec in enumerate(specs):
+            gu, gw = (x.cpu().numpy() for x in s.get_state(i))
+            ou, ow = oracle_reference_run(spec, ins[i][0], ins[i][1], 6)
+            err = max(rel_l2(gu, ou), rel_l2(gw, ow))
+            _log(f"[batch] problem {i} prec {prec} rel-L2 {err:.3e}")
+            assert err <= tol
+        s.close()
+
+
+def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1, tol=1e-10):
+    """Run `steps_half` half steps (the last one checked) at full size and compare
+    sampled output nodes with the oracle evaluated cell by cell."""
+    B = _B()
+    s = B.Solver(spec, precision=precision)
+    u0, w0 = w_state
+    s.set_state(u0, w0)
+    del u0, w0
+    if steps_half > 1:
+        s.half_steps(steps_half - 1)
+    xin_u, xin_w = s.get_state()
+    to_grid = 1 - s.state_grid() if spec.method != W.CONSERVATIVE else (
+        W.PRIMAL if (steps_half - 1) % 2 == 0 else W.DUAL)
+    s.half_steps(1)
+    yu, yw = s.get_state()
+    rng = np.random.default_rng(seed)
+    n_out = spec.nodes(to_grid)
+    samples = list(rng.choice(n_out, size=n_samples, replace=False))
+    # always include the first and last output node (wall / wrap-around cells)
+    samples = [0, n_out - 1] + samples
+
+    if spec.method == W.CONSERVATIVE:
+        # xin: (primal, dual); the grid read is the other grid at the middle time
+        src_u = xin_w if to_grid == W.PRIMAL else xin_u
+        old = xin_u if to_grid == W.PRIMAL else xin_w
+        new = yu if to_grid == W.PRIMAL else yw
+
+        def u_in(ix):
+            return src_u[torch.as_tensor(ix, device="cuda")].cpu().numpy()
+
+        def u_old(ix):
+            return old[torch.as_tensor(ix, device="cuda")].cpu().numpy()
+        ou, _ = sampled_oracle(spec, to_grid, u_in, None, samples, u_old=u_old)
+        gu = new[torch.as_tensor(samples, device="cuda")].cpu().numpy()
+        err = rel_l2(gu, ou)
+    else:
+        def u_in(ix):
+            return xin_u[torch.as_tensor(ix, device="cuda")].cpu().numpy()
+
+        def v_in(ix):
+            return xin_w[torch.as_tensor(ix, device="cuda")].cpu().numpy()
+        ou, ov = sampled_oracle(spec, to_grid, u_in, v_in, samples)
+        sel = torch.as_tensor(samples, device="cuda")
+        gu, gv = yu[sel].cpu().numpy(), yw[sel].cpu().numpy()
+        err = max(rel_l2(gu, ou), rel_l2(gv, ov))
+    s.close()
+    _log(f"    sampled rel-L2 = {err:.3e} (tol {tol:g})")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_3d_m3_sampled(prec):
+    """256^3, m = 3, periodic, dissipative full: both half-step directions, sampled."""
+    B = _B()
+    _log(f"[full-size] c4 256^3 {prec}")
+    w = W.c4_3d(device="cuda")
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    for steps_half in (1, 2):
+        _sampled_check(w.spec, precision, 48, 7 + steps_half, (w.u0, w.v0), steps_half, tol)
+    del w
+    torch.cuda.empty_cache()
+
+
+def test_full_size_2d_cons_m4_sampled():
+    """2048^2, m = 4, Dirichlet, conservative: both grids, wall nodes included."""
+    B = _B()
+    _log("[full-size] c3 2048^2")
+    w = W.c3_2d()
+    for prec, tol in ((B.HW_FP64, 1e-10), (B.HW_FP32, 5e-5)):
+        for steps_half in (1, 2):
+            _sampled_check(w.spec, prec, 48, 11, (w.u0, w.u_half), steps_half, tol)
+
+
+def test_full_size_2d_diss_m3_sampled():
+    B = _B()
+    _log("[full-size] c2 512^2")
+    w = W.c2_2d()
+    for steps_half in (1, 2):
+        _sampled_check(w.spec, B.HW_FP64, 64, 13, (w.u0, w.v0), steps_half, 1e-10)
