@@ -1,0 +1,230 @@
+"""Benchmark: cell-updates/s of the 3-D dissipative Hermite method, m = 3, on the
+256^3 periodic unit cube with 8 Gaussian pulses (lambda = c dt/h = 0.9), FP32 form
+against the FP64 form, with the L2 error reached.
+
+One step = one full time step = two half steps over all 256^3 cells (two
+cell-updates per node).  The timed region is `hw_advance(K)`: a hipGraph of 2K
+half-step kernel launches on the current stream, inputs resident in HBM.
+
+Prints ONE JSON line (rank 0, N = 1).  Only one GPU is used; --gpus N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s, 3-D m=3, at stated L2 error; FP32-MFMA vs FP64 form"
+HBM_PEAK_GBS = 8000.0
+PEAKS_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+# algorithmic work of one cell-update of the 3-D dissipative full method, m = 3:
+# flops of the interpolants (centre rows of p0, q0, the three mixed interpolants),
+# the modified first-step Laplacian and the closed-form time sums, counted per cell
+# without sharing between neighbouring cells; bytes = read one node + write one node
+FLOPS_PER_CELL = 48272
+BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed steps of the FP64 form (default: same as --steps)")
+    ap.add_argument("--kernel", choices=["auto", "generic", "tiled"], default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--cpu-layers", type=int, default=8,
+                    help="z-layers of the grid in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def timed_advance(torch, B, solver_h, steps, warmup):
+    """warmup steps, then exactly `steps` steps bracketed by synchronisation and HIP
+    events on the launch stream; returns (elapsed s, event ms)."""
+    stream = torch.cuda.current_stream()
+    if warmup:
+        B.hw_advance(solver_h, warmup, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    B.hw_advance(solver_h, steps, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, e0.elapsed_time(e1)
+
+
+def run_form(torch, B, W, w, precision, kernel, steps, warmup):
+    """Untimed pass of `steps` steps (captures and caches the step graph), reset to
+    the initial data, `warmup` untimed steps, then the timed `steps` steps."""
+    spec = w.spec
+    s = B.Solver(spec, precision=precision, kernel=kernel)
+    s.set_state(w.u0, w.v0)
+    B.hw_advance(s.h, steps)
+    torch.cuda.synchronize()
+    s.set_state(w.u0, w.v0)
+    elapsed, ev_ms = timed_advance(torch, B, s.h, steps, warmup)
+    return s, elapsed, ev_ms
+
+
+def l2_errors(torch, W, w, s, t_final):
+    """nodal L2 error of the value coefficient against the exact radial solution"""
+    u, _ = s.get_state()
+    val = u[:, 0]
+    spec = w.spec
+    pts = torch.as_tensor(spec.points(W.PRIMAL), device="cuda")
+    ex = torch.empty_like(val)
+    chunk = 1 << 21
+    for a in range(0, pts.shape[0], chunk):
+        ex[a:a + chunk] = w.exact(t_final, points=pts[a:a + chunk], xp=torch)
+    h3 = spec.h(0) * spec.h(1) * spec.h(2)
+    diff = val - ex
+    err = math.sqrt(h3 * float((diff * diff).sum()))
+    ref = math.sqrt(h3 * float((ex * ex).sum()))
+    return err, err / ref, val
+
+
+def cpu_baseline(W, layers, n):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload: the
+    first `layers` z-layers of cells of the n^3 grid, one primal -> dual half step."""
+    import oracle
+    w = W.c4_3d(n=4)  # for the pulse parameters only
+    centres, amps, sigma = w.meta["centres"], w.meta["amps"], w.meta["sigma"]
+    h = 1.0 / n
+    dt = 0.9 * h
+    # slab: x, y periodic; z = [0, layers*h]; its primal nodes are the real grid's
+    # first layers+1 node layers, the data uses minimum images in every dimension
+    box = W.make_spec(3, 3, [n, n, layers], [0.0, 0.0, 0.0], [1.0, 1.0, layers * h], 1.0,
+                      dt=dt, bc=[W.PERIODIC, W.PERIODIC, W.DIRICHLET])
+    terms = []
+    for x0, A in zip(centres, amps):
+        def term(i, x, L, hh, x0=x0, A=A):
+            t = W.gaussian_derivs(x, x0[i], sigma, L, hh, period=1.0)
+            return t * A if i == 0 else t
+        terms.append(term)
+    u = W.separable_nodal(box, W.PRIMAL, 4, terms)
+    v = np.zeros((box.nodes(W.PRIMAL), 27))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p = oracle.make_problem(3, 3, box.n, box.xl, box.xr, 1.0, dt, box.bc, W.DISS_FULL)
+    t0 = time.perf_counter()
+    uo, _ = oracle.diss_half(p, oracle.DUAL, u, v, nthreads=threads)
+    el = time.perf_counter() - t0
+    cells = uo.shape[0]
+    try:
+        model = subprocess.run(["sh", "-c", "grep -m1 'model name' /proc/cpuinfo | cut -d: -f2"],
+                               capture_output=True, text=True).stdout.strip()
+    except Exception:
+        model = ""
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{cells} cells ({layers} z-layers of the {n}^3 grid), one primal->dual "
+                      f"half step, FP64, {el:.1f} s, CPU: {model}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the Hermite half step shards by slabs with a "
+              "one-node halo exchange, which this build does not implement; use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1802_05246_amd import binding as B
+    from paper_1802_05246_amd import workloads as W
+
+    B.lib()
+    kernel = {"auto": B.HW_KERNEL_AUTO, "generic": B.HW_KERNEL_GENERIC,
+              "tiled": B.HW_KERNEL_TILED}[args.kernel]
+    n = args.n
+    log(f"[bench] building {n}^3 m=3 pulse data on the GPU")
+    w = W.c4_3d(n=n, device="cuda")
+    spec = w.spec
+    cells_per_step = 2 * spec.nodes(W.PRIMAL)  # two half steps, periodic: n^3 nodes each
+    K, Wm = args.steps, args.warmup
+
+    # FP32 form (the metric's value)
+    log(f"[bench] fp32 form: warmup {Wm}, timed {K} steps")
+    s32, el32, ev32 = run_form(torch, B, W, w, B.HW_FP32, kernel, K, Wm)
+    rate32 = cells_per_step * K / el32
+    t_final = (K + Wm) * spec.dt
+    err32 = rel32 = None
+    if not args.no_error:
+        err32, rel32, val32 = l2_errors(torch, W, w, s32, t_final)
+    s32.close()
+
+    # FP64 form
+    K64 = args.fp64_steps or K
+    log(f"[bench] fp64 form: warmup {Wm}, timed {K64} steps")
+    s64, el64, ev64 = run_form(torch, B, W, w, B.HW_FP64, kernel, K64, Wm)
+    rate64 = cells_per_step * K64 / el64
+    err64 = rel64 = diff_32_64 = None
+    if not args.no_error:
+        if K64 == K:
+            err64, rel64, val64 = l2_errors(torch, W, w, s64, t_final)
+            diff_32_64 = float(torch.linalg.norm(val32 - val64) / torch.linalg.norm(val64))
+        else:
+            err64, rel64, _ = l2_errors(torch, W, w, s64, (K64 + Wm) * spec.dt)
+    s64.close()
+    del w
+    torch.cuda.empty_cache()
+
+    # roofline of the dominant kernel (the half-step kernel of the FP32 form)
+    launches = 2 * K
+    avg_ms = ev32 / launches
+    cells_per_launch = spec.nodes(W.PRIMAL)
+    tiled = args.kernel != "generic"
+    flops_launch = FLOPS_PER_CELL * cells_per_launch
+    bytes_launch = BYTES_PER_CELL["fp32"] * cells_per_launch
+    ach_tflops = flops_launch / (avg_ms * 1e-3) / 1e12
+    ach_gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "mfma" if tiled else "alu", "achieved": round(ach_tflops, 2),
+            "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
+            "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": None,
+            "kernel_avg_ms": round(avg_ms, 4), "hbm_algorithmic_gbs": round(ach_gbs, 1),
+            "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_layers} z-layers")
+        cpu = cpu_baseline(W, args.cpu_layers, n)
+
+    out = {
+        "metric": METRIC, "value": rate32, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": el32 / K * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3-D dissipative Hermite (modified first step), m=3, periodic "
+                               f"unit cube {n}^3, c dt/h = 0.9, 8 Gaussian pulses sigma 0.05, v0 = 0",
+                   "n": n, "m": 3, "cfl": 0.9, "cells_per_step": cells_per_step,
+                   "kernel": args.kernel},
+        "l2_error": {"fp32_abs": err32, "fp32_rel": rel32, "fp64_abs": err64, "fp64_rel": rel64,
+                     "fp32_vs_fp64_rel": diff_32_64, "t_final": t_final,
+                     "against": "exact radial solution, value coefficient at the primal nodes"},
+        "fp64_form": {"value": rate64, "unit": "cell-updates/s", "steps": K64,
+                      "ms_per_step": el64 / K64 * 1e3, "speedup_fp32_over_fp64": rate32 / rate64,
+                      "kernel_avg_ms": ev64 / (2 * K64)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -555,7 +555,10 @@ hw_status hw_batch_advance(hw_solver* s, int n, void* stream)
     if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
     if (n == 0) return HW_OK;
     const int q = (int)((s->half_steps >> 1) & 1);
-    auto key = std::make_pair(n, q);
+    // the conservative slot parity selects buffers; dissipative steps do not depend on it
+    bool any_cons = false;
+    for (const Prob& P : s->probs) any_cons |= (P.p.method == HW_CONSERVATIVE);
+    auto key = std::make_pair(n, any_cons ? q : 0);
     auto it = s->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it == s->graphs.end()) {

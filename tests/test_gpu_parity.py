@@ -1,9 +1,15 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances: FP64 form rel-L2 <= 1e-10 over every coefficient of every node (the
-expected level is 1e-13..1e-11; cond(H_6) ~ 1.4e5 sets the ceiling);  FP32 form
-rel-L2 <= 2e-5 for a few steps (single-precision round-off times the operator
-condition numbers, cond(H_3) ~ 273).
+Tolerances.  FP64 form: rel-L2 <= 1e-10 for u and for v separately, over every
+coefficient of every node (expected 1e-13..1e-11; cond(H_6) ~ 1.4e5 sets the
+ceiling).  FP32 form: the relative L2 error of the joint vector [u, tau*v]
+(tau = dt/2, so both parts carry the units of u) is at most
+max(2e-5, 2 u32 cond(H_m) n_half), u32 = 2^-24: each half step perturbs the nodal
+data by single-precision rounding, which interpolation amplifies by at most
+cond(H_m), and the perturbations add up over the n_half checked half steps.  A
+per-field bound would not do for v right after v0 = 0: there v is small and made of
+second differences of very smooth data, so its own relative rounding error is large
+although it is tiny next to u.
 """
 import sys
 
@@ -17,6 +23,23 @@ from helpers import oracle_reference_run, rel_l2, sampled_oracle
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+COND_H = [2.0, 7.17, 38.8, 273.3, 2082.6, 16786.7, 140353.5]
+
+
+def fp32_tol(m, n_half):
+    return max(2e-5, 2.0 * 2.0 ** -24 * COND_H[m] * max(1, n_half))
+
+
+def joint_err(spec, gu, gv, ou, ov):
+    """relative L2 of [u, tau v] (u only for the conservative method)"""
+    if spec.method == W.CONSERVATIVE or gv is None:
+        return rel_l2(gu, ou)
+    tau = 0.5 * spec.dt
+    a = np.concatenate([np.ravel(gu), tau * np.ravel(gv)])
+    b = np.concatenate([np.ravel(ou), tau * np.ravel(ov)])
+    return rel_l2(a, b)
 
 
 def _B():
@@ -92,8 +115,10 @@ def test_small_grids_match_oracle(case, prec):
     s.half_steps(n_half)
     gu, gw = (x.cpu().numpy() for x in s.get_state())
     ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
-    err = max(rel_l2(gu, ou), rel_l2(gw, ow))
-    tol = 1e-10 if prec == "fp64" else 2e-5
+    if prec == "fp64":
+        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+    else:
+        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(m, n_half)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
     s.close()
@@ -195,7 +220,7 @@ def test_batch_matches_oracle_per_problem():
         spec = W.make_spec(2, m, n, 0.0, 1.0, 0.5 + 0.3 * k, cfl=0.8, bc=bc, method=meth)
         specs.append(spec)
         states.append(_state(spec, 100 + k))
-    for prec, tol in ((B.HW_FP64, 1e-10), (B.HW_FP32, 5e-5)):
+    for prec in (B.HW_FP64, B.HW_FP32):
         s = B.Solver(problems=specs, precision=prec)
         ins = []
         for i, (u, w) in enumerate(states):
@@ -206,13 +231,16 @@ def test_batch_matches_oracle_per_problem():
         for i, spec in enumerate(specs):
             gu, gw = (x.cpu().numpy() for x in s.get_state(i))
             ou, ow = oracle_reference_run(spec, ins[i][0], ins[i][1], 6)
-            err = max(rel_l2(gu, ou), rel_l2(gw, ow))
+            if prec == B.HW_FP64:
+                err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+            else:
+                err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(spec.m, 6)
             _log(f"[batch] problem {i} prec {prec} rel-L2 {err:.3e}")
             assert err <= tol
         s.close()
 
 
-def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1, tol=1e-10):
+def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1):
     """Run `steps_half` half steps (the last one checked) at full size and compare
     sampled output nodes with the oracle evaluated cell by cell."""
     B = _B()
@@ -246,7 +274,7 @@ def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1,
             return old[torch.as_tensor(ix, device="cuda")].cpu().numpy()
         ou, _ = sampled_oracle(spec, to_grid, u_in, None, samples, u_old=u_old)
         gu = new[torch.as_tensor(samples, device="cuda")].cpu().numpy()
-        err = rel_l2(gu, ou)
+        gv = ov = None
     else:
         def u_in(ix):
             return xin_u[torch.as_tensor(ix, device="cuda")].cpu().numpy()
@@ -256,8 +284,13 @@ def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1,
         ou, ov = sampled_oracle(spec, to_grid, u_in, v_in, samples)
         sel = torch.as_tensor(samples, device="cuda")
         gu, gv = yu[sel].cpu().numpy(), yw[sel].cpu().numpy()
-        err = max(rel_l2(gu, ou), rel_l2(gv, ov))
     s.close()
+    B = _B()
+    if precision == B.HW_FP64:
+        err = max(rel_l2(gu, ou), rel_l2(gv, ov) if gv is not None else 0.0)
+        tol = 1e-10
+    else:
+        err, tol = joint_err(spec, gu, gv, ou, ov), fp32_tol(spec.m, 1)
     _log(f"    sampled rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
 
@@ -269,9 +302,8 @@ def test_full_size_3d_m3_sampled(prec):
     _log(f"[full-size] c4 256^3 {prec}")
     w = W.c4_3d(device="cuda")
     precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
-    tol = 1e-10 if prec == "fp64" else 2e-5
     for steps_half in (1, 2):
-        _sampled_check(w.spec, precision, 48, 7 + steps_half, (w.u0, w.v0), steps_half, tol)
+        _sampled_check(w.spec, precision, 48, 7 + steps_half, (w.u0, w.v0), steps_half)
     del w
     torch.cuda.empty_cache()
 
@@ -281,9 +313,9 @@ def test_full_size_2d_cons_m4_sampled():
     B = _B()
     _log("[full-size] c3 2048^2")
     w = W.c3_2d()
-    for prec, tol in ((B.HW_FP64, 1e-10), (B.HW_FP32, 5e-5)):
+    for prec in (B.HW_FP64, B.HW_FP32):
         for steps_half in (1, 2):
-            _sampled_check(w.spec, prec, 48, 11, (w.u0, w.u_half), steps_half, tol)
+            _sampled_check(w.spec, prec, 48, 11, (w.u0, w.u_half), steps_half)
 
 
 def test_full_size_2d_diss_m3_sampled():
@@ -291,4 +323,4 @@ def test_full_size_2d_diss_m3_sampled():
     _log("[full-size] c2 512^2")
     w = W.c2_2d()
     for steps_half in (1, 2):
-        _sampled_check(w.spec, B.HW_FP64, 64, 13, (w.u0, w.v0), steps_half, 1e-10)
+        _sampled_check(w.spec, B.HW_FP64, 64, 13, (w.u0, w.v0), steps_half)
