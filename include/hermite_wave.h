@@ -120,6 +120,11 @@ hw_status hw_cons_startup(hw_solver* s, const double* u0, const double* v0_or_nu
  * Dissipative: requires the state on the primal grid. */
 hw_status hw_advance(hw_solver* s, int n_full_steps, void* stream);
 
+/* Capture and instantiate the hipGraph that hw_advance(s, n) replays from the
+ * current step parity, without launching it, so that a later hw_advance(s, n) does
+ * no capture work.  Batches: use it with the batch solver as well. */
+hw_status hw_prepare_advance(hw_solver* s, int n_full_steps);
+
 /* Advance n half steps with plain kernel launches (no graph). */
 hw_status hw_half_steps(hw_solver* s, int n_half, void* stream);
 

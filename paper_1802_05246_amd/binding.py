@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 
 # every entry point declared in include/hermite_wave.h
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
-                "hw_advance", "hw_half_steps", "hw_get_state", "hw_state_grid", "hw_energy",
+                "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_get_state", "hw_state_grid", "hw_energy",
                 "hw_time", "hw_last_error", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
                 "hw_batch_get_state"]
@@ -70,6 +70,7 @@ def lib():
             "hw_cons_startup": ([vp, dp, dp, vp], ctypes.c_int),
             "hw_advance": ([vp, ctypes.c_int, vp], ctypes.c_int),
             "hw_half_steps": ([vp, ctypes.c_int, vp], ctypes.c_int),
+            "hw_prepare_advance": ([vp, ctypes.c_int], ctypes.c_int),
             "hw_get_state": ([vp, dp, dp, vp], ctypes.c_int),
             "hw_state_grid": ([vp], ctypes.c_int),
             "hw_energy": ([vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
@@ -181,6 +182,10 @@ def hw_advance(h, n, stream=None):
 
 def hw_batch_advance(h, n, stream=None):
     _check(lib().hw_batch_advance(h, n, _stream(stream)))
+
+
+def hw_prepare_advance(h, n):
+    _check(lib().hw_prepare_advance(h, n))
 
 
 def hw_half_steps(h, n, stream=None):

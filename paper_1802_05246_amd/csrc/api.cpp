@@ -444,23 +444,23 @@ hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out)
 void hw_destroy(hw_solver* s)
 {
     if (!s) return;
-    for (auto& kv : s->graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (Prob& P : s->probs) {
         for (int g = 0; g < 2; ++g) {
             for (int sl = 0; sl < 2; ++sl)
-                if (P.u[g][sl]) hipFree(P.u[g][sl]);
-            if (P.v[g]) hipFree(P.v[g]);
+                if (P.u[g][sl]) (void)hipFree(P.u[g][sl]);
+            if (P.v[g]) (void)hipFree(P.v[g]);
         }
-        if (P.v0tmp) hipFree(P.v0tmp);
+        if (P.v0tmp) (void)hipFree(P.v0tmp);
     }
-    if (s->ops) hipFree(s->ops);
-    if (s->dops) hipFree(s->dops);
-    if (s->descs) hipFree(s->descs);
-    if (s->startup_desc) hipFree(s->startup_desc);
-    if (s->startup_prefix) hipFree(s->startup_prefix);
-    if (s->prefix) hipFree(s->prefix);
-    if (s->partials) hipFree(s->partials);
-    if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+    if (s->ops) (void)hipFree(s->ops);
+    if (s->dops) (void)hipFree(s->dops);
+    if (s->descs) (void)hipFree(s->descs);
+    if (s->startup_desc) (void)hipFree(s->startup_desc);
+    if (s->startup_prefix) (void)hipFree(s->startup_prefix);
+    if (s->prefix) (void)hipFree(s->prefix);
+    if (s->partials) (void)hipFree(s->partials);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
 
@@ -547,6 +547,48 @@ hw_status hw_half_steps(hw_solver* s, int n, void* stream)
     return HW_OK;
 }
 
+static hw_status graph_for(hw_solver* s, int n, hipGraphExec_t* out)
+{
+    const int q = (int)((s->half_steps >> 1) & 1);
+    // the conservative slot parity selects buffers; dissipative steps do not depend on it
+    bool any_cons = false;
+    for (const Prob& P : s->probs) any_cons |= (P.p.method == HW_CONSERVATIVE);
+    auto key = std::make_pair(n, any_cons ? q : 0);
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) {
+        *out = it->second;
+        return HW_OK;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+    hw_status r = HW_OK;
+    int64_t hs = s->half_steps;
+    for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
+        r = launch_half(s, (int)(hs & 1), (int)((hs >> 1) & 1), s->cap_stream);
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+    if (r != HW_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return fail(HW_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HW_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    s->graphs[key] = exec;
+    *out = exec;
+    return HW_OK;
+}
+
+hw_status hw_prepare_advance(hw_solver* s, int n)
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (n < 1) return fail(HW_EINVAL, "step count must be >= 1");
+    if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
+    hipGraphExec_t exec = nullptr;
+    return graph_for(s, n, &exec);
+}
+
 hw_status hw_batch_advance(hw_solver* s, int n, void* stream)
 {
     if (check_solver(s)) return HW_EINVAL;
@@ -554,33 +596,9 @@ hw_status hw_batch_advance(hw_solver* s, int n, void* stream)
     if (!s->state_set) return fail(HW_ESTATE, "state not set");
     if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
     if (n == 0) return HW_OK;
-    const int q = (int)((s->half_steps >> 1) & 1);
-    // the conservative slot parity selects buffers; dissipative steps do not depend on it
-    bool any_cons = false;
-    for (const Prob& P : s->probs) any_cons |= (P.p.method == HW_CONSERVATIVE);
-    auto key = std::make_pair(n, any_cons ? q : 0);
-    auto it = s->graphs.find(key);
     hipGraphExec_t exec = nullptr;
-    if (it == s->graphs.end()) {
-        hipGraph_t graph = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-        hw_status r = HW_OK;
-        int64_t hs = s->half_steps;
-        for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
-            r = launch_half(s, (int)(hs & 1), (int)((hs >> 1) & 1), s->cap_stream);
-        hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
-        if (r != HW_OK) {
-            if (graph) hipGraphDestroy(graph);
-            return r;
-        }
-        if (e != hipSuccess) return fail(HW_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (e != hipSuccess) return fail(HW_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
-        s->graphs[key] = exec;
-    } else {
-        exec = it->second;
-    }
+    hw_status r = graph_for(s, n, &exec);
+    if (r != HW_OK) return r;
     HIP_TRY(hipGraphLaunch(exec, (hipStream_t)stream));
     s->half_steps += 2 * (int64_t)n;
     return HW_OK;

@@ -1,14 +1,507 @@
-// LDS-tiled MFMA half-step kernel for the 3-D dissipative full method, m = 3.
+// LDS-tiled half-step kernel for the 3-D dissipative method with the modified first
+// step (Sec. 3.3, d = 3), nodal degree m = 3, element type T = float or double.
+//
+// A workgroup owns a column of 4 x TY cells and walks it upwards in z, one node
+// layer of the input grid at a time.  Per layer:
+//   1. the (4+1) x (TY+1) nodes of the layer (u: 64, v: 27 coefficients) are
+//      staged in LDS; ghost nodes outside non-periodic walls are mirrored with the
+//      odd / even coefficient signs of Sec. 3.1.3;
+//   2. x-pass, once per x-edge of the layer (shared by the cells on both sides):
+//      the 8 inputs (side s, l_x) of every (l_y, l_z) line meet the 16 stacked rows
+//      [H_3 rows 0..3 | rows 2..7 of H_3 times (k+2)(k+1) | H_{m-1} on l <= 2];
+//      v lines meet H_{m-1};
+//   3. y- and z-passes per (cell, k_x): the y-pass of this layer is combined with
+//      the previous layer's (kept in registers) into the z-pass, giving for the
+//      cell between them p0 (centre rows), Q = I_{m-1}^3 v and
+//      R = sum_i (lambda_i/2)^2 d_i^2 c^(i) (the modified first step);
+//   4. the Taylor series in time is summed in closed form (Sec. 3.1.2): with
+//      S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2) the weights become compile-time
+//      constants, Q and R are stored pre-scaled by S, each output by 1/S(alpha):
+//        u' = p0 + (1/S(a)) sum_b W(a,b) [tau S Q/(2j+1)! + S R/(2j+2)!]
+//        v' = (1/(tau S(a))) sum_b W(a,b) [tau S Q/(2j)!  + S R/(2j+1)!]
+//      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!, j = |b|, k = a + 2b;
+//   5. the outputs of the cells are written back coalesced, row by row.
+// Every node of the input grid is read from HBM once per column (plus the one-node
+// halo shared with the neighbouring columns), every output node written once.
+#include "hermite_tables.h"
 #include "hw_kernels.h"
+
+namespace {
+
+constexpr int TX = 4;
+
+constexpr double kFact[20] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40320.0,
+                              362880.0, 3628800.0, 39916800.0, 479001600.0, 6227020800.0,
+                              87178291200.0, 1307674368000.0, 20922789888000.0,
+                              355687428096000.0, 6402373705728000.0, 121645100408832000.0};
+
+// 1-D operators, compile-time (indices must be compile-time constants)
+__device__ constexpr double opH3(int r, int c) { return kH3c[r * 8 + c]; }          // c = s*4 + l
+__device__ constexpr double opD2(int r, int c)                                        // r = 0..5
+{
+    return kH3c[(r + 2) * 8 + c] * (double)((r + 2) * (r + 1));
+}
+__device__ constexpr double opH2(int r, int c) { return kH2c[r * 6 + c]; }          // c = s*3 + l
+__device__ constexpr double opH2t(int r, int c)                                       // c = s*4 + l
+{
+    return (c % 4 == 3) ? 0.0 : kH2c[r * 6 + (c / 4) * 3 + (c % 4)];
+}
+// x-pass stacked rows: 0..3 H_3 centre rows, 4..9 second-derivative rows, 10..15 H_2t
+__device__ constexpr double opX(int r, int c)
+{
+    return r < 4 ? opH3(r, c) : (r < 10 ? opD2(r - 4, c) : opH2t(r - 10, c));
+}
+__device__ constexpr double wgt(int ax, int ay, int az, int bx, int by, int bz)
+{
+    return kFact[bx + by + bz] / (kFact[bx] * kFact[by] * kFact[bz]) * kFact[ax + 2 * bx] /
+           kFact[ax] * kFact[ay + 2 * by] / kFact[ay] * kFact[az + 2 * bz] / kFact[az];
+}
+
+template <typename T, int TY>
+struct Shared {
+    static constexpr int NXL = TX + 1, NYL = TY + 1;
+    static constexpr int NNODE = NXL * NYL;
+    static constexpr int NEDGE = TX * NYL;
+    static constexpr int NC = TX * TY;
+    T nu[NNODE][64];
+    T nv[NNODE][27];
+    T xu[NEDGE][16][16]; // [edge][row][l_y + 4 l_z]; reused for the staged outputs
+    T xv[NEDGE][6][9];   // [edge][row][l_y + 3 l_z]
+    T p0[NC][64];        // [cell][kx + 4 ky + 16 kz]
+    T q[NC][216];        // [cell][kx + 6 ky + 36 kz], tau S Q
+    T r[NC][216];        // S R
+};
+
+struct Map1 {
+    int j, ghost;
+};
+
+__device__ inline Map1 map_node(int gi, int ext, int bc)
+{
+    Map1 m;
+    m.ghost = 0;
+    if (bc == 0) {
+        int j = gi;
+        while (j < 0) j += ext;
+        while (j >= ext) j -= ext;
+        m.j = j;
+    } else if (gi < 0) {
+        m.j = 0;
+        m.ghost = 1;
+    } else if (gi >= ext) {
+        m.j = ext - 1;
+        m.ghost = 1;
+    } else {
+        m.j = gi;
+    }
+    return m;
+}
+
+// sign of coefficient l of a node mirrored across a wall of type bc
+__device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
+
+template <typename T, int PX, int PY, int PZ>
+__device__ void timesum_u(const T* __restrict__ q, const T* __restrict__ r, const T* __restrict__ p0,
+                          T* __restrict__ ou, const T inv[3])
+{
+#pragma unroll
+    for (int ax = PX; ax <= 3; ax += 2)
+#pragma unroll
+        for (int ay = PY; ay <= 3; ay += 2)
+#pragma unroll
+            for (int az = PZ; az <= 3; az += 2) {
+                T acc = T(0);
+#pragma unroll
+                for (int bz = 0; az + 2 * bz <= 5; ++bz)
+#pragma unroll
+                    for (int by = 0; ay + 2 * by <= 5; ++by)
+#pragma unroll
+                        for (int bx = 0; ax + 2 * bx <= 5; ++bx) {
+                            const int j = bx + by + bz;
+                            const int k = (ax + 2 * bx) + 6 * (ay + 2 * by) + 36 * (az + 2 * bz);
+                            const double w = wgt(ax, ay, az, bx, by, bz);
+                            acc += T(w / kFact[2 * j + 1]) * q[k];
+                            acc += T(w / kFact[2 * j + 2]) * r[k];
+                        }
+                T sc = T(1);
+                if (ax >= 2) sc *= inv[0];
+                if (ay >= 2) sc *= inv[1];
+                if (az >= 2) sc *= inv[2];
+                const int a = ax + 4 * ay + 16 * az;
+                ou[a] = p0[a] + sc * acc;
+            }
+}
+
+template <typename T, int PX, int PY, int PZ>
+__device__ void timesum_v(const T* __restrict__ q, const T* __restrict__ r, T* __restrict__ ov,
+                          const T inv[3], T inv_tau)
+{
+#pragma unroll
+    for (int ax = PX; ax <= 2; ax += 2)
+#pragma unroll
+        for (int ay = PY; ay <= 2; ay += 2)
+#pragma unroll
+            for (int az = PZ; az <= 2; az += 2) {
+                T acc = T(0);
+#pragma unroll
+                for (int bz = 0; az + 2 * bz <= 5; ++bz)
+#pragma unroll
+                    for (int by = 0; ay + 2 * by <= 5; ++by)
+#pragma unroll
+                        for (int bx = 0; ax + 2 * bx <= 5; ++bx) {
+                            const int j = bx + by + bz;
+                            const int k = (ax + 2 * bx) + 6 * (ay + 2 * by) + 36 * (az + 2 * bz);
+                            const double w = wgt(ax, ay, az, bx, by, bz);
+                            acc += T(w / kFact[2 * j]) * q[k];
+                            acc += T(w / kFact[2 * j + 1]) * r[k];
+                        }
+                T sc = inv_tau;
+                if (ax >= 2) sc *= inv[0];
+                if (ay >= 2) sc *= inv[1];
+                if (az >= 2) sc *= inv[2];
+                ov[ax + 3 * ay + 9 * az] = sc * acc;
+            }
+}
+
+template <typename T>
+__device__ void timesum_class(int p, int uv, const T* q, const T* r, const T* p0, T* ou, T* ov,
+                              const T inv[3], T inv_tau)
+{
+    // p = px + 2 py + 4 pz; compile-time weights per parity class
+    switch (p + 8 * uv) {
+    case 0: timesum_u<T, 0, 0, 0>(q, r, p0, ou, inv); break;
+    case 1: timesum_u<T, 1, 0, 0>(q, r, p0, ou, inv); break;
+    case 2: timesum_u<T, 0, 1, 0>(q, r, p0, ou, inv); break;
+    case 3: timesum_u<T, 1, 1, 0>(q, r, p0, ou, inv); break;
+    case 4: timesum_u<T, 0, 0, 1>(q, r, p0, ou, inv); break;
+    case 5: timesum_u<T, 1, 0, 1>(q, r, p0, ou, inv); break;
+    case 6: timesum_u<T, 0, 1, 1>(q, r, p0, ou, inv); break;
+    case 7: timesum_u<T, 1, 1, 1>(q, r, p0, ou, inv); break;
+    case 8: timesum_v<T, 0, 0, 0>(q, r, ov, inv, inv_tau); break;
+    case 9: timesum_v<T, 1, 0, 0>(q, r, ov, inv, inv_tau); break;
+    case 10: timesum_v<T, 0, 1, 0>(q, r, ov, inv, inv_tau); break;
+    case 11: timesum_v<T, 1, 1, 0>(q, r, ov, inv, inv_tau); break;
+    case 12: timesum_v<T, 0, 0, 1>(q, r, ov, inv, inv_tau); break;
+    case 13: timesum_v<T, 1, 0, 1>(q, r, ov, inv, inv_tau); break;
+    case 14: timesum_v<T, 0, 1, 1>(q, r, ov, inv, inv_tau); break;
+    default: timesum_v<T, 1, 1, 1>(q, r, ov, inv, inv_tau); break;
+    }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(16 * TX * TY)
+k_tiled3d_m3(TiledArgs a, int tz)
+{
+    using S = Shared<T, TY>;
+    constexpr int NT = 16 * TX * TY;
+    constexpr int NC = S::NC, NXL = S::NXL, NNODE = S::NNODE, NEDGE = S::NEDGE;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    S& sh = *reinterpret_cast<S*>(smem_raw);
+    const int tid = threadIdx.x;
+
+    const int tiles_x = (a.ext_to[0] + TX - 1) / TX;
+    const int x0 = (blockIdx.x % tiles_x) * TX;
+    const int y0 = (blockIdx.x / tiles_x) * TY;
+    const int cz0 = blockIdx.y * tz;
+    const int cz1 = min(cz0 + tz, a.ext_to[2]);
+    const int off = (a.to_grid == 1) ? 0 : -1; // input node of corner s = cell + off + s
+
+    const T l2x = T(a.lam2[0]), l2y = T(a.lam2[1]), l2z = T(a.lam2[2]);
+    const T sy[3] = {T(1), l2y, l2y * l2y}, sz[3] = {T(1), l2z, l2z * l2z};
+    const T inv[3] = {T(1.0 / a.lam2[0]), T(1.0 / a.lam2[1]), T(1.0 / a.lam2[2])};
+    const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
+    const T* __restrict__ gu = (const T*)a.u_in;
+    const T* __restrict__ gv = (const T*)a.v_in;
+
+    // ---- stage 1: one node layer (global -> LDS), ghosts mirrored with signs ----
+    const long long plane = (long long)a.ext_from[0] * a.ext_from[1];
+    auto load_layer = [&](int layer_gz) {
+        const Map1 mz = map_node(layer_gz, a.ext_from[2], a.bc[2]);
+        for (int e = tid; e < NNODE * 91; e += NT) {
+            const int node = e / 91, c = e % 91;
+            const int na = node % NXL, nb = node / NXL;
+            const Map1 mx = map_node(x0 + off + na, a.ext_from[0], a.bc[0]);
+            const Map1 my = map_node(y0 + off + nb, a.ext_from[1], a.bc[1]);
+            const long long gnode = (long long)mx.j + (long long)a.ext_from[0] * my.j + plane * mz.j;
+            const bool isv = c >= 64;
+            const int cc = isv ? c - 64 : c;
+            const int M = isv ? 3 : 4;
+            const int lx = cc % M, ly = (cc / M) % M, lz = cc / (M * M);
+            bool neg = false;
+            if (mx.ghost && flips(a.bc[0], lx)) neg = !neg;
+            if (my.ghost && flips(a.bc[1], ly)) neg = !neg;
+            if (mz.ghost && flips(a.bc[2], lz)) neg = !neg;
+            const T val = isv ? gv[gnode * 27 + cc] : gu[gnode * 64 + cc];
+            if (isv) sh.nv[node][cc] = neg ? -val : val;
+            else sh.nu[node][cc] = neg ? -val : val;
+        }
+    };
+
+    // ---- stage-3 task of this thread: [p0: 4 kx | R: 6 kx | Q: 6 kx] x NC cells ----
+    const int t3 = tid / NC, cell3 = tid % NC;
+    const int kind = t3 < 4 ? 0 : (t3 < 10 ? 1 : 2);
+    const int kx = kind == 0 ? t3 : (kind == 1 ? t3 - 4 : t3 - 10);
+    const int ccx = cell3 % TX, ccy = cell3 / TX;
+    const int e0 = ccx + TX * ccy, e1 = ccx + TX * (ccy + 1); // x-edges below / above in y
+    // previous layer's y-pass results (registers)
+    T pA[24], pB[24];
+
+    const int nlayers = cz1 - cz0 + 1;
+    for (int step = 0; step < nlayers; ++step) {
+        load_layer(cz0 + off + step);
+        __syncthreads();
+
+        // ---- 2. x-pass ----
+        for (int task = tid; task < NEDGE * 25; task += NT) {
+            if (task < NEDGE * 16) {
+                const int e = task / 16, line = task % 16;
+                const int cx = e % TX, b = e / TX;
+                const int n0 = cx + NXL * b;
+                const int ly = line % 4, lz = line / 4;
+                T in[8];
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) in[s * 4 + l] = sh.nu[n0 + s][l + 4 * ly + 16 * lz];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (opX(r, c) != 0.0) acc += T(opX(r, c)) * in[c];
+                    sh.xu[e][r][line] = acc;
+                }
+            } else {
+                const int tv = task - NEDGE * 16;
+                const int e = tv / 9, line = tv % 9;
+                const int cx = e % TX, b = e / TX;
+                const int n0 = cx + NXL * b;
+                const int ly = line % 3, lz = line / 3;
+                T in[6];
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) in[s * 3 + l] = sh.nv[n0 + s][l + 3 * ly + 9 * lz];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        if (opH2(r, c) != 0.0) acc += T(opH2(r, c)) * in[c];
+                    sh.xv[e][r][line] = acc;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- 3. y-pass of this layer, z-pass with the previous one ----
+        const bool emit = step > 0;
+        const int cz = cz0 + step - 1; // cell layer produced in this step
+        if (kind == 0) {
+            // p0: Y[ky][lz] = sum_{s,ly} H3[ky][s,ly] xu[e_s][kx][ly + 4 lz]
+            T cur[16];
+#pragma unroll
+            for (int lz = 0; lz < 4; ++lz) {
+                T in[8];
+#pragma unroll
+                for (int ly = 0; ly < 4; ++ly) {
+                    in[ly] = sh.xu[e0][kx][ly + 4 * lz];
+                    in[4 + ly] = sh.xu[e1][kx][ly + 4 * lz];
+                }
+#pragma unroll
+                for (int ky = 0; ky < 4; ++ky) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (opH3(ky, c) != 0.0) acc += T(opH3(ky, c)) * in[c];
+                    cur[ky + 4 * lz] = acc;
+                }
+            }
+            if (emit) {
+#pragma unroll
+                for (int ky = 0; ky < 4; ++ky)
+#pragma unroll
+                    for (int kz = 0; kz < 4; ++kz) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int lz = 0; lz < 4; ++lz) {
+                            if (opH3(kz, lz) != 0.0) acc += T(opH3(kz, lz)) * pA[ky + 4 * lz];
+                            if (opH3(kz, 4 + lz) != 0.0) acc += T(opH3(kz, 4 + lz)) * cur[ky + 4 * lz];
+                        }
+                        sh.p0[cell3][kx + 4 * ky + 16 * kz] = acc;
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) pA[i] = cur[i];
+        } else if (kind == 1) {
+            // R: Rxy[ky][lz<=2] (x and y terms, z op H_2), Rz[ky][lz<=3] (z term, z op d2)
+            T curA[18], curB[24];
+#pragma unroll
+            for (int lz = 0; lz < 4; ++lz) {
+                T d2x[6], h2x[8];
+#pragma unroll
+                for (int ly = 0; ly < 4; ++ly) {
+                    h2x[ly] = sh.xu[e0][10 + kx][ly + 4 * lz];
+                    h2x[4 + ly] = sh.xu[e1][10 + kx][ly + 4 * lz];
+                }
+                if (lz < 3) {
+#pragma unroll
+                    for (int ly = 0; ly < 3; ++ly) {
+                        d2x[ly] = sh.xu[e0][4 + kx][ly + 4 * lz];
+                        d2x[3 + ly] = sh.xu[e1][4 + kx][ly + 4 * lz];
+                    }
+#pragma unroll
+                    for (int ky = 0; ky < 6; ++ky) {
+                        T ax_ = T(0), ay_ = T(0);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+                            if (opH2(ky, c) != 0.0) ax_ += T(opH2(ky, c)) * d2x[c];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            if (opD2(ky, c) != 0.0) ay_ += T(opD2(ky, c)) * h2x[c];
+                        curA[ky + 6 * lz] = l2x * ax_ + l2y * ay_;
+                    }
+                }
+#pragma unroll
+                for (int ky = 0; ky < 6; ++ky) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (opH2t(ky, c) != 0.0) acc += T(opH2t(ky, c)) * h2x[c];
+                    curB[ky + 6 * lz] = acc;
+                }
+            }
+            if (emit) {
+                const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
+#pragma unroll
+                for (int ky = 0; ky < 6; ++ky)
+#pragma unroll
+                    for (int kz = 0; kz < 6; ++kz) {
+                        T acc = T(0), accz = T(0);
+#pragma unroll
+                        for (int lz = 0; lz < 3; ++lz) {
+                            if (opH2(kz, lz) != 0.0) acc += T(opH2(kz, lz)) * pA[ky + 6 * lz];
+                            if (opH2(kz, 3 + lz) != 0.0) acc += T(opH2(kz, 3 + lz)) * curA[ky + 6 * lz];
+                        }
+#pragma unroll
+                        for (int lz = 0; lz < 4; ++lz) {
+                            if (opD2(kz, lz) != 0.0) accz += T(opD2(kz, lz)) * pB[ky + 6 * lz];
+                            if (opD2(kz, 4 + lz) != 0.0) accz += T(opD2(kz, 4 + lz)) * curB[ky + 6 * lz];
+                        }
+                        sh.r[cell3][kx + 6 * ky + 36 * kz] =
+                            (acc + l2z * accz) * (skx * sy[ky / 2] * sz[kz / 2]);
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 18; ++i) pA[i] = curA[i];
+#pragma unroll
+            for (int i = 0; i < 24; ++i) pB[i] = curB[i];
+        } else {
+            // Q: Qy[ky][lz<=2] = sum_{s,ly} H2[ky][s,ly] xv[e_s][kx][ly + 3 lz]
+            T cur[18];
+#pragma unroll
+            for (int lz = 0; lz < 3; ++lz) {
+                T in[6];
+#pragma unroll
+                for (int ly = 0; ly < 3; ++ly) {
+                    in[ly] = sh.xv[e0][kx][ly + 3 * lz];
+                    in[3 + ly] = sh.xv[e1][kx][ly + 3 * lz];
+                }
+#pragma unroll
+                for (int ky = 0; ky < 6; ++ky) {
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        if (opH2(ky, c) != 0.0) acc += T(opH2(ky, c)) * in[c];
+                    cur[ky + 6 * lz] = acc;
+                }
+            }
+            if (emit) {
+                const T skx = tau * (kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x));
+#pragma unroll
+                for (int ky = 0; ky < 6; ++ky)
+#pragma unroll
+                    for (int kz = 0; kz < 6; ++kz) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int lz = 0; lz < 3; ++lz) {
+                            if (opH2(kz, lz) != 0.0) acc += T(opH2(kz, lz)) * pA[ky + 6 * lz];
+                            if (opH2(kz, 3 + lz) != 0.0) acc += T(opH2(kz, 3 + lz)) * cur[ky + 6 * lz];
+                        }
+                        sh.q[cell3][kx + 6 * ky + 36 * kz] = acc * (skx * sy[ky / 2] * sz[kz / 2]);
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < 18; ++i) pA[i] = cur[i];
+        }
+        if (!emit) continue; // the first layer only primes the registers
+        __syncthreads();
+
+        // ---- 4. time sums: task (class p, u or v) x NC cells; outputs staged in xu ----
+        T* ou_base = &sh.xu[0][0][0];
+        T* ov_base = ou_base + NC * 64;
+        for (int task = tid; task < 16 * NC; task += NT) {
+            const int cl = task / NC, c = task % NC;
+            const int p = cl % 8, uv = cl / 8;
+            timesum_class<T>(p, uv, sh.q[c], sh.r[c], sh.p0[c], ou_base + c * 64, ov_base + c * 27,
+                             inv, inv_tau);
+        }
+        __syncthreads();
+
+        // ---- 5. store the cell layer cz ----
+        {
+            T* __restrict__ out_u = (T*)a.u_out;
+            T* __restrict__ out_v = (T*)a.v_out;
+            for (int i = tid; i < NC * 91; i += NT) {
+                int c, coef;
+                bool isv;
+                if (i < NC * 64) {
+                    c = i / 64;
+                    coef = i % 64;
+                    isv = false;
+                } else {
+                    c = (i - NC * 64) / 27;
+                    coef = (i - NC * 64) % 27;
+                    isv = true;
+                }
+                const int gx = x0 + c % TX, gy = y0 + c / TX;
+                if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+                const long long g = gx + (long long)a.ext_to[0] * (gy + (long long)a.ext_to[1] * cz);
+                if (isv) out_v[g * 27 + coef] = ov_base[c * 27 + coef];
+                else out_u[g * 64 + coef] = ou_base[c * 64 + coef];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int TY>
+hipError_t launch(const TiledArgs& a, hipStream_t st)
+{
+    constexpr int NT = 16 * TX * TY;
+    const size_t lds = sizeof(Shared<T, TY>);
+    auto kern = k_tiled3d_m3<T, TY>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    const int tz = 64;
+    const int tiles = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + TY - 1) / TY);
+    const int chunks = (a.ext_to[2] + tz - 1) / tz;
+    hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz);
+    return hipGetLastError();
+}
+
+} // namespace
 
 bool hw_tiled_supported(int d, int m, int method, int precision)
 {
-    (void)d; (void)m; (void)method; (void)precision;
-    return false;
+    return d == 3 && m == 3 && method == 0 && (precision == 0 || precision == 1);
 }
 
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st)
 {
-    (void)a; (void)precision; (void)st;
-    return hipErrorInvalidValue;
+    for (int i = 0; i < 3; ++i)
+        if (!(a.lam2[i] >= 2.5e-7) || a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
+    if (precision == 0) return launch<double, 4>(a, st);
+    return launch<float, 8>(a, st);
 }

@@ -135,3 +135,36 @@ def sampled_oracle(spec, to_grid, u_in, v_in, samples, u_old=None):
             out_u.append(ru[0])
             out_v.append(rv[0])
     return np.array(out_u), (np.array(out_v) if out_v else None)
+
+
+def _gram0(M):
+    """G0[a][b] = int_{-1/2}^{1/2} z^(a+b) dz"""
+    a = np.arange(M)
+    e = a[:, None] + a[None, :]
+    return np.where(e % 2 == 0, 1.0 / ((e + 1) * 2.0 ** e), 0.0)
+
+
+def poly_norm2(coefs, d, M):
+    """Squared L2 norm over the cell [-1/2,1/2]^d of the local Taylor polynomials
+    sum_l a_l z^l (one per row), summed over rows."""
+    a = np.asarray(coefs, dtype=np.float64).reshape((-1,) + (M,) * d)
+    G = _gram0(M)
+    g = a
+    for ax in range(d):
+        g = np.moveaxis(np.tensordot(g, G, axes=([ax + 1], [0])), -1, ax + 1)
+    return float(np.sum(a * g))
+
+
+def poly_rel_err(spec, gu, ou, gv=None, ov=None):
+    """Relative L2 error of the local Taylor polynomials of [u, tau v] at the nodes,
+    in the L2 norm of the cell (the norm of the paper's error measurements): each
+    coefficient counts with its weight in the function, so the tiny high mixed
+    derivatives do not dominate."""
+    d, M = spec.d, spec.m + 1
+    num = poly_norm2(np.asarray(gu) - np.asarray(ou), d, M)
+    den = poly_norm2(ou, d, M)
+    if gv is not None and spec.method != 2:
+        tau = 0.5 * spec.dt
+        num += tau * tau * poly_norm2(np.asarray(gv) - np.asarray(ov), d, M - 1)
+        den += tau * tau * poly_norm2(ov, d, M - 1)
+    return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))

@@ -2,14 +2,17 @@
 
 Tolerances.  FP64 form: rel-L2 <= 1e-10 for u and for v separately, over every
 coefficient of every node (expected 1e-13..1e-11; cond(H_6) ~ 1.4e5 sets the
-ceiling).  FP32 form: the relative L2 error of the joint vector [u, tau*v]
-(tau = dt/2, so both parts carry the units of u) is at most
-max(2e-5, 2 u32 cond(H_m) n_half), u32 = 2^-24: each half step perturbs the nodal
-data by single-precision rounding, which interpolation amplifies by at most
-cond(H_m), and the perturbations add up over the n_half checked half steps.  A
-per-field bound would not do for v right after v0 = 0: there v is small and made of
-second differences of very smooth data, so its own relative rounding error is large
-although it is tiny next to u.
+ceiling).  FP32 form: the error is measured in the norm the paper measures errors
+in, the L2 norm of the solution: the relative L2 norm over the cell of the local
+Taylor polynomials of [u, tau*v] (tau = dt/2) at the nodes.  Each half step
+perturbs the data by single-precision rounding (u32 = 2^-24); interpolation and the
+time sums amplify it by a modest factor in this norm that grows with the size of the
+Hermite operator's entries (largest |entry| of H_m: 1, 2, 6, 21, 90, 385, 1638 for
+m = 0..6), and the perturbations add up over the checked half steps:
+tol = 200 u32 n_half max(1, max|H_m| / max|H_3|).  (Coefficient by coefficient the
+highest mixed derivatives of smooth data are tiny and are computed through products
+of Hermite rows with entries up to 21 (m = 3); their relative rounding error is
+large although they hardly contribute to the function.)
 """
 import sys
 
@@ -18,28 +21,25 @@ import pytest
 
 from paper_1802_05246_amd import workloads as W
 
-from helpers import oracle_reference_run, rel_l2, sampled_oracle
+from helpers import oracle_reference_run, poly_rel_err, rel_l2, sampled_oracle
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 
-COND_H = [2.0, 7.17, 38.8, 273.3, 2082.6, 16786.7, 140353.5]
+U32 = 2.0 ** -24
+
+
+_HMAX = [1.0, 2.0, 6.0, 21.0, 90.0, 385.0, 1638.0]  # largest |entry| of H_m
 
 
 def fp32_tol(m, n_half):
-    return max(2e-5, 2.0 * 2.0 ** -24 * COND_H[m] * max(1, n_half))
+    return 200.0 * U32 * max(1, n_half) * max(1.0, _HMAX[m] / _HMAX[3])
 
 
 def joint_err(spec, gu, gv, ou, ov):
-    """relative L2 of [u, tau v] (u only for the conservative method)"""
-    if spec.method == W.CONSERVATIVE or gv is None:
-        return rel_l2(gu, ou)
-    tau = 0.5 * spec.dt
-    a = np.concatenate([np.ravel(gu), tau * np.ravel(gv)])
-    b = np.concatenate([np.ravel(ou), tau * np.ravel(ov)])
-    return rel_l2(a, b)
+    return poly_rel_err(spec, gu, ou, gv, ov)
 
 
 def _B():
@@ -324,3 +324,62 @@ def test_full_size_2d_diss_m3_sampled():
     w = W.c2_2d()
     for steps_half in (1, 2):
         _sampled_check(w.spec, B.HW_FP64, 64, 13, (w.u0, w.v0), steps_half)
+
+
+TILED_CASES = [
+    ([5, 4, 6], [W.PERIODIC, W.PERIODIC, W.PERIODIC]),
+    ([9, 11, 3], [W.PERIODIC, W.PERIODIC, W.PERIODIC]),
+    ([6, 5, 7], [W.DIRICHLET, W.NEUMANN, W.PERIODIC]),
+    ([4, 9, 5], [W.NEUMANN, W.DIRICHLET, W.DIRICHLET]),
+    ([7, 3, 4], [W.PERIODIC, W.DIRICHLET, W.NEUMANN]),
+]
+
+
+@pytest.mark.parametrize("n,bc", TILED_CASES, ids=[f"{'x'.join(map(str, n))}-bc{''.join(map(str, b))}" for n, b in TILED_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_3d_m3_matches_oracle(n, bc, prec):
+    """The LDS-tiled 3-D m = 3 kernel (ragged tiles, every wall type, both half-step
+    directions, anisotropic h): FP64 to 1e-10 per coefficient, FP32 to the
+    polynomial-L2 tolerance."""
+    B = _B()
+    _log(f"[tiled] n={n} bc={bc} {prec}")
+    spec = W.make_spec(3, 3, n, 0.0, [1.0, 0.8, 0.9], 1.2, cfl=0.85, bc=bc, method=W.DISS_FULL)
+    u, w = _state(spec, 31 + sum(n))
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_TILED)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    n_half = 4
+    s.half_steps(n_half)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
+    if prec == "fp64":
+        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+    else:
+        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(3, n_half)
+    _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
+    assert err <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tiled_equals_generic(prec):
+    """Same problem through both kernels: FP64 agree to round-off, FP32 to the
+    FP32 tolerance (different summation orders)."""
+    B = _B()
+    spec = W.make_spec(3, 3, [10, 9, 8], 0.0, 1.0, 1.0, cfl=0.9, bc=W.PERIODIC)
+    u, w = _state(spec, 77)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    a = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_TILED)
+    b = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_GENERIC)
+    for s in (a, b):
+        s.set_state(u, w)
+        s.advance(3)
+    ua, wa = (x.cpu().numpy() for x in a.get_state())
+    ub, wb = (x.cpu().numpy() for x in b.get_state())
+    if prec == "fp64":
+        assert max(rel_l2(ua, ub), rel_l2(wa, wb)) < 1e-11
+    else:
+        assert joint_err(spec, ua, wa, ub, wb) < fp32_tol(3, 6)
+    a.close()
+    b.close()
