@@ -409,6 +409,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         hipMemcpy(s->prefix, s->h_prefix.data(), s->h_prefix.size() * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(HW_EHIP, "descriptor upload failed"));
+    if (s->use_tiled && hw_tiled_prepare(s->precision) != hipSuccess)
+        return cleanup(fail(HW_EHIP, "tiled kernel table setup failed"));
     if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail(HW_EHIP, "stream creation failed"));
     *out = s;

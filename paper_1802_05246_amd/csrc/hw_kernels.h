@@ -28,4 +28,5 @@ struct TiledArgs {
     double tau, lam2[3];
 };
 bool hw_tiled_supported(int d, int m, int method, int precision);
+hipError_t hw_tiled_prepare(int precision); // builds the constant tables (call outside capture)
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st);

@@ -6,23 +6,32 @@
 //   1. the (4+1) x (TY+1) nodes of the layer (u: 64, v: 27 coefficients) are
 //      staged in LDS; ghost nodes outside non-periodic walls are mirrored with the
 //      odd / even coefficient signs of Sec. 3.1.3;
-//   2. x-pass, once per x-edge of the layer (shared by the cells on both sides):
-//      the 8 inputs (side s, l_x) of every (l_y, l_z) line meet the 16 stacked rows
-//      [H_3 rows 0..3 | rows 2..7 of H_3 times (k+2)(k+1) | H_{m-1} on l <= 2];
-//      v lines meet H_{m-1};
-//   3. y- and z-passes per (cell, k_x): the y-pass of this layer is combined with
-//      the previous layer's (kept in registers) into the z-pass, giving for the
-//      cell between them p0 (centre rows), Q = I_{m-1}^3 v and
-//      R = sum_i (lambda_i/2)^2 d_i^2 c^(i) (the modified first step);
-//   4. the Taylor series in time is summed in closed form (Sec. 3.1.2): with
-//      S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2) the weights become compile-time
-//      constants, Q and R are stored pre-scaled by S, each output by 1/S(alpha):
+//   2. x-pass, once per x-edge of the layer (shared by the cells on both sides), on
+//      the matrix cores: the 16 stacked rows [H_3 rows 0..3 | rows 2..7 of H_3 times
+//      (k+2)(k+1) | H_{m-1} on l <= 2] times the 8 inputs (side s, l_x) of the 16
+//      (l_y, l_z) lines of the edge, one 16x16x8 product per edge; v lines meet
+//      H_{m-1} on the vector units;
+//   3. y- and z-passes per (cell, k_x, half of the k_y range): the y-pass of this
+//      layer is combined with the previous layer's (kept in registers) into the
+//      z-pass, giving for the cell between the two layers p0 (centre rows),
+//      Q = I_{m-1}^3 v and R = sum_i (lambda_i/2)^2 d_i^2 c^(i) (modified first step);
+//   4. the Taylor series in time is summed in closed form (Sec. 3.1.2).  With
+//      S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2) the weights are constants: Q and R
+//      are stored pre-scaled by S and each output is scaled by 1/S(alpha),
 //        u' = p0 + (1/S(a)) sum_b W(a,b) [tau S Q/(2j+1)! + S R/(2j+2)!]
 //        v' = (1/(tau S(a))) sum_b W(a,b) [tau S Q/(2j)!  + S R/(2j+1)!]
-//      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!, j = |b|, k = a + 2b;
+//      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!, j = |b|, k = a + 2b.  Only k with
+//      the parity of a enter, so the sums split into 8 parity classes, each a dense
+//      (<= 16 outputs) x (27 Q + 27 R inputs) block applied to 16 cells at a time on
+//      the matrix cores;
 //   5. the outputs of the cells are written back coalesced, row by row.
 // Every node of the input grid is read from HBM once per column (plus the one-node
 // halo shared with the neighbouring columns), every output node written once.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
 #include "hermite_tables.h"
 #include "hw_kernels.h"
 
@@ -35,27 +44,35 @@ constexpr double kFact[20] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0, 720.0, 5040.0, 40
                               87178291200.0, 1307674368000.0, 20922789888000.0,
                               355687428096000.0, 6402373705728000.0, 121645100408832000.0};
 
-// 1-D operators, compile-time (indices must be compile-time constants)
-__device__ constexpr double opH3(int r, int c) { return kH3c[r * 8 + c]; }          // c = s*4 + l
-__device__ constexpr double opD2(int r, int c)                                        // r = 0..5
+// 1-D operators (compile-time tables; device uses need compile-time indices)
+__host__ __device__ constexpr double opH3(int r, int c) { return kH3c[r * 8 + c]; } // c = s*4 + l
+__host__ __device__ constexpr double opD2(int r, int c)                               // r = 0..5
 {
     return kH3c[(r + 2) * 8 + c] * (double)((r + 2) * (r + 1));
 }
-__device__ constexpr double opH2(int r, int c) { return kH2c[r * 6 + c]; }          // c = s*3 + l
-__device__ constexpr double opH2t(int r, int c)                                       // c = s*4 + l
+__host__ __device__ constexpr double opH2(int r, int c) { return kH2c[r * 6 + c]; } // c = s*3 + l
+__host__ __device__ constexpr double opH2t(int r, int c)                              // c = s*4 + l
 {
     return (c % 4 == 3) ? 0.0 : kH2c[r * 6 + (c / 4) * 3 + (c % 4)];
 }
 // x-pass stacked rows: 0..3 H_3 centre rows, 4..9 second-derivative rows, 10..15 H_2t
-__device__ constexpr double opX(int r, int c)
+__host__ __device__ constexpr double opX(int r, int c)
 {
     return r < 4 ? opH3(r, c) : (r < 10 ? opD2(r - 4, c) : opH2t(r - 10, c));
 }
-__device__ constexpr double wgt(int ax, int ay, int az, int bx, int by, int bz)
-{
-    return kFact[bx + by + bz] / (kFact[bx] * kFact[by] * kFact[bz]) * kFact[ax + 2 * bx] /
-           kFact[ax] * kFact[ay + 2 * by] / kFact[ay] * kFact[az + 2 * bz] / kFact[az];
-}
+
+// LDS strides are odd numbers of 4-byte words so that the lanes of a wave, which
+// index neighbouring nodes, edges or cells, fall into different banks.
+constexpr int NUP = 65;  // node stride of u
+constexpr int NVP = 29;  // node stride of v
+constexpr int XUE = 257; // x-edge stride of the u x-pass results: [row][l_y + 4 l_z] + 1
+constexpr int XVE = 55;  // x-edge stride of the v x-pass results: [row][l_y + 3 l_z] + 1
+constexpr int P0S = 65;  // cell stride of p0: [kx + 4 ky + 16 kz]
+constexpr int ZS = 433;  // cell stride of [tau S Q (216) | S R (216) | 0]
+constexpr int OUS = 65;  // cell stride of the staged u outputs
+
+// time-sum blocks: 8 classes x 14 K-steps of 4 (54 inputs padded to 56)
+constexpr int TS_KSTEPS = 14;
 
 template <typename T, int TY>
 struct Shared {
@@ -63,13 +80,50 @@ struct Shared {
     static constexpr int NNODE = NXL * NYL;
     static constexpr int NEDGE = TX * NYL;
     static constexpr int NC = TX * TY;
-    T nu[NNODE][64];
-    T nv[NNODE][27];
-    T xu[NEDGE][16][16]; // [edge][row][l_y + 4 l_z]; reused for the staged outputs
-    T xv[NEDGE][6][9];   // [edge][row][l_y + 3 l_z]
-    T p0[NC][64];        // [cell][kx + 4 ky + 16 kz]
-    T q[NC][216];        // [cell][kx + 6 ky + 36 kz], tau S Q
-    T r[NC][216];        // S R
+    T nu[NNODE * NUP];
+    T nv[NNODE * NVP];
+    T xu[NEDGE * XUE]; // reused for the staged outputs
+    T xv[NEDGE * XVE];
+    T p0[NC * P0S];
+    T z[NC * ZS];
+    static_assert(NC * (OUS + 27) <= NEDGE * XUE, "staged outputs must fit the x-pass region");
+    static_assert(NC % 16 == 0, "cells come in groups of 16 for the time-sum products");
+};
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(float a, float b, vec c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row of the 16x16 result held in element r of lane l (column = l % 16)
+    static __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mfma<double> {
+    typedef double vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(double a, double b, vec c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Device tables (per element type), built once on the host:
+//   xa[2][64]          A operand of the x-pass (K-step, lane): opX[l%16][4 ks + l/16]
+//   ta[8][14][64]      A operand of the class blocks (class, K-step, lane)
+//   tk[8][56]          LDS offset in the cell block [Q|R|0] of input kk of a class
+//   tr[8][16]          output decode of (class, row): -1 unused, else
+//                      is_v << 12 | scale mask (alpha_i >= 2) << 8 | flat alpha index
+template <typename T>
+struct Tables {
+    T xa[2][64];
+    T ta[8][TS_KSTEPS][64];
+    int tk[8][TS_KSTEPS * 4];
+    int tr[8][16];
 };
 
 struct Map1 {
@@ -100,104 +154,119 @@ __device__ inline Map1 map_node(int gi, int ext, int bc)
 // sign of coefficient l of a node mirrored across a wall of type bc
 __device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
 
-template <typename T, int PX, int PY, int PZ>
-__device__ void timesum_u(const T* __restrict__ q, const T* __restrict__ r, const T* __restrict__ p0,
-                          T* __restrict__ ou, const T inv[3])
+// One output row of a 1-D Hermite operator from the sums E[l] = left + right and
+// differences O[l] = left - right of the two nodes' data.  The operators satisfy
+// H[k][right, l] = (-1)^(k+l) H[k][left, l] (reflection of the cell about its centre),
+// so row k needs only the left-node column and E or O by the parity of k + l; `parity`
+// is the derivative order k of the row (row + 2 for the second-derivative rows).
+template <int NL, typename T, typename Op>
+__device__ inline T sym(Op op, int row, int parity, const T* E, const T* O)
 {
+    T acc = T(0);
 #pragma unroll
-    for (int ax = PX; ax <= 3; ax += 2)
-#pragma unroll
-        for (int ay = PY; ay <= 3; ay += 2)
-#pragma unroll
-            for (int az = PZ; az <= 3; az += 2) {
-                T acc = T(0);
-#pragma unroll
-                for (int bz = 0; az + 2 * bz <= 5; ++bz)
-#pragma unroll
-                    for (int by = 0; ay + 2 * by <= 5; ++by)
-#pragma unroll
-                        for (int bx = 0; ax + 2 * bx <= 5; ++bx) {
-                            const int j = bx + by + bz;
-                            const int k = (ax + 2 * bx) + 6 * (ay + 2 * by) + 36 * (az + 2 * bz);
-                            const double w = wgt(ax, ay, az, bx, by, bz);
-                            acc += T(w / kFact[2 * j + 1]) * q[k];
-                            acc += T(w / kFact[2 * j + 2]) * r[k];
-                        }
-                T sc = T(1);
-                if (ax >= 2) sc *= inv[0];
-                if (ay >= 2) sc *= inv[1];
-                if (az >= 2) sc *= inv[2];
-                const int a = ax + 4 * ay + 16 * az;
-                ou[a] = p0[a] + sc * acc;
-            }
-}
-
-template <typename T, int PX, int PY, int PZ>
-__device__ void timesum_v(const T* __restrict__ q, const T* __restrict__ r, T* __restrict__ ov,
-                          const T inv[3], T inv_tau)
-{
-#pragma unroll
-    for (int ax = PX; ax <= 2; ax += 2)
-#pragma unroll
-        for (int ay = PY; ay <= 2; ay += 2)
-#pragma unroll
-            for (int az = PZ; az <= 2; az += 2) {
-                T acc = T(0);
-#pragma unroll
-                for (int bz = 0; az + 2 * bz <= 5; ++bz)
-#pragma unroll
-                    for (int by = 0; ay + 2 * by <= 5; ++by)
-#pragma unroll
-                        for (int bx = 0; ax + 2 * bx <= 5; ++bx) {
-                            const int j = bx + by + bz;
-                            const int k = (ax + 2 * bx) + 6 * (ay + 2 * by) + 36 * (az + 2 * bz);
-                            const double w = wgt(ax, ay, az, bx, by, bz);
-                            acc += T(w / kFact[2 * j]) * q[k];
-                            acc += T(w / kFact[2 * j + 1]) * r[k];
-                        }
-                T sc = inv_tau;
-                if (ax >= 2) sc *= inv[0];
-                if (ay >= 2) sc *= inv[1];
-                if (az >= 2) sc *= inv[2];
-                ov[ax + 3 * ay + 9 * az] = sc * acc;
-            }
-}
-
-template <typename T>
-__device__ void timesum_class(int p, int uv, const T* q, const T* r, const T* p0, T* ou, T* ov,
-                              const T inv[3], T inv_tau)
-{
-    // p = px + 2 py + 4 pz; compile-time weights per parity class
-    switch (p + 8 * uv) {
-    case 0: timesum_u<T, 0, 0, 0>(q, r, p0, ou, inv); break;
-    case 1: timesum_u<T, 1, 0, 0>(q, r, p0, ou, inv); break;
-    case 2: timesum_u<T, 0, 1, 0>(q, r, p0, ou, inv); break;
-    case 3: timesum_u<T, 1, 1, 0>(q, r, p0, ou, inv); break;
-    case 4: timesum_u<T, 0, 0, 1>(q, r, p0, ou, inv); break;
-    case 5: timesum_u<T, 1, 0, 1>(q, r, p0, ou, inv); break;
-    case 6: timesum_u<T, 0, 1, 1>(q, r, p0, ou, inv); break;
-    case 7: timesum_u<T, 1, 1, 1>(q, r, p0, ou, inv); break;
-    case 8: timesum_v<T, 0, 0, 0>(q, r, ov, inv, inv_tau); break;
-    case 9: timesum_v<T, 1, 0, 0>(q, r, ov, inv, inv_tau); break;
-    case 10: timesum_v<T, 0, 1, 0>(q, r, ov, inv, inv_tau); break;
-    case 11: timesum_v<T, 1, 1, 0>(q, r, ov, inv, inv_tau); break;
-    case 12: timesum_v<T, 0, 0, 1>(q, r, ov, inv, inv_tau); break;
-    case 13: timesum_v<T, 1, 0, 1>(q, r, ov, inv, inv_tau); break;
-    case 14: timesum_v<T, 0, 1, 1>(q, r, ov, inv, inv_tau); break;
-    default: timesum_v<T, 1, 1, 1>(q, r, ov, inv, inv_tau); break;
+    for (int l = 0; l < NL; ++l) {
+        const double w = op(row, l);
+        if (w != 0.0) acc += T(w) * (((parity + l) & 1) ? O[l] : E[l]);
     }
+    return acc;
+}
+
+// y- and z-passes of the R and Q paths for rows k_y = KH .. KH+2 of one (cell, k_x).
+// Rxy[ky][lz <= 2] = (l_x/2)^2 H2t_y d2_x + (l_y/2)^2 d2_y H2t_x  (z operator H_2),
+// Rz[ky][lz <= 3]  = H2t_y H2t_x                                 (z operator d2, x (l_z/2)^2),
+// Qy[ky][lz <= 2]  = H2_y H2_x v.  The z-pass combines the previous layer (pA, pB, pC,
+// side s = 0) with this one (side s = 1) and stores tau S Q and S R of the cell.
+template <int KH, typename T>
+__device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* xv1, int kx, bool emit,
+                             T (&pA)[16], T (&pB)[12], T (&pC)[9], T* zc, T l2x, T l2y, T l2z,
+                             const T (&sz)[3], T tau)
+{
+    T curA[9], curB[12], curC[9];
+#pragma unroll
+    for (int lz = 0; lz < 4; ++lz) {
+        T Eh[4], Oh[4];
+#pragma unroll
+        for (int ly = 0; ly < 4; ++ly) {
+            const T a0 = xu0[(10 + kx) * 16 + ly + 4 * lz], a1 = xu1[(10 + kx) * 16 + ly + 4 * lz];
+            Eh[ly] = a0 + a1;
+            Oh[ly] = a0 - a1;
+        }
+        if (lz < 3) {
+            T Ed[3], Od[3], Eq[3], Oq[3];
+#pragma unroll
+            for (int ly = 0; ly < 3; ++ly) {
+                const T d0 = xu0[(4 + kx) * 16 + ly + 4 * lz], d1 = xu1[(4 + kx) * 16 + ly + 4 * lz];
+                const T q0 = xv0[kx * 9 + ly + 3 * lz], q1 = xv1[kx * 9 + ly + 3 * lz];
+                Ed[ly] = d0 + d1;
+                Od[ly] = d0 - d1;
+                Eq[ly] = q0 + q1;
+                Oq[ly] = q0 - q1;
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int ky = KH + j;
+                const T ax_ = sym<3>(opH2, ky, ky, Ed, Od);
+                const T ay_ = sym<4>(opD2, ky, ky + 2, Eh, Oh);
+                curA[j + 3 * lz] = l2x * ax_ + l2y * ay_;
+                curC[j + 3 * lz] = sym<3>(opH2, ky, ky, Eq, Oq);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) curB[j + 3 * lz] = sym<3>(opH2, KH + j, KH + j, Eh, Oh);
+    }
+    if (emit) {
+        const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int ky = KH + j;
+            const T syk = (ky / 2 == 0) ? T(1) : ((ky / 2 == 1) ? l2y : l2y * l2y);
+            T EA[3], OA[3], EC[3], OC[3], EB[4], OB[4];
+#pragma unroll
+            for (int lz = 0; lz < 3; ++lz) {
+                EA[lz] = pA[j + 3 * lz] + curA[j + 3 * lz];
+                OA[lz] = pA[j + 3 * lz] - curA[j + 3 * lz];
+                EC[lz] = pC[j + 3 * lz] + curC[j + 3 * lz];
+                OC[lz] = pC[j + 3 * lz] - curC[j + 3 * lz];
+            }
+#pragma unroll
+            for (int lz = 0; lz < 4; ++lz) {
+                EB[lz] = pB[j + 3 * lz] + curB[j + 3 * lz];
+                OB[lz] = pB[j + 3 * lz] - curB[j + 3 * lz];
+            }
+#pragma unroll
+            for (int kz = 0; kz < 6; ++kz) {
+                const T acc = sym<3>(opH2, kz, kz, EA, OA);
+                const T accq = sym<3>(opH2, kz, kz, EC, OC);
+                const T accz = sym<4>(opD2, kz, kz + 2, EB, OB);
+                const T sc = skx * syk * sz[kz / 2];
+                const int k = kx + 6 * ky + 36 * kz;
+                zc[k] = accq * (tau * sc);
+                zc[216 + k] = (acc + l2z * accz) * sc;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        pA[i] = curA[i];
+        pC[i] = curC[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) pB[i] = curB[i];
 }
 
 template <typename T, int TY>
 __global__ void __launch_bounds__(16 * TX * TY)
-k_tiled3d_m3(TiledArgs a, int tz)
+k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
 {
     using S = Shared<T, TY>;
+    using MF = Mfma<T>;
     constexpr int NT = 16 * TX * TY;
+    constexpr int NW = NT / 64;
     constexpr int NC = S::NC, NXL = S::NXL, NNODE = S::NNODE, NEDGE = S::NEDGE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     S& sh = *reinterpret_cast<S*>(smem_raw);
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 
     const int tiles_x = (a.ext_to[0] + TX - 1) / TX;
     const int x0 = (blockIdx.x % tiles_x) * TX;
@@ -207,257 +276,235 @@ k_tiled3d_m3(TiledArgs a, int tz)
     const int off = (a.to_grid == 1) ? 0 : -1; // input node of corner s = cell + off + s
 
     const T l2x = T(a.lam2[0]), l2y = T(a.lam2[1]), l2z = T(a.lam2[2]);
-    const T sy[3] = {T(1), l2y, l2y * l2y}, sz[3] = {T(1), l2z, l2z * l2z};
-    const T inv[3] = {T(1.0 / a.lam2[0]), T(1.0 / a.lam2[1]), T(1.0 / a.lam2[2])};
+    const T sz[3] = {T(1), l2z, l2z * l2z};
+    const T invx = T(1.0 / a.lam2[0]), invy = T(1.0 / a.lam2[1]), invz = T(1.0 / a.lam2[2]);
     const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
     const T* __restrict__ gu = (const T*)a.u_in;
     const T* __restrict__ gv = (const T*)a.v_in;
 
-    // ---- stage 1: one node layer (global -> LDS), ghosts mirrored with signs ----
+    // the padding slot of every cell block reads as zero in the class products
+    for (int c = tid; c < NC; c += NT) sh.z[c * ZS + 432] = T(0);
+    const T xa0 = tabs->xa[0][lane], xa1 = tabs->xa[1][lane];
+
+    // ---- 1. node layers: fetched into registers one layer ahead, then stashed in
+    //         LDS; ghosts mirrored with signs ----
     const long long plane = (long long)a.ext_from[0] * a.ext_from[1];
-    auto load_layer = [&](int layer_gz) {
+    constexpr int NUC = (NNODE * 16 + NT - 1) / NT; // u chunks (4 coefficients) per thread
+    constexpr int NVE = (NNODE * 27 + NT - 1) / NT; // v coefficients per thread
+    T ru[NUC][4], rv[NVE];
+    // per-thread load slots: the xy part of the source node and the ghost signs are
+    // fixed for the column; only the layer (z) changes
+    int us_off[NUC], us_msk[NUC], vs_off[NVE], vs_msk[NVE];
+#pragma unroll
+    for (int i = 0; i < NUC; ++i) {
+        const int e = tid + i * NT;
+        us_off[i] = 0;
+        us_msk[i] = 0;
+        if (e >= NNODE * 16) continue;
+        const int node = e >> 4, qq = e & 15;
+        const Map1 mx = map_node(x0 + off + node % NXL, a.ext_from[0], a.bc[0]);
+        const Map1 my = map_node(y0 + off + node / NXL, a.ext_from[1], a.bc[1]);
+        us_off[i] = mx.j + a.ext_from[0] * my.j;
+        int m = 1;
+#pragma unroll
+        for (int lx = 0; lx < 4; ++lx)
+            if (mx.ghost && flips(a.bc[0], lx)) m |= 2 << lx;
+        if (my.ghost && flips(a.bc[1], qq & 3)) m |= 32;
+        us_msk[i] = m;
+    }
+#pragma unroll
+    for (int i = 0; i < NVE; ++i) {
+        const int e = tid + i * NT;
+        vs_off[i] = 0;
+        vs_msk[i] = 0;
+        if (e >= NNODE * 27) continue;
+        const int node = e / 27, cc = e % 27;
+        const Map1 mx = map_node(x0 + off + node % NXL, a.ext_from[0], a.bc[0]);
+        const Map1 my = map_node(y0 + off + node / NXL, a.ext_from[1], a.bc[1]);
+        vs_off[i] = mx.j + a.ext_from[0] * my.j;
+        bool neg = false;
+        if (mx.ghost && flips(a.bc[0], cc % 3)) neg = !neg;
+        if (my.ghost && flips(a.bc[1], (cc / 3) % 3)) neg = !neg;
+        vs_msk[i] = 1 | (neg ? 2 : 0);
+    }
+    auto fetch = [&](int layer_gz) {
         const Map1 mz = map_node(layer_gz, a.ext_from[2], a.bc[2]);
-        for (int e = tid; e < NNODE * 91; e += NT) {
-            const int node = e / 91, c = e % 91;
-            const int na = node % NXL, nb = node / NXL;
-            const Map1 mx = map_node(x0 + off + na, a.ext_from[0], a.bc[0]);
-            const Map1 my = map_node(y0 + off + nb, a.ext_from[1], a.bc[1]);
-            const long long gnode = (long long)mx.j + (long long)a.ext_from[0] * my.j + plane * mz.j;
-            const bool isv = c >= 64;
-            const int cc = isv ? c - 64 : c;
-            const int M = isv ? 3 : 4;
-            const int lx = cc % M, ly = (cc / M) % M, lz = cc / (M * M);
-            bool neg = false;
-            if (mx.ghost && flips(a.bc[0], lx)) neg = !neg;
-            if (my.ghost && flips(a.bc[1], ly)) neg = !neg;
-            if (mz.ghost && flips(a.bc[2], lz)) neg = !neg;
-            const T val = isv ? gv[gnode * 27 + cc] : gu[gnode * 64 + cc];
-            if (isv) sh.nv[node][cc] = neg ? -val : val;
-            else sh.nu[node][cc] = neg ? -val : val;
+        const long long zoff = plane * mz.j;
+#pragma unroll
+        for (int i = 0; i < NUC; ++i) {
+            if (!(us_msk[i] & 1)) continue;
+            const int qq = (tid + i * NT) & 15;
+            const bool zneg = mz.ghost && flips(a.bc[2], qq >> 2);
+            const bool yz = ((us_msk[i] & 32) != 0) != zneg;
+            const T* src = gu + (zoff + us_off[i]) * 64 + 4 * qq;
+#pragma unroll
+            for (int lx = 0; lx < 4; ++lx) {
+                const bool ng = yz != ((us_msk[i] >> (lx + 1)) & 1);
+                const T val = src[lx];
+                ru[i][lx] = ng ? -val : val;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NVE; ++i) {
+            if (!(vs_msk[i] & 1)) continue;
+            const int cc = (tid + i * NT) % 27;
+            const bool ng = ((vs_msk[i] & 2) != 0) != (mz.ghost && flips(a.bc[2], cc / 9));
+            const T val = gv[(zoff + vs_off[i]) * 27 + cc];
+            rv[i] = ng ? -val : val;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < NUC; ++i) {
+            const int e = tid + i * NT;
+            if (e >= NNODE * 16) break;
+            T* dst = sh.nu + (e >> 4) * NUP + 4 * (e & 15);
+#pragma unroll
+            for (int lx = 0; lx < 4; ++lx) dst[lx] = ru[i][lx];
+        }
+#pragma unroll
+        for (int i = 0; i < NVE; ++i) {
+            const int e = tid + i * NT;
+            if (e >= NNODE * 27) break;
+            sh.nv[(e / 27) * NVP + e % 27] = rv[i];
         }
     };
 
-    // ---- stage-3 task of this thread: [p0: 4 kx | R: 6 kx | Q: 6 kx] x NC cells ----
+    // ---- stage-3 task: [R and Q: 6 kx x 2 ky halves | p0: 4 kx] x NC cells ----
     const int t3 = tid / NC, cell3 = tid % NC;
-    const int kind = t3 < 4 ? 0 : (t3 < 10 ? 1 : 2);
-    const int kx = kind == 0 ? t3 : (kind == 1 ? t3 - 4 : t3 - 10);
+    const bool is_p0 = t3 >= 12;
+    // t3 = 6 * half + kx: the two halves of the k_y range sit in different waves
+    const int kx = is_p0 ? t3 - 12 : t3 % 6;
+    const bool hi = !is_p0 && t3 >= 6; // upper half of the k_y range (3..5)
     const int ccx = cell3 % TX, ccy = cell3 / TX;
     const int e0 = ccx + TX * ccy, e1 = ccx + TX * (ccy + 1); // x-edges below / above in y
-    // previous layer's y-pass results (registers)
-    T pA[24], pB[24];
+    T pA[16], pB[12], pC[9];                                   // previous layer's y-results
 
     const int nlayers = cz1 - cz0 + 1;
+    fetch(cz0 + off);
     for (int step = 0; step < nlayers; ++step) {
-        load_layer(cz0 + off + step);
+        stash();
         __syncthreads();
+        if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
-        // ---- 2. x-pass ----
-        for (int task = tid; task < NEDGE * 25; task += NT) {
-            if (task < NEDGE * 16) {
-                const int e = task / 16, line = task % 16;
-                const int cx = e % TX, b = e / TX;
-                const int n0 = cx + NXL * b;
-                const int ly = line % 4, lz = line / 4;
-                T in[8];
+        // ---- 2. x-pass: u on the matrix cores (one edge per wave), v on the VALU ----
+        for (int e = wave; e < NEDGE; e += NW) {
+            const int cx = e % TX, b = e / TX;
+            const int n0 = cx + NXL * b;
+            // B[k][j] = input (s, l_x = k) of line j = l_y + 4 l_z: nu[node][l_x + 4 j]
+            const T b0 = sh.nu[n0 * NUP + (lane >> 4) + 4 * (lane & 15)];
+            const T b1 = sh.nu[(n0 + 1) * NUP + (lane >> 4) + 4 * (lane & 15)];
+            typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+            acc = MF::mac(xa0, b0, acc);
+            acc = MF::mac(xa1, b1, acc);
+            T* dst = sh.xu + e * XUE + (lane & 15);
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
+            for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * 16] = acc[r];
+        }
+        for (int task = tid; task < NEDGE * 9; task += NT) {
+            const int e = task % NEDGE, line = task / NEDGE;
+            const int cx = e % TX, b = e / TX;
+            const int n0 = cx + NXL * b;
+            const int ly = line % 3, lz = line / 3;
+            T E[3], O[3];
 #pragma unroll
-                    for (int l = 0; l < 4; ++l) in[s * 4 + l] = sh.nu[n0 + s][l + 4 * ly + 16 * lz];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (opX(r, c) != 0.0) acc += T(opX(r, c)) * in[c];
-                    sh.xu[e][r][line] = acc;
-                }
-            } else {
-                const int tv = task - NEDGE * 16;
-                const int e = tv / 9, line = tv % 9;
-                const int cx = e % TX, b = e / TX;
-                const int n0 = cx + NXL * b;
-                const int ly = line % 3, lz = line / 3;
-                T in[6];
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) in[s * 3 + l] = sh.nv[n0 + s][l + 3 * ly + 9 * lz];
-#pragma unroll
-                for (int r = 0; r < 6; ++r) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        if (opH2(r, c) != 0.0) acc += T(opH2(r, c)) * in[c];
-                    sh.xv[e][r][line] = acc;
-                }
+            for (int l = 0; l < 3; ++l) {
+                const T a0 = sh.nv[n0 * NVP + l + 3 * ly + 9 * lz];
+                const T a1 = sh.nv[(n0 + 1) * NVP + l + 3 * ly + 9 * lz];
+                E[l] = a0 + a1;
+                O[l] = a0 - a1;
             }
+            T* dst = sh.xv + e * XVE + line;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) dst[r * 9] = sym<3>(opH2, r, r, E, O);
         }
         __syncthreads();
 
         // ---- 3. y-pass of this layer, z-pass with the previous one ----
         const bool emit = step > 0;
-        const int cz = cz0 + step - 1; // cell layer produced in this step
-        if (kind == 0) {
+        const T* xu0 = sh.xu + e0 * XUE;
+        const T* xu1 = sh.xu + e1 * XUE;
+        if (is_p0) {
             // p0: Y[ky][lz] = sum_{s,ly} H3[ky][s,ly] xu[e_s][kx][ly + 4 lz]
             T cur[16];
 #pragma unroll
             for (int lz = 0; lz < 4; ++lz) {
-                T in[8];
+                T E[4], O[4];
 #pragma unroll
                 for (int ly = 0; ly < 4; ++ly) {
-                    in[ly] = sh.xu[e0][kx][ly + 4 * lz];
-                    in[4 + ly] = sh.xu[e1][kx][ly + 4 * lz];
+                    const T a0 = xu0[kx * 16 + ly + 4 * lz], a1 = xu1[kx * 16 + ly + 4 * lz];
+                    E[ly] = a0 + a1;
+                    O[ly] = a0 - a1;
                 }
 #pragma unroll
-                for (int ky = 0; ky < 4; ++ky) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (opH3(ky, c) != 0.0) acc += T(opH3(ky, c)) * in[c];
-                    cur[ky + 4 * lz] = acc;
-                }
+                for (int ky = 0; ky < 4; ++ky) cur[ky + 4 * lz] = sym<4>(opH3, ky, ky, E, O);
             }
             if (emit) {
 #pragma unroll
-                for (int ky = 0; ky < 4; ++ky)
+                for (int ky = 0; ky < 4; ++ky) {
+                    T E[4], O[4];
 #pragma unroll
-                    for (int kz = 0; kz < 4; ++kz) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int lz = 0; lz < 4; ++lz) {
-                            if (opH3(kz, lz) != 0.0) acc += T(opH3(kz, lz)) * pA[ky + 4 * lz];
-                            if (opH3(kz, 4 + lz) != 0.0) acc += T(opH3(kz, 4 + lz)) * cur[ky + 4 * lz];
-                        }
-                        sh.p0[cell3][kx + 4 * ky + 16 * kz] = acc;
+                    for (int lz = 0; lz < 4; ++lz) {
+                        E[lz] = pA[ky + 4 * lz] + cur[ky + 4 * lz];
+                        O[lz] = pA[ky + 4 * lz] - cur[ky + 4 * lz];
                     }
+#pragma unroll
+                    for (int kz = 0; kz < 4; ++kz)
+                        sh.p0[cell3 * P0S + kx + 4 * ky + 16 * kz] = sym<4>(opH3, kz, kz, E, O);
+                }
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) pA[i] = cur[i];
-        } else if (kind == 1) {
-            // R: Rxy[ky][lz<=2] (x and y terms, z op H_2), Rz[ky][lz<=3] (z term, z op d2)
-            T curA[18], curB[24];
-#pragma unroll
-            for (int lz = 0; lz < 4; ++lz) {
-                T d2x[6], h2x[8];
-#pragma unroll
-                for (int ly = 0; ly < 4; ++ly) {
-                    h2x[ly] = sh.xu[e0][10 + kx][ly + 4 * lz];
-                    h2x[4 + ly] = sh.xu[e1][10 + kx][ly + 4 * lz];
-                }
-                if (lz < 3) {
-#pragma unroll
-                    for (int ly = 0; ly < 3; ++ly) {
-                        d2x[ly] = sh.xu[e0][4 + kx][ly + 4 * lz];
-                        d2x[3 + ly] = sh.xu[e1][4 + kx][ly + 4 * lz];
-                    }
-#pragma unroll
-                    for (int ky = 0; ky < 6; ++ky) {
-                        T ax_ = T(0), ay_ = T(0);
-#pragma unroll
-                        for (int c = 0; c < 6; ++c)
-                            if (opH2(ky, c) != 0.0) ax_ += T(opH2(ky, c)) * d2x[c];
-#pragma unroll
-                        for (int c = 0; c < 8; ++c)
-                            if (opD2(ky, c) != 0.0) ay_ += T(opD2(ky, c)) * h2x[c];
-                        curA[ky + 6 * lz] = l2x * ax_ + l2y * ay_;
-                    }
-                }
-#pragma unroll
-                for (int ky = 0; ky < 6; ++ky) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (opH2t(ky, c) != 0.0) acc += T(opH2t(ky, c)) * h2x[c];
-                    curB[ky + 6 * lz] = acc;
-                }
-            }
-            if (emit) {
-                const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
-#pragma unroll
-                for (int ky = 0; ky < 6; ++ky)
-#pragma unroll
-                    for (int kz = 0; kz < 6; ++kz) {
-                        T acc = T(0), accz = T(0);
-#pragma unroll
-                        for (int lz = 0; lz < 3; ++lz) {
-                            if (opH2(kz, lz) != 0.0) acc += T(opH2(kz, lz)) * pA[ky + 6 * lz];
-                            if (opH2(kz, 3 + lz) != 0.0) acc += T(opH2(kz, 3 + lz)) * curA[ky + 6 * lz];
-                        }
-#pragma unroll
-                        for (int lz = 0; lz < 4; ++lz) {
-                            if (opD2(kz, lz) != 0.0) accz += T(opD2(kz, lz)) * pB[ky + 6 * lz];
-                            if (opD2(kz, 4 + lz) != 0.0) accz += T(opD2(kz, 4 + lz)) * curB[ky + 6 * lz];
-                        }
-                        sh.r[cell3][kx + 6 * ky + 36 * kz] =
-                            (acc + l2z * accz) * (skx * sy[ky / 2] * sz[kz / 2]);
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < 18; ++i) pA[i] = curA[i];
-#pragma unroll
-            for (int i = 0; i < 24; ++i) pB[i] = curB[i];
+        } else if (!hi) {
+            yz_rq<0>(xu0, xu1, sh.xv + e0 * XVE, sh.xv + e1 * XVE, kx, emit, pA, pB, pC,
+                     sh.z + cell3 * ZS, l2x, l2y, l2z, sz, tau);
         } else {
-            // Q: Qy[ky][lz<=2] = sum_{s,ly} H2[ky][s,ly] xv[e_s][kx][ly + 3 lz]
-            T cur[18];
-#pragma unroll
-            for (int lz = 0; lz < 3; ++lz) {
-                T in[6];
-#pragma unroll
-                for (int ly = 0; ly < 3; ++ly) {
-                    in[ly] = sh.xv[e0][kx][ly + 3 * lz];
-                    in[3 + ly] = sh.xv[e1][kx][ly + 3 * lz];
-                }
-#pragma unroll
-                for (int ky = 0; ky < 6; ++ky) {
-                    T acc = T(0);
-#pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        if (opH2(ky, c) != 0.0) acc += T(opH2(ky, c)) * in[c];
-                    cur[ky + 6 * lz] = acc;
-                }
-            }
-            if (emit) {
-                const T skx = tau * (kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x));
-#pragma unroll
-                for (int ky = 0; ky < 6; ++ky)
-#pragma unroll
-                    for (int kz = 0; kz < 6; ++kz) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int lz = 0; lz < 3; ++lz) {
-                            if (opH2(kz, lz) != 0.0) acc += T(opH2(kz, lz)) * pA[ky + 6 * lz];
-                            if (opH2(kz, 3 + lz) != 0.0) acc += T(opH2(kz, 3 + lz)) * cur[ky + 6 * lz];
-                        }
-                        sh.q[cell3][kx + 6 * ky + 36 * kz] = acc * (skx * sy[ky / 2] * sz[kz / 2]);
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < 18; ++i) pA[i] = cur[i];
+            yz_rq<3>(xu0, xu1, sh.xv + e0 * XVE, sh.xv + e1 * XVE, kx, emit, pA, pB, pC,
+                     sh.z + cell3 * ZS, l2x, l2y, l2z, sz, tau);
         }
         if (!emit) continue; // the first layer only primes the registers
         __syncthreads();
 
-        // ---- 4. time sums: task (class p, u or v) x NC cells; outputs staged in xu ----
-        T* ou_base = &sh.xu[0][0][0];
-        T* ov_base = ou_base + NC * 64;
-        for (int task = tid; task < 16 * NC; task += NT) {
-            const int cl = task / NC, c = task % NC;
-            const int p = cl % 8, uv = cl / 8;
-            timesum_class<T>(p, uv, sh.q[c], sh.r[c], sh.p0[c], ou_base + c * 64, ov_base + c * 27,
-                             inv, inv_tau);
+        // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product ----
+        T* ou_base = sh.xu;
+        T* ov_base = ou_base + NC * OUS;
+        for (int task = wave; task < 8 * (NC / 16); task += NW) {
+            const int p = task % 8, g = task / 8;
+            const int cell = 16 * g + (lane & 15);
+            const T* zc = sh.z + cell * ZS;
+            typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ks = 0; ks < TS_KSTEPS; ++ks) {
+                const T av = tabs->ta[p][ks][lane];
+                const T bv = zc[tabs->tk[p][4 * ks + (lane >> 4)]];
+                acc = MF::mac(av, bv, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int info = tabs->tr[p][MF::row(lane, r)];
+                if (info < 0) continue;
+                const int ai = info & 0xff;
+                T sc = (info & 0x1000) ? inv_tau : T(1);
+                if (info & 0x100) sc *= invx;
+                if (info & 0x200) sc *= invy;
+                if (info & 0x400) sc *= invz;
+                if (info & 0x1000) ov_base[cell * 27 + ai] = sc * acc[r];
+                else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + sc * acc[r];
+            }
         }
         __syncthreads();
 
-        // ---- 5. store the cell layer cz ----
+        // ---- 5. store the cell layer cz (row by row of the tile, coalesced) ----
         {
+            const int cz = cz0 + step - 1;
             T* __restrict__ out_u = (T*)a.u_out;
             T* __restrict__ out_v = (T*)a.v_out;
             for (int i = tid; i < NC * 91; i += NT) {
                 int c, coef;
                 bool isv;
                 if (i < NC * 64) {
-                    c = i / 64;
-                    coef = i % 64;
+                    c = i >> 6;
+                    coef = i & 63;
                     isv = false;
                 } else {
                     c = (i - NC * 64) / 27;
@@ -468,26 +515,120 @@ k_tiled3d_m3(TiledArgs a, int tz)
                 if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
                 const long long g = gx + (long long)a.ext_to[0] * (gy + (long long)a.ext_to[1] * cz);
                 if (isv) out_v[g * 27 + coef] = ov_base[c * 27 + coef];
-                else out_u[g * 64 + coef] = ou_base[c * 64 + coef];
+                else out_u[g * 64 + coef] = ou_base[c * OUS + coef];
             }
         }
         __syncthreads();
     }
 }
 
+// ---------------------------------------------------------------------------
+// host: constant tables and launch
+// ---------------------------------------------------------------------------
+double weight(int ax, int ay, int az, int bx, int by, int bz)
+{
+    return kFact[bx + by + bz] / (kFact[bx] * kFact[by] * kFact[bz]) * kFact[ax + 2 * bx] /
+           kFact[ax] * kFact[ay + 2 * by] / kFact[ay] * kFact[az + 2 * bz] / kFact[az];
+}
+
+template <typename T>
+void build_tables(Tables<T>& t)
+{
+    std::memset(&t, 0, sizeof t);
+    for (int ks = 0; ks < 2; ++ks)
+        for (int l = 0; l < 64; ++l) t.xa[ks][l] = (T)opX(l % 16, 4 * ks + l / 16);
+    for (int p = 0; p < 8; ++p) {
+        const int px = p & 1, py = (p >> 1) & 1, pz = (p >> 2) & 1;
+        // rows: 8 u outputs, then the v outputs of the class
+        int ra[16][3], nrow = 0;
+        bool rv[16];
+        for (int o = 0; o < 8; ++o) {
+            ra[nrow][0] = px + 2 * (o & 1);
+            ra[nrow][1] = py + 2 * ((o >> 1) & 1);
+            ra[nrow][2] = pz + 2 * (o >> 2);
+            rv[nrow++] = false;
+        }
+        for (int az = pz; az <= 2; az += 2)
+            for (int ay = py; ay <= 2; ay += 2)
+                for (int ax = px; ax <= 2; ax += 2) {
+                    ra[nrow][0] = ax;
+                    ra[nrow][1] = ay;
+                    ra[nrow][2] = az;
+                    rv[nrow++] = true;
+                }
+        for (int row = 0; row < 16; ++row) {
+            if (row >= nrow) {
+                t.tr[p][row] = -1;
+                continue;
+            }
+            const int* al = ra[row];
+            const int flat = rv[row] ? al[0] + 3 * al[1] + 9 * al[2] : al[0] + 4 * al[1] + 16 * al[2];
+            int mask = 0;
+            for (int i = 0; i < 3; ++i)
+                if (al[i] >= 2) mask |= 1 << i;
+            t.tr[p][row] = (rv[row] ? 0x1000 : 0) | (mask << 8) | flat;
+        }
+        // inputs kk: 0..26 Q, 27..53 R, 54..55 padding (zero slot)
+        double W[16][TS_KSTEPS * 4] = {};
+        for (int kk = 0; kk < TS_KSTEPS * 4; ++kk) {
+            if (kk >= 54) {
+                t.tk[p][kk] = 432;
+                continue;
+            }
+            const bool isr = kk >= 27;
+            const int tt = kk % 27;
+            const int k[3] = {px + 2 * (tt % 3), py + 2 * ((tt / 3) % 3), pz + 2 * (tt / 9)};
+            t.tk[p][kk] = (isr ? 216 : 0) + k[0] + 6 * k[1] + 36 * k[2];
+            for (int row = 0; row < nrow; ++row) {
+                const int* al = ra[row];
+                if (k[0] < al[0] || k[1] < al[1] || k[2] < al[2]) continue;
+                const int bx = (k[0] - al[0]) / 2, by = (k[1] - al[1]) / 2, bz = (k[2] - al[2]) / 2;
+                const int j = bx + by + bz;
+                const double w = weight(al[0], al[1], al[2], bx, by, bz);
+                // u: Q/(2j+1)!, R/(2j+2)!;  v: Q/(2j)!, R/(2j+1)!
+                const int fq = rv[row] ? 2 * j : 2 * j + 1;
+                W[row][kk] = w / kFact[isr ? fq + 1 : fq];
+            }
+        }
+        for (int ks = 0; ks < TS_KSTEPS; ++ks)
+            for (int l = 0; l < 64; ++l) t.ta[p][ks][l] = (T)W[l % 16][4 * ks + l / 16];
+    }
+}
+
+template <typename T>
+const Tables<T>* device_tables(hipError_t* err)
+{
+    static std::mutex mu;
+    static Tables<T>* dev = nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    *err = hipSuccess;
+    if (dev) return dev;
+    Tables<T>* h = new Tables<T>();
+    build_tables(*h);
+    void* p = nullptr;
+    *err = hipMalloc(&p, sizeof(Tables<T>));
+    if (*err == hipSuccess) *err = hipMemcpy(p, h, sizeof(Tables<T>), hipMemcpyHostToDevice);
+    delete h;
+    if (*err != hipSuccess) return nullptr;
+    dev = (Tables<T>*)p;
+    return dev;
+}
+
 template <typename T, int TY>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
     constexpr int NT = 16 * TX * TY;
+    hipError_t e;
+    const Tables<T>* tabs = device_tables<T>(&e);
+    if (!tabs) return e;
     const size_t lds = sizeof(Shared<T, TY>);
     auto kern = k_tiled3d_m3<T, TY>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int tz = 64;
     const int tiles = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + TY - 1) / TY);
     const int chunks = (a.ext_to[2] + tz - 1) / tz;
-    hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz);
+    hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz, tabs);
     return hipGetLastError();
 }
 
@@ -496,6 +637,14 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
 bool hw_tiled_supported(int d, int m, int method, int precision)
 {
     return d == 3 && m == 3 && method == 0 && (precision == 0 || precision == 1);
+}
+
+hipError_t hw_tiled_prepare(int precision)
+{
+    hipError_t e;
+    if (precision == 0) device_tables<double>(&e);
+    else device_tables<float>(&e);
+    return e;
 }
 
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st)
