@@ -11,6 +11,7 @@ Prints ONE JSON line (rank 0, N = 1).  Only one GPU is used; --gpus N > 1 exits.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,6 +35,43 @@ FLOPS_PER_CELL = 48272
 BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 
 
+# HBM traffic of one launch of the dominant kernel (FP32 tiled half step on this
+# workload), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by the ratio of true to counted bytes of a plain copy of
+# known size measured in the same pass (the --copy-calibration leg).  The record is
+# tied to the source it was measured on: after any change of that file the traffic
+# is reported as null until the counters are taken again.
+TRAFFIC_RECORD = None
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_tiled3d.hip")
+COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy (1 GiB read + 1 GiB written)
+
+
+def source_digest(path=TRAFFIC_SOURCE):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes():
+    rec = TRAFFIC_RECORD
+    if not rec or rec.get("source_sha256") != source_digest():
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def copy_calibration(torch):
+    """A plain elementwise copy of COPY_ELEMS float32 values (reads 4 B and writes 4 B
+    per element): the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of a profiling pass."""
+    a = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -49,8 +87,10 @@ def parse():
     ap.add_argument("--kernel", choices=["auto", "generic", "tiled"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--cpu-layers", type=int, default=8,
+    ap.add_argument("--cpu-layers", type=int, default=40,
                     help="z-layers of the grid in the oracle's timed sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the plain copy used to scale HBM byte counters")
     return ap.parse_args()
 
 
@@ -153,6 +193,9 @@ def main():
     from paper_1802_05246_amd import workloads as W
 
     B.lib()
+    if args.copy_calibration:
+        log("[bench] copy calibration")
+        copy_calibration(torch)
     kernel = {"auto": B.HW_KERNEL_AUTO, "generic": B.HW_KERNEL_GENERIC,
               "tiled": B.HW_KERNEL_TILED}[args.kernel]
     n = args.n
@@ -199,7 +242,7 @@ def main():
     ach_gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "mfma" if tiled else "alu", "achieved": round(ach_tflops, 2),
             "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
-            "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": None,
+            "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": traffic_bytes(),
             "kernel_avg_ms": round(avg_ms, 4), "hbm_algorithmic_gbs": round(ach_gbs, 1),
             "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
 

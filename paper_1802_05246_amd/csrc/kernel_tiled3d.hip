@@ -285,6 +285,21 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     // the padding slot of every cell block reads as zero in the class products
     for (int c = tid; c < NC; c += NT) sh.z[c * ZS + 432] = T(0);
     const T xa0 = tabs->xa[0][lane], xa1 = tabs->xa[1][lane];
+    // with a multiple of 8 waves every wave keeps one parity class for the whole run
+    // and holds that class's operands in registers (no table loads in the loop)
+    constexpr bool kFixedClass = (NW % 8) == 0;
+    T tav[kFixedClass ? TS_KSTEPS : 1];
+    int tkv[kFixedClass ? TS_KSTEPS : 1], trv[kFixedClass ? 4 : 1];
+    if constexpr (kFixedClass) {
+        const int p = wave % 8;
+#pragma unroll
+        for (int ks = 0; ks < TS_KSTEPS; ++ks) {
+            tav[ks] = tabs->ta[p][ks][lane];
+            tkv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) trv[r] = tabs->tr[p][MF::row(lane, r)];
+    }
 
     // ---- 1. node layers: fetched into registers one layer ahead, then stashed in
     //         LDS; ghosts mirrored with signs ----
@@ -327,30 +342,27 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         if (my.ghost && flips(a.bc[1], (cc / 3) % 3)) neg = !neg;
         vs_msk[i] = 1 | (neg ? 2 : 0);
     }
+    // fetch() only issues the loads (every slot loads, idle slots from node 0) and
+    // records the z-ghost state of the layer; the signs are applied in stash(), so
+    // the loads stay in flight while the previous layer is being processed.
+    int zghost = 0;
     auto fetch = [&](int layer_gz) {
         const Map1 mz = map_node(layer_gz, a.ext_from[2], a.bc[2]);
         const long long zoff = plane * mz.j;
+        zghost = mz.ghost;
 #pragma unroll
         for (int i = 0; i < NUC; ++i) {
-            if (!(us_msk[i] & 1)) continue;
             const int qq = (tid + i * NT) & 15;
-            const bool zneg = mz.ghost && flips(a.bc[2], qq >> 2);
-            const bool yz = ((us_msk[i] & 32) != 0) != zneg;
-            const T* src = gu + (zoff + us_off[i]) * 64 + 4 * qq;
+            const long long node = (us_msk[i] & 1) ? zoff + us_off[i] : 0;
+            const T* src = gu + node * 64 + 4 * qq;
 #pragma unroll
-            for (int lx = 0; lx < 4; ++lx) {
-                const bool ng = yz != ((us_msk[i] >> (lx + 1)) & 1);
-                const T val = src[lx];
-                ru[i][lx] = ng ? -val : val;
-            }
+            for (int lx = 0; lx < 4; ++lx) ru[i][lx] = src[lx];
         }
 #pragma unroll
         for (int i = 0; i < NVE; ++i) {
-            if (!(vs_msk[i] & 1)) continue;
             const int cc = (tid + i * NT) % 27;
-            const bool ng = ((vs_msk[i] & 2) != 0) != (mz.ghost && flips(a.bc[2], cc / 9));
-            const T val = gv[(zoff + vs_off[i]) * 27 + cc];
-            rv[i] = ng ? -val : val;
+            const long long node = (vs_msk[i] & 1) ? zoff + vs_off[i] : 0;
+            rv[i] = gv[node * 27 + cc];
         }
     };
     auto stash = [&]() {
@@ -358,15 +370,23 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         for (int i = 0; i < NUC; ++i) {
             const int e = tid + i * NT;
             if (e >= NNODE * 16) break;
-            T* dst = sh.nu + (e >> 4) * NUP + 4 * (e & 15);
+            const int qq = e & 15;
+            const bool zneg = zghost && flips(a.bc[2], qq >> 2);
+            const bool yz = ((us_msk[i] & 32) != 0) != zneg;
+            T* dst = sh.nu + (e >> 4) * NUP + 4 * qq;
 #pragma unroll
-            for (int lx = 0; lx < 4; ++lx) dst[lx] = ru[i][lx];
+            for (int lx = 0; lx < 4; ++lx) {
+                const bool ng = yz != ((us_msk[i] >> (lx + 1)) & 1);
+                dst[lx] = ng ? -ru[i][lx] : ru[i][lx];
+            }
         }
 #pragma unroll
         for (int i = 0; i < NVE; ++i) {
             const int e = tid + i * NT;
             if (e >= NNODE * 27) break;
-            sh.nv[(e / 27) * NVP + e % 27] = rv[i];
+            const int cc = e % 27;
+            const bool ng = ((vs_msk[i] & 2) != 0) != (zghost && flips(a.bc[2], cc / 9));
+            sh.nv[(e / 27) * NVP + cc] = ng ? -rv[i] : rv[i];
         }
     };
 
@@ -475,13 +495,17 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             typename MF::vec acc = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int ks = 0; ks < TS_KSTEPS; ++ks) {
-                const T av = tabs->ta[p][ks][lane];
-                const T bv = zc[tabs->tk[p][4 * ks + (lane >> 4)]];
-                acc = MF::mac(av, bv, acc);
+                if constexpr (kFixedClass) {
+                    acc = MF::mac(tav[ks], zc[tkv[ks]], acc);
+                } else {
+                    const T av = tabs->ta[p][ks][lane];
+                    const T bv = zc[tabs->tk[p][4 * ks + (lane >> 4)]];
+                    acc = MF::mac(av, bv, acc);
+                }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int info = tabs->tr[p][MF::row(lane, r)];
+                const int info = kFixedClass ? trv[r] : tabs->tr[p][MF::row(lane, r)];
                 if (info < 0) continue;
                 const int ai = info & 0xff;
                 T sc = (info & 0x1000) ? inv_tau : T(1);
