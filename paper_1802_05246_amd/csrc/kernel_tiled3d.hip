@@ -69,7 +69,7 @@ constexpr int XUE = 257; // x-edge stride of the u x-pass results: [row][l_y + 4
 constexpr int XVE = 55;  // x-edge stride of the v x-pass results: [row][l_y + 3 l_z] + 1
 constexpr int P0S = 65;  // cell stride of p0: [kx + 4 ky + 16 kz]
 constexpr int ZS = 433;  // cell stride of [tau S Q (216) | S R (216) | 0]
-constexpr int OUS = 65;  // cell stride of the staged u outputs
+constexpr int OUS = 68;  // cell stride of the staged u outputs (16-byte rows for the stores)
 
 // time-sum blocks: 8 classes x 14 K-steps of 4 (54 inputs padded to 56)
 constexpr int TS_KSTEPS = 14;
@@ -82,11 +82,11 @@ struct Shared {
     static constexpr int NC = TX * TY;
     T nu[NNODE * NUP];
     T nv[NNODE * NVP];
-    T xu[NEDGE * XUE]; // reused for the staged outputs
+    T xu[NEDGE * XUE];
     T xv[NEDGE * XVE];
     T p0[NC * P0S];
     T z[NC * ZS];
-    static_assert(NC * (OUS + 27) <= NEDGE * XUE, "staged outputs must fit the x-pass region");
+    alignas(32) T out[NC * (OUS + 27)]; // staged outputs of a cell layer: u (stride OUS), then v (27)
     static_assert(NC % 16 == 0, "cells come in groups of 16 for the time-sum products");
 };
 
@@ -160,9 +160,8 @@ __device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) 
 // so row k needs only the left-node column and E or O by the parity of k + l; `parity`
 // is the derivative order k of the row (row + 2 for the second-derivative rows).
 template <int NL, typename T, typename Op>
-__device__ inline T sym(Op op, int row, int parity, const T* E, const T* O)
+__device__ inline T sym(Op op, int row, int parity, const T* E, const T* O, T acc = T(0))
 {
-    T acc = T(0);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         const double w = op(row, l);
@@ -172,15 +171,28 @@ __device__ inline T sym(Op op, int row, int parity, const T* E, const T* O)
 }
 
 // y- and z-passes of the R and Q paths for rows k_y = KH .. KH+2 of one (cell, k_x).
-// Rxy[ky][lz <= 2] = (l_x/2)^2 H2t_y d2_x + (l_y/2)^2 d2_y H2t_x  (z operator H_2),
-// Rz[ky][lz <= 3]  = H2t_y H2t_x                                 (z operator d2, x (l_z/2)^2),
-// Qy[ky][lz <= 2]  = H2_y H2_x v.  The z-pass combines the previous layer (pA, pB, pC,
-// side s = 0) with this one (side s = 1) and stores tau S Q and S R of the cell.
+// With f = S_x(k_x) S_y(k_y) (the x and y factors of the scaling S(k)):
+//   Ay[ky][lz <= 2] = f (l_x/2)^2 H2t_y d2_x + f (l_y/2)^2 d2_y H2t_x   (z operator H_2),
+//   By[ky][lz <= 3] = f (l_z/2)^2 H2t_y H2t_x                         (z operator d2),
+//   Cy[ky][lz <= 2] = f tau H2_y H2_x v.
+// The z-pass combines the previous layer (pA, pB, pC, side s = 0) with this one
+// (side s = 1) and stores tau S Q and S R of the cell (S_z(k_z) applied last).
 template <int KH, typename T>
 __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* xv1, int kx, bool emit,
                              T (&pA)[16], T (&pB)[12], T (&pC)[9], T* zc, T l2x, T l2y, T l2z,
                              const T (&sz)[3], T tau)
 {
+    const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
+    T fx[3], fy[3], fb[3], fc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int ky = KH + j;
+        const T f = (ky / 2 == 0) ? skx : ((ky / 2 == 1) ? skx * l2y : skx * (l2y * l2y));
+        fx[j] = f * l2x;
+        fy[j] = f * l2y;
+        fb[j] = f * l2z;
+        fc[j] = f * tau;
+    }
     T curA[9], curB[12], curC[9];
 #pragma unroll
     for (int lz = 0; lz < 4; ++lz) {
@@ -207,19 +219,17 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
                 const int ky = KH + j;
                 const T ax_ = sym<3>(opH2, ky, ky, Ed, Od);
                 const T ay_ = sym<4>(opD2, ky, ky + 2, Eh, Oh);
-                curA[j + 3 * lz] = l2x * ax_ + l2y * ay_;
-                curC[j + 3 * lz] = sym<3>(opH2, ky, ky, Eq, Oq);
+                curA[j + 3 * lz] = fx[j] * ax_ + fy[j] * ay_;
+                curC[j + 3 * lz] = fc[j] * sym<3>(opH2, ky, ky, Eq, Oq);
             }
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) curB[j + 3 * lz] = sym<3>(opH2, KH + j, KH + j, Eh, Oh);
+        for (int j = 0; j < 3; ++j) curB[j + 3 * lz] = fb[j] * sym<3>(opH2, KH + j, KH + j, Eh, Oh);
     }
     if (emit) {
-        const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int ky = KH + j;
-            const T syk = (ky / 2 == 0) ? T(1) : ((ky / 2 == 1) ? l2y : l2y * l2y);
             T EA[3], OA[3], EC[3], OC[3], EB[4], OB[4];
 #pragma unroll
             for (int lz = 0; lz < 3; ++lz) {
@@ -235,13 +245,11 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
             }
 #pragma unroll
             for (int kz = 0; kz < 6; ++kz) {
-                const T acc = sym<3>(opH2, kz, kz, EA, OA);
-                const T accq = sym<3>(opH2, kz, kz, EC, OC);
-                const T accz = sym<4>(opD2, kz, kz + 2, EB, OB);
-                const T sc = skx * syk * sz[kz / 2];
+                const T r = sym<4>(opD2, kz, kz + 2, EB, OB, sym<3>(opH2, kz, kz, EA, OA));
+                const T q = sym<3>(opH2, kz, kz, EC, OC);
                 const int k = kx + 6 * ky + 36 * kz;
-                zc[k] = accq * (tau * sc);
-                zc[216 + k] = (acc + l2z * accz) * sc;
+                zc[k] = kz < 2 ? q : q * sz[kz / 2];
+                zc[216 + k] = kz < 2 ? r : r * sz[kz / 2];
             }
         }
     }
@@ -263,7 +271,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     constexpr int NT = 16 * TX * TY;
     constexpr int NW = NT / 64;
     constexpr int NC = S::NC, NXL = S::NXL, NNODE = S::NNODE, NEDGE = S::NEDGE;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    extern __shared__ __align__(32) unsigned char smem_raw[];
     S& sh = *reinterpret_cast<S*>(smem_raw);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -277,8 +285,6 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
 
     const T l2x = T(a.lam2[0]), l2y = T(a.lam2[1]), l2z = T(a.lam2[2]);
     const T sz[3] = {T(1), l2z, l2z * l2z};
-    const T invx = T(1.0 / a.lam2[0]), invy = T(1.0 / a.lam2[1]), invz = T(1.0 / a.lam2[2]);
-    const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
     const T* __restrict__ gu = (const T*)a.u_in;
     const T* __restrict__ gv = (const T*)a.v_in;
 
@@ -288,8 +294,26 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     // with a multiple of 8 waves every wave keeps one parity class for the whole run
     // and holds that class's operands in registers (no table loads in the loop)
     constexpr bool kFixedClass = (NW % 8) == 0;
-    T tav[kFixedClass ? TS_KSTEPS : 1];
-    int tkv[kFixedClass ? TS_KSTEPS : 1], trv[kFixedClass ? 4 : 1];
+    const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
+    const T invx = T(1.0 / a.lam2[0]), invy = T(1.0 / a.lam2[1]), invz = T(1.0 / a.lam2[2]);
+    // output decode of table entry `info`: LDS offset in the staged outputs (u rows
+    // relative to the cell's u block, v rows offset by the v region) and scale 1/S(a),
+    // times 1/tau for v
+    auto decode = [&](int info, int& dst, T& sc) {
+        if (info < 0) {
+            dst = -1;
+            sc = T(0);
+            return;
+        }
+        const int ai = info & 0xff;
+        sc = (info & 0x1000) ? inv_tau : T(1);
+        if (info & 0x100) sc *= invx;
+        if (info & 0x200) sc *= invy;
+        if (info & 0x400) sc *= invz;
+        dst = (info & 0x1000) ? (1 << 16) | ai : ai;
+    };
+    T tav[kFixedClass ? TS_KSTEPS : 1], rsc[kFixedClass ? 4 : 1];
+    int tkv[kFixedClass ? TS_KSTEPS : 1], rdst[kFixedClass ? 4 : 1];
     if constexpr (kFixedClass) {
         const int p = wave % 8;
 #pragma unroll
@@ -298,7 +322,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             tkv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) trv[r] = tabs->tr[p][MF::row(lane, r)];
+        for (int r = 0; r < 4; ++r) decode(tabs->tr[p][MF::row(lane, r)], rdst[r], rsc[r]);
     }
 
     // ---- 1. node layers: fetched into registers one layer ahead, then stashed in
@@ -401,10 +425,59 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     T pA[16], pB[12], pC[9];                                   // previous layer's y-results
 
     const int nlayers = cz1 - cz0 + 1;
+    T* const ou_base = sh.out;
+    T* const ov_base = sh.out + NC * OUS;
+    // ---- 5. store a staged cell layer.  Full tiles: one group of 4 coefficients
+    //         per thread for u (NT = 16 NC groups); the v outputs of a tile row of
+    //         TX = 4 cells are contiguous in memory, TY rows x 27 groups.  Partial
+    //         tiles (and v rows whose pitch breaks the group alignment): one value per
+    //         thread and step ----
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    const bool full_x = x0 + TX <= a.ext_to[0];
+    const bool vec_v = full_x && (a.ext_to[0] % 4 == 0);
+    const long long plane_to = (long long)a.ext_to[0] * a.ext_to[1];
+    const int su_c = tid >> 4, su_q = tid & 15;
+    const bool su_ok = y0 + su_c / TX < a.ext_to[1];
+    const long long su_g = ((long long)(x0 + su_c % TX) + (long long)a.ext_to[0] * (y0 + su_c / TX)) * 64 + 4 * su_q;
+    const int sv_r = tid / 27, sv_q = tid % 27;
+    const bool sv_ok = tid < TY * 27 && y0 + sv_r < a.ext_to[1];
+    const long long sv_g = ((long long)x0 + (long long)a.ext_to[0] * (y0 + sv_r)) * 27 + 4 * sv_q;
+    auto store_layer = [&](int cz) {
+        T* __restrict__ out_u = (T*)a.u_out;
+        T* __restrict__ out_v = (T*)a.v_out;
+        if (full_x) {
+            if (su_ok)
+                *(vec4*)(out_u + cz * plane_to * 64 + su_g) = *(const vec4*)(ou_base + su_c * OUS + 4 * su_q);
+        } else {
+            for (int i = tid; i < NC * 64; i += NT) {
+                const int c = i >> 6, coef = i & 63;
+                const int gx = x0 + c % TX, gy = y0 + c / TX;
+                if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+                out_u[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 64 + coef] = ou_base[c * OUS + coef];
+            }
+        }
+        if (vec_v) {
+            if (sv_ok)
+                *(vec4*)(out_v + cz * plane_to * 27 + sv_g) = *(const vec4*)(ov_base + sv_r * (TX * 27) + 4 * sv_q);
+        } else {
+            for (int i = tid; i < NC * 27; i += NT) {
+                const int c = i / 27, coef = i % 27;
+                const int gx = x0 + c % TX, gy = y0 + c / TX;
+                if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+                out_v[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 27 + coef] = ov_base[c * 27 + coef];
+            }
+        }
+    };
+
+    // Per node layer: stash it, store the cell layer finished in the previous pass,
+    // issue the loads of the next node layer, then the x-, y/z- and time passes.  The
+    // stores go out before the loads, so the in-order memory counter that the next
+    // stash waits on covers stores issued a whole pass earlier.
     fetch(cz0 + off);
     for (int step = 0; step < nlayers; ++step) {
         stash();
         __syncthreads();
+        if (step >= 2) store_layer(cz0 + step - 2);
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
         // ---- 2. x-pass: u on the matrix cores (one edge per wave), v on the VALU ----
@@ -486,8 +559,6 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         __syncthreads();
 
         // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product ----
-        T* ou_base = sh.xu;
-        T* ov_base = ou_base + NC * OUS;
         for (int task = wave; task < 8 * (NC / 16); task += NW) {
             const int p = task % 8, g = task / 8;
             const int cell = 16 * g + (lane & 15);
@@ -505,44 +576,24 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int info = kFixedClass ? trv[r] : tabs->tr[p][MF::row(lane, r)];
-                if (info < 0) continue;
-                const int ai = info & 0xff;
-                T sc = (info & 0x1000) ? inv_tau : T(1);
-                if (info & 0x100) sc *= invx;
-                if (info & 0x200) sc *= invy;
-                if (info & 0x400) sc *= invz;
-                if (info & 0x1000) ov_base[cell * 27 + ai] = sc * acc[r];
+                int dst;
+                T sc;
+                if constexpr (kFixedClass) {
+                    dst = rdst[r];
+                    sc = rsc[r];
+                } else {
+                    decode(tabs->tr[p][MF::row(lane, r)], dst, sc);
+                }
+                if (dst < 0) continue;
+                const int ai = dst & 0xffff;
+                if (dst >> 16) ov_base[cell * 27 + ai] = sc * acc[r];
                 else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + sc * acc[r];
             }
         }
+    }
+    if (nlayers >= 2) {
         __syncthreads();
-
-        // ---- 5. store the cell layer cz (row by row of the tile, coalesced) ----
-        {
-            const int cz = cz0 + step - 1;
-            T* __restrict__ out_u = (T*)a.u_out;
-            T* __restrict__ out_v = (T*)a.v_out;
-            for (int i = tid; i < NC * 91; i += NT) {
-                int c, coef;
-                bool isv;
-                if (i < NC * 64) {
-                    c = i >> 6;
-                    coef = i & 63;
-                    isv = false;
-                } else {
-                    c = (i - NC * 64) / 27;
-                    coef = (i - NC * 64) % 27;
-                    isv = true;
-                }
-                const int gx = x0 + c % TX, gy = y0 + c / TX;
-                if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
-                const long long g = gx + (long long)a.ext_to[0] * (gy + (long long)a.ext_to[1] * cz);
-                if (isv) out_v[g * 27 + coef] = ov_base[c * 27 + coef];
-                else out_u[g * 64 + coef] = ou_base[c * OUS + coef];
-            }
-        }
-        __syncthreads();
+        store_layer(cz1 - 1);
     }
 }
 
