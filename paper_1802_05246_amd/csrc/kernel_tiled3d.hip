@@ -481,18 +481,32 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
         // ---- 2. x-pass: u on the matrix cores (one edge per wave), v on the VALU ----
-        for (int e = wave; e < NEDGE; e += NW) {
-            const int cx = e % TX, b = e / TX;
-            const int n0 = cx + NXL * b;
-            // B[k][j] = input (s, l_x = k) of line j = l_y + 4 l_z: nu[node][l_x + 4 j]
-            const T b0 = sh.nu[n0 * NUP + (lane >> 4) + 4 * (lane & 15)];
-            const T b1 = sh.nu[(n0 + 1) * NUP + (lane >> 4) + 4 * (lane & 15)];
-            typename MF::vec acc = {T(0), T(0), T(0), T(0)};
-            acc = MF::mac(xa0, b0, acc);
-            acc = MF::mac(xa1, b1, acc);
-            T* dst = sh.xu + e * XUE + (lane & 15);
+        {
+            // B[k][j] = input (s, l_x = k) of line j = l_y + 4 l_z: nu[node][l_x + 4 j];
+            // the operands of all of the wave's edges are read before the products
+            constexpr int EPW = (NEDGE + NW - 1) / NW;
+            T b0[EPW], b1[EPW];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * 16] = acc[r];
+            for (int i = 0; i < EPW; ++i) {
+                const int e = wave + i * NW;
+                if (e < NEDGE) {
+                    const int n0 = e % TX + NXL * (e / TX);
+                    b0[i] = sh.nu[n0 * NUP + (lane >> 4) + 4 * (lane & 15)];
+                    b1[i] = sh.nu[(n0 + 1) * NUP + (lane >> 4) + 4 * (lane & 15)];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < EPW; ++i) {
+                const int e = wave + i * NW;
+                if (e < NEDGE) {
+                    typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+                    acc = MF::mac(xa0, b0[i], acc);
+                    acc = MF::mac(xa1, b1[i], acc);
+                    T* dst = sh.xu + e * XUE + (lane & 15);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * 16] = acc[r];
+                }
+            }
         }
         for (int task = tid; task < NEDGE * 9; task += NT) {
             const int e = task % NEDGE, line = task / NEDGE;
@@ -564,15 +578,30 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             const int cell = 16 * g + (lane & 15);
             const T* zc = sh.z + cell * ZS;
             typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+            if constexpr (kFixedClass) {
+                // all B operands first: the products then run back to back instead of
+                // each waiting for its own LDS read
+                T bv[TS_KSTEPS];
 #pragma unroll
-            for (int ks = 0; ks < TS_KSTEPS; ++ks) {
-                if constexpr (kFixedClass) {
-                    acc = MF::mac(tav[ks], zc[tkv[ks]], acc);
-                } else {
-                    const T av = tabs->ta[p][ks][lane];
-                    const T bv = zc[tabs->tk[p][4 * ks + (lane >> 4)]];
-                    acc = MF::mac(av, bv, acc);
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[tkv[ks]];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(tav[ks], bv[ks], acc);
+            } else {
+                // the class's operands come from the (cached) constant tables: all of
+                // them are requested at once, so the task waits for memory only once
+                T av[TS_KSTEPS], bv[TS_KSTEPS];
+                int kv[TS_KSTEPS];
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) {
+                    kv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
+                    av[ks] = tabs->ta[p][ks][lane];
                 }
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[kv[ks]];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(av[ks], bv[ks], acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
