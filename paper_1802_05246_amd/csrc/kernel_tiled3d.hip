@@ -415,9 +415,14 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     };
 
     // ---- stage-3 task: [R and Q: 6 kx x 2 ky halves | p0: 4 kx] x NC cells ----
-    const int t3 = tid / NC, cell3 = tid % NC;
+    // task ids: 0..5 lower half of the k_y range (k_x = id), 6..11 upper half, 12..15 p0.
+    // A wave holds 64 / NC consecutive slots; the order keeps the two halves in different
+    // waves (with 4 slots per wave, the last two waves pair two half tasks with two p0
+    // tasks, the light path)
+    const int slot = tid / NC, cell3 = tid % NC;
+    constexpr int kOrder4[16] = {0, 1, 2, 3, 6, 7, 8, 9, 4, 5, 12, 13, 10, 11, 14, 15};
+    const int t3 = (64 / NC == 4) ? kOrder4[slot] : slot;
     const bool is_p0 = t3 >= 12;
-    // t3 = 6 * half + kx: the two halves of the k_y range sit in different waves
     const int kx = is_p0 ? t3 - 12 : t3 % 6;
     const bool hi = !is_p0 && t3 >= 6; // upper half of the k_y range (3..5)
     const int ccx = cell3 % TX, ccy = cell3 / TX;
