@@ -168,3 +168,23 @@ def poly_rel_err(spec, gu, ou, gv=None, ov=None):
         num += tau * tau * poly_norm2(np.asarray(gv) - np.asarray(ov), d, M - 1)
         den += tau * tau * poly_norm2(ov, d, M - 1)
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
+
+
+def oracle_growth_per_step(d, m, lam, method, taylor_stages=0, n=8, steps=300, block=10, seed=0):
+    """Growth per full step of the fluctuations (state minus its per-coefficient means
+    over the nodes) of random data with v = 0 on a periodic grid, oracle arithmetic.
+    The fluctuation norm is sampled every `block` steps; the growth compares the
+    largest sample of the last third of the run with the largest of the middle third."""
+    spec = W.make_spec(d, m, [n] * d, 0.0, 1.0, 1.0, cfl=lam, bc=W.PERIODIC, method=method,
+                       taylor_stages=taylor_stages)
+    p = oracle.make_problem(d, m, spec.n, spec.xl, spec.xr, 1.0, spec.dt, spec.bc, method,
+                            taylor_stages=taylor_stages)
+    u, v = W.random_state(spec, seed)
+    v[:] = 0.0
+    tau = 0.5 * spec.dt
+    norms = []
+    for _ in range(steps // block):
+        u, v = oracle.diss_advance(p, u, v, block)
+        norms.append(np.sqrt(((u - u.mean(0)) ** 2).sum() + tau * tau * ((v - v.mean(0)) ** 2).sum()))
+    k = len(norms) // 3
+    return (max(norms[2 * k:3 * k]) / max(norms[k:2 * k])) ** (1.0 / (k * block))

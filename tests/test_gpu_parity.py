@@ -85,6 +85,11 @@ CASES = [
     (3, 3, [5, 4, 6], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 0),
     (3, 3, [4, 3, 5], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], W.DISS_FULL, 0),
     (3, 2, [4, 4, 3], [W.PERIODIC, W.PERIODIC, W.DIRICHLET], W.DISS_SIMPLE, 0),
+    (3, 3, [5, 4, 3], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_SIMPLE, 0),
+    (3, 3, [4, 3, 4], [W.DIRICHLET, W.PERIODIC, W.NEUMANN], W.DISS_SIMPLE, 0),
+    (3, 3, [4, 5, 3], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 7),
+    (3, 3, [3, 4, 4], [W.PERIODIC, W.DIRICHLET, W.PERIODIC], W.DISS_FULL, 8),
+    (2, 3, [6, 5], [W.PERIODIC, W.PERIODIC], W.DISS_SIMPLE, 7),
     (1, 0, [8], [W.PERIODIC], W.CONSERVATIVE, 0),
     (1, 4, [9], [W.DIRICHLET], W.CONSERVATIVE, 0),
     (2, 4, [7, 6], [W.DIRICHLET, W.DIRICHLET], W.CONSERVATIVE, 0),

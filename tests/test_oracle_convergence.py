@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_1802_05246_amd import workloads as W
+from helpers import oracle_growth_per_step
 
 
 def _P(spec):
@@ -142,3 +143,20 @@ def test_stable_at_cfl_one(method, m, d, cfl):
             u, v = oracle.diss_advance(p, u, v, block)
             amps.append(np.abs(u).max())
     assert np.isfinite(amps).all() and max(amps[1:]) < 3 * amps[0], amps
+
+
+# ---- stability of the variants (Sec. 3.3, Sec. 6.1), measured on the oracle --------------
+def test_full_exact_series_m5_unstable_at_cfl_one():
+    """The modified-first-step variant with the exact series has a growing mode for
+    m = 5 at c dt = h (while m <= 3 decays)."""
+    assert oracle_growth_per_step(2, 5, 1.0, W.DISS_FULL) > 1.0 + 1e-3
+    assert oracle_growth_per_step(2, 3, 1.0, W.DISS_FULL) < 1.0 + 1e-4
+
+
+def test_simple_variant_truncated_series_unstable():
+    """Cutting the Taylor series of the straightforward variant after stage 2m+1
+    (2m+2 terms with s = 0) makes m = 3 unstable at lambda = 0.8; the exact series and
+    the cut after stage 2m+2 stay stable."""
+    assert oracle_growth_per_step(2, 3, 0.8, W.DISS_SIMPLE, taylor_stages=7, n=12) > 1.1
+    assert oracle_growth_per_step(2, 3, 0.8, W.DISS_SIMPLE, taylor_stages=8, n=12) < 1.0 + 1e-4
+    assert oracle_growth_per_step(2, 3, 0.8, W.DISS_SIMPLE, taylor_stages=0, n=12) < 1.0 + 1e-4
