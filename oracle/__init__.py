@@ -75,6 +75,8 @@ def lib():
         L.hwo_nodes.argtypes = [pp, ctypes.c_int]
         L.hwo_nodes.restype = ctypes.c_int64
         L.hwo_diss_half.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, ip, ctypes.c_int64, ctypes.c_int]
+        L.hwo_diss_half_forced.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp, dp, ip,
+                                           ctypes.c_int64, ctypes.c_int]
         L.hwo_cons_half.argtypes = [pp, ctypes.c_int, dp, dp, dp, ip, ctypes.c_int64, ctypes.c_int]
         L.hwo_cons_startup.argtypes = [pp, dp, dp, dp, ctypes.c_int]
         L.hwo_cons_energy.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int]
@@ -116,18 +118,28 @@ def _sel(sel):
     return s, s.size
 
 
-def diss_half(p: Problem, to_grid: int, u, v, sel=None, nthreads=0):
+def diss_half(p: Problem, to_grid: int, u, v, sel=None, nthreads=0, forcing=None):
     """One dissipative half step onto `to_grid` (Sec. 3.1.2, Sec. 3.3).  With `sel`
-    only those output nodes are computed (rows in the order given)."""
+    only those output nodes are computed (rows in the order given).  `forcing`, if
+    given, has shape (nodes of to_grid, R, (2m)^d): the scaled space-time Taylor
+    coefficients h^k/k! d^k d^r/dt^r f of the forcing at every output node and the
+    start of the half step, r < R (Sec. 3.1.2 eq. (recursion_diss_1d_2))."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)
     s, ns = _sel(sel)
     cnt = ns if s is not None else nodes(p, to_grid)
     uo = np.zeros((cnt, (p.m + 1) ** p.d))
     vo = np.zeros((cnt, p.m ** p.d))
-    rc = lib().hwo_diss_half(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(uo), _dp(vo),
-                             None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                             ns, nthreads)
+    selp = None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    if forcing is None:
+        rc = lib().hwo_diss_half(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(uo), _dp(vo),
+                                 selp, ns, nthreads)
+    else:
+        f = np.ascontiguousarray(forcing, dtype=np.float64)
+        if f.ndim != 3 or f.shape[0] != nodes(p, to_grid) or f.shape[2] != (2 * p.m) ** p.d:
+            raise ValueError(f"forcing must have shape (nodes, R, (2m)^d), got {f.shape}")
+        rc = lib().hwo_diss_half_forced(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(f), f.shape[1],
+                                        _dp(uo), _dp(vo), selp, ns, nthreads)
     if rc:
         raise ValueError(f"diss_half failed ({rc})")
     return uo, vo

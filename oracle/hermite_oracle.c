@@ -309,9 +309,13 @@ static void scratch_alloc(scratch_t *s, int d, int m)
     s->vacc = b + 10 * T;
 }
 
+/* fcell: forcing of this cell, n_orders blocks of (2m)^d scaled space-time Taylor       */
+/* coefficients phi[r][k] = h^k/k! d^k/dx^k d^r/dt^r f at the cell centre and the start  */
+/* of the half step (or NULL).  Stage s receives dt^s/s! phi[s-1] in V_s, eq.            */
+/* (recursion_diss_1d_2) of Sec. 3.1.2 applied in every dimension.                        */
 static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t *cr,
-                      const double *u_in, const double *v_in, double *u_out, double *v_out,
-                      scratch_t *s)
+                      const double *u_in, const double *v_in, const double *fcell, int n_orders,
+                      double *u_out, double *v_out, scratch_t *s)
 {
     const int d = p->d, m = p->m, M = m + 1, Mv = m, P = 2 * m + 2;
     const int T = pw(P, d);
@@ -341,10 +345,13 @@ static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t 
     }
 
     const int modified = (p->method == HWO_DISS_FULL && d >= 2);
-    const int s_limit = p->taylor_stages > 0 ? p->taylor_stages : d * (2 * m + 2) + 2;
-    double wgt = 1.0;
+    const int nf = fcell ? n_orders : 0;
+    const int s_limit = p->taylor_stages > 0 ? p->taylor_stages : d * (2 * m + 2) + 2 + nf;
+    const int Fv = pw(2 * m, d);
+    double wgt = 1.0, fac = 1.0;
     for (int st = 1; st <= s_limit; ++st) {
         wgt *= 0.5;
+        fac *= dt / st; /* dt^s / s! */
         /* U_s = dt/s V_{s-1} */
         for (int k = 0; k < T; ++k) s->Un[k] = dt / st * s->V[k];
         if (st == 1 && modified) {
@@ -382,6 +389,19 @@ static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t 
             scaled_laplacian(p, P, s->U, s->tmp);
             for (int k = 0; k < T; ++k) s->Vn[k] = c2 * dt / st * s->tmp[k];
         }
+        if (st - 1 < nf) {
+            /* forcing: V_s += dt^s/s! phi[s-1], phi embedded from extent 2m into P */
+            const double *ph = fcell + (int64_t)(st - 1) * Fv;
+            for (int q = 0; q < Fv; ++q) {
+                int rem = q, off = 0, stp = 1;
+                for (int i = 0; i < d; ++i) {
+                    off += (rem % (2 * m)) * stp;
+                    rem /= 2 * m;
+                    stp *= P;
+                }
+                s->Vn[off] += fac * ph[q];
+            }
+        }
         int nonzero = 0;
         for (int k = 0; k < T; ++k) {
             s->U[k] = s->Un[k];
@@ -390,7 +410,7 @@ static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t 
             vacc[k] += wgt * s->V[k];
             nonzero |= (s->U[k] != 0.0) | (s->V[k] != 0.0);
         }
-        if (!nonzero && p->taylor_stages <= 0) break; /* the series has terminated */
+        if (!nonzero && p->taylor_stages <= 0 && st >= nf) break; /* the series has terminated */
     }
 
     /* evaluation at the cell centre: coefficients l <= m (u), l <= m-1 (v) */
@@ -448,6 +468,14 @@ static int nthreads_or_default(int nthreads)
 int hwo_diss_half(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
                   double *u_out, double *v_out, const int64_t *sel, int64_t nsel, int nthreads)
 {
+    return hwo_diss_half_forced(p, to_grid, u_in, v_in, NULL, 0, u_out, v_out, sel, nsel, nthreads);
+}
+
+int hwo_diss_half_forced(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
+                         const double *f_coef, int n_orders, double *u_out, double *v_out,
+                         const int64_t *sel, int64_t nsel, int nthreads)
+{
+    if (n_orders < 0 || (n_orders > 0 && !f_coef)) return -1;
     if (check_problem(p) || p->m < 1 || (p->method != HWO_DISS_FULL && p->method != HWO_DISS_SIMPLE))
         return -1;
     const int d = p->d, M = p->m + 1, Mv = p->m;
@@ -467,7 +495,10 @@ int hwo_diss_half(const hwo_problem *p, int to_grid, const double *u_in, const d
             corners_t cr;
             out_index(p, to_grid, node, idx);
             find_corners(p, to_grid, idx, &cr);
-            diss_cell(p, tb, &cr, u_in, v_in, u_out + q * Mu_tot, v_out + q * Mv_tot, &s);
+            const double *fcell =
+                n_orders > 0 ? f_coef + node * (int64_t)n_orders * pw(2 * p->m, d) : NULL;
+            diss_cell(p, tb, &cr, u_in, v_in, fcell, n_orders, u_out + q * Mu_tot,
+                      v_out + q * Mv_tot, &s);
         }
         free(s.p0);
     }

@@ -25,6 +25,12 @@ int hwo_hermite_matrix(int m, double *H);
 int64_t hwo_nodes(const hwo_problem *p, int grid);
 int hwo_diss_half(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
                   double *u_out, double *v_out, const int64_t *sel, int64_t nsel, int nthreads);
+/* The same with a forcing term f (u_tt = c^2 Laplacian u + f): f_coef holds, for every */
+/* node of the grid written, n_orders blocks of (2m)^d values phi[r][k] =               */
+/* h^k/k! d^k/dx^k d^r/dt^r f at that node and the start of the half step.              */
+int hwo_diss_half_forced(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
+                         const double *f_coef, int n_orders, double *u_out, double *v_out,
+                         const int64_t *sel, int64_t nsel, int nthreads);
 int hwo_cons_half(const hwo_problem *p, int to_grid, const double *u_from, const double *u_old,
                   double *u_new, const int64_t *sel, int64_t nsel, int nthreads);
 int hwo_cons_startup(const hwo_problem *p, const double *u0, const double *v0, double *u_half,

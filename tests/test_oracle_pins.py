@@ -408,3 +408,49 @@ def test_diss_1d_energy_never_increases(m, cfl):
         e = oracle.diss_energy(p, grid, u, v)
         assert e <= e_prev * (1 + 1e-12)
         e_prev = e
+
+
+# ---------------------------------------------------------------------------
+# forcing: u_tt = c^2 Lap u + f (Sec. 3.1.2 eq. (recursion_diss_1d_2))
+# ---------------------------------------------------------------------------
+def _forced_polynomial_case(d, m, cfl, method, bdeg=4, seed=11):
+    """u(x, t) = sum_b t^b U_b(x) with U_b of degree 2m-1 per dimension and its forcing
+    f = u_tt - c^2 Lap u; returns the problem, the data at t = 0 on the primal grid,
+    the forcing coefficients at the dual nodes and the exact data at t = dt/2."""
+    rng = np.random.default_rng(seed)
+    spec = W.make_spec(d, m, [3] * d, 0.0, 1.0, 1.0, cfl=cfl, bc=W.DIRICHLET, method=method)
+    U = [_rand_poly(rng, d, 2 * m - 1) for _ in range(bdeg + 1)]
+    zero = np.zeros_like(U[0])
+    c2 = spec.c ** 2
+    f = []  # f_r = d^r f / dt^r at t = 0
+    for r in range(bdeg + 1):
+        acc = -c2 * _lap(U[r], d)
+        if r + 2 <= bdeg:
+            acc = acc + (r + 2) * (r + 1) * U[r + 2]
+        f.append(math.factorial(r) * acc)
+    tau = 0.5 * spec.dt
+    uT = sum((tau ** b) * U[b] for b in range(bdeg + 1))
+    vT = sum((b * tau ** (b - 1)) * U[b] for b in range(1, bdeg + 1)) if bdeg >= 1 else zero
+    u0 = _poly_nodal(U[0], spec, W.PRIMAL, m + 1)
+    v0 = _poly_nodal(U[1], spec, W.PRIMAL, m)
+    phi = np.stack([_poly_nodal(fr, spec, W.DUAL, 2 * m) for fr in f], axis=1)
+    return spec, u0, v0, phi, _poly_nodal(uT, spec, W.DUAL, m + 1), _poly_nodal(vT, spec, W.DUAL, m)
+
+
+@pytest.mark.parametrize("d,m,method", [(1, 2, W.DISS_FULL), (1, 3, W.DISS_FULL), (2, 2, W.DISS_FULL),
+                                        (2, 3, W.DISS_SIMPLE), (3, 2, W.DISS_FULL), (3, 1, W.DISS_SIMPLE)])
+@pytest.mark.parametrize("cfl", [0.7, 1.0])
+def test_diss_forced_polynomial_solution_exact(d, m, method, cfl):
+    """With the forcing's space-time Taylor coefficients fed into the stages, a
+    polynomial solution of the forced equation (degree 2m-1 in space, 4 in time) is
+    evolved exactly over a half step; leaving the forcing out, or cutting its time
+    expansion short, is not exact."""
+    spec, u0, v0, phi, uT, vT = _forced_polynomial_case(d, m, cfl, method)
+    p = _oracle_problem(spec)
+    uo, vo = oracle.diss_half(p, oracle.DUAL, u0, v0, forcing=phi)
+    np.testing.assert_allclose(uo, uT, atol=1e-11, rtol=0)
+    np.testing.assert_allclose(vo, vT, atol=1e-10, rtol=0)
+    un, vn = oracle.diss_half(p, oracle.DUAL, u0, v0)
+    assert np.abs(vn - vT).max() > 1e-6
+    us, vs = oracle.diss_half(p, oracle.DUAL, u0, v0, forcing=phi[:, :2])
+    assert np.abs(vs - vT).max() > 1e-9
