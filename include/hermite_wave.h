@@ -128,6 +128,23 @@ hw_status hw_prepare_advance(hw_solver* s, int n_full_steps);
 /* Advance n half steps with plain kernel launches (no graph). */
 hw_status hw_half_steps(hw_solver* s, int n_half, void* stream);
 
+/* One half step of a single dissipative problem with a forcing term,
+ * u_tt = c^2 Lap u + f (Sec. 3.1.2 eq. (recursion_diss_1d_2): stage s of the Taylor
+ * series in time receives dt^s/s! times the (s-1)-th time derivative of f; here in
+ * closed form, exact for f polynomial in time up to the orders given).
+ * f_coef: device pointer (FP64, caller-owned, read during the call's kernel on `stream`)
+ *   to [n_out][n_orders][(2m)^d] values phi[r][k] = h^k/k! d^k/dx^k d^r/dt^r f (k a
+ *   multi-index, k_x fastest, 0 <= k_i < 2m) at every node of the grid this half step
+ *   writes (the grid opposite hw_state_grid; node order as in hw_layout) and at the
+ *   time at the start of the half step.  f of degree <= 2m-1 per dimension is
+ *   represented exactly.
+ * n_orders: 0..16 (0 = no forcing; f_coef may then be NULL).
+ * Runs the generic kernel (plain launch, no graph); a taylor_stages truncation drops
+ * the forcing terms of later stages as well.  HW_EINVAL for batches, the
+ * conservative method, n_orders out of range or a NULL f_coef with n_orders > 0;
+ * HW_ESTATE if no state is set. */
+hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream);
+
 /* Copy the state out (device pointers, FP64, layouts as above).
  * Dissipative: u and v of the grid that holds the state (hw_state_grid).
  * Conservative: u on the primal grid and u on the dual grid (newest levels). */

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 
 # every entry point declared in include/hermite_wave.h
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
-                "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_get_state", "hw_state_grid", "hw_energy",
+                "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_get_state", "hw_state_grid", "hw_energy",
                 "hw_time", "hw_last_error", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
                 "hw_batch_get_state"]
@@ -71,6 +71,7 @@ def lib():
             "hw_advance": ([vp, ctypes.c_int, vp], ctypes.c_int),
             "hw_half_steps": ([vp, ctypes.c_int, vp], ctypes.c_int),
             "hw_prepare_advance": ([vp, ctypes.c_int], ctypes.c_int),
+            "hw_half_step_forced": ([vp, dp, ctypes.c_int, vp], ctypes.c_int),
             "hw_get_state": ([vp, dp, dp, vp], ctypes.c_int),
             "hw_state_grid": ([vp], ctypes.c_int),
             "hw_energy": ([vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
@@ -192,6 +193,10 @@ def hw_half_steps(h, n, stream=None):
     _check(lib().hw_half_steps(h, n, _stream(stream)))
 
 
+def hw_half_step_forced(h, f_coef, n_orders, stream=None):
+    _check(lib().hw_half_step_forced(h, _ptr(f_coef), n_orders, _stream(stream)))
+
+
 def hw_get_state(h, u, w, stream=None):
     _check(lib().hw_get_state(h, _ptr(u), _ptr(w), _stream(stream)))
 
@@ -270,6 +275,16 @@ class Solver:
 
     def half_steps(self, n):
         hw_half_steps(self.h, n)
+
+    def half_step_forced(self, f_coef):
+        """One half step with forcing coefficients of shape (n_out, R, (2m)^d) (see
+        hw_half_step_forced); None or R = 0: no forcing."""
+        if f_coef is None:
+            hw_half_step_forced(self.h, None, 0)
+            return
+        f = self._dev(f_coef)
+        hw_half_step_forced(self.h, f, int(f.shape[1]))
+        self.torch.cuda.current_stream().synchronize()
 
     def state_grid(self):
         return hw_state_grid(self.h)

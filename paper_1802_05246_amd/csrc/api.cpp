@@ -87,6 +87,7 @@ struct hw_solver {
     size_t lds = 0;
     int grid = 0;
     double* partials = nullptr;
+    double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
     int energy_grid = 0;
     hipStream_t cap_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -409,6 +410,26 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         hipMemcpy(s->prefix, s->h_prefix.data(), s->h_prefix.size() * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(HW_EHIP, "descriptor upload failed"));
+    if (count == 1 && p0.method != HW_CONSERVATIVE) {
+        // forcing weights: u: tau^(r+2) j!/(2j+r+2)!, v: tau^(r+1) j!/(2j+r+1)!, zero for
+        // terms beyond a stage truncation (the term enters stage 2j+r+2 / 2j+r+1)
+        std::vector<double> fw((size_t)2 * HW_MAXF * HW_MAXJ, 0.0);
+        const double tau = 0.5 * p0.dt;
+        const int S = p0.taylor_stages;
+        for (int r = 0; r < HW_MAXF; ++r)
+            for (int j = 0; j < HW_MAXJ; ++j) {
+                const int su = 2 * j + r + 2, sv = 2 * j + r + 1;
+                if (S <= 0 || su <= S)
+                    fw[(size_t)r * HW_MAXJ + j] = std::pow(tau, r + 2) * fact(j) / fact(su);
+                if (S <= 0 || sv <= S)
+                    fw[(size_t)(HW_MAXF + r) * HW_MAXJ + j] = std::pow(tau, r + 1) * fact(j) / fact(sv);
+            }
+        if (hipMalloc((void**)&s->forcing_w, fw.size() * sizeof(double)) != hipSuccess)
+            return cleanup(fail(HW_ENOMEM, "forcing table allocation failed"));
+        if (hipMemcpy(s->forcing_w, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return cleanup(fail(HW_EHIP, "forcing table upload failed"));
+    }
     if (s->use_tiled && hw_tiled_prepare(s->precision) != hipSuccess)
         return cleanup(fail(HW_EHIP, "tiled kernel table setup failed"));
     if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -462,6 +483,7 @@ void hw_destroy(hw_solver* s)
     if (s->startup_prefix) (void)hipFree(s->startup_prefix);
     if (s->prefix) (void)hipFree(s->prefix);
     if (s->partials) (void)hipFree(s->partials);
+    if (s->forcing_w) (void)hipFree(s->forcing_w);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
@@ -546,6 +568,25 @@ hw_status hw_half_steps(hw_solver* s, int n, void* stream)
         if (r != HW_OK) return r;
         s->half_steps++;
     }
+    return HW_OK;
+}
+
+hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream)
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (s->probs.size() != 1 || s->probs[0].p.method == HW_CONSERVATIVE || !s->forcing_w)
+        return fail(HW_EINVAL, "forcing applies to a single dissipative problem");
+    if (n_orders < 0 || n_orders > HW_MAXF)
+        return fail(HW_EINVAL, "n_orders must be in 0..%d", HW_MAXF);
+    if (n_orders > 0 && !f_coef) return fail(HW_EINVAL, "null forcing coefficients");
+    if (!s->state_set) return fail(HW_ESTATE, "state not set");
+    hipStream_t st = (hipStream_t)stream;
+    const int phase = (int)(s->half_steps & 1);
+    ForcingArgs fa{n_orders > 0 ? f_coef : nullptr, n_orders, s->forcing_w};
+    // the generic kernel carries the forcing terms (the tiled kernel does not)
+    HIP_TRY(hw_launch_generic(s->d, s->fp64, s->descs + (size_t)(phase * 2) * 1, s->prefix + (size_t)phase * 2, 1,
+                              s->total_cells[phase], s->ops, s->lds, s->grid, st, &fa));
+    s->half_steps++;
     return HW_OK;
 }
 

@@ -44,6 +44,18 @@ struct ProblemDesc {
     double cuQ[HW_MAXJ], cuR[HW_MAXJ], cvQ[HW_MAXJ], cvR[HW_MAXJ];
 };
 
+// Forcing of one dissipative half step (u_tt = c^2 Lap u + f): for every output node,
+// `orders` blocks of (2m)^d scaled space-time Taylor coefficients
+// h^k/k! d^k/dx^k d^r/dt^r f at the node and the start of the half step (FP64).
+// w[0][r][j] = tau^(r+2) j!/(2j+r+2)! (u), w[1][r][j] = tau^(r+1) j!/(2j+r+1)! (v),
+// zero beyond a stage truncation.
+#define HW_MAXF 16
+struct ForcingArgs {
+    const double* coef; // null: no forcing
+    int orders;
+    const double* w;    // [2][HW_MAXF][HW_MAXJ]
+};
+
 // Energy (conservative): sum over the cells centred at the nodes of `center_grid`
 // of w_cell * <I f, I g>_{m+1} (f, g data on the other grid).
 struct EnergyDesc {

@@ -11,7 +11,7 @@ size_t hw_energy_lds_bytes(int d, int m);
 
 hipError_t hw_launch_generic(int d, bool fp64, const ProblemDesc* descs, const int64_t* prefix,
                              int nprob, int64_t total, const void* ops, size_t lds, int grid,
-                             hipStream_t st);
+                             hipStream_t st, const ForcingArgs* forcing = nullptr);
 hipError_t hw_launch_energy(int d, bool fp64, const EnergyDesc& E, const double* dops,
                             double* partials, int grid, hipStream_t st);
 hipError_t hw_launch_convert(const void* src, bool src64, void* dst, bool dst64, int64_t n,

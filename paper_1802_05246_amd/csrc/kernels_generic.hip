@@ -161,7 +161,7 @@ __device__ void gather(const Geom& P, const Corners& cr, const T* __restrict__ d
 
 template <typename T, int D>
 __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64_t cell, T* sm,
-                          int lane)
+                          int lane, const ForcingArgs& FA)
 {
     const int m = P.m, M = m + 1, Pn = 2 * m + 2, K = Pn, Kv = 2 * m;
     const bool simple = (P.variant == HWV_DISS_SIMPLE) || D == 1;
@@ -281,6 +281,44 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
         if (is_u) uo[c] = acc;
         else vo[c] = acc;
     }
+    if (FA.coef == nullptr) return;
+
+    // forcing: u' += sum_r sum_j tau^(r+2)/(2j+r+2)! [L^j f_r], v' += sum_r sum_j
+    // tau^(r+1)/(2j+r+1)! [L^j f_r] with [L^j a]_alpha = sum_|beta|=j g(alpha,beta)
+    // a_(alpha+2 beta); f_r has extent 2m per dimension.  Every lane adds to the
+    // outputs it wrote above.
+    const int KvD = ipow(Kv, D);
+    const double* fc = FA.coef + cell * (int64_t)FA.orders * KvD;
+    for (int r = 0; r < FA.orders; ++r) {
+        __syncthreads();
+        for (int e = lane; e < KvD; e += GW) bufA[e] = T(fc[(int64_t)r * KvD + e]);
+        __syncthreads();
+        for (int o = lane; o < Mu_tot + Mv_tot; o += GW) {
+            const bool is_u = o < Mu_tot;
+            const int c = is_u ? o : o - Mu_tot;
+            const int Mo = is_u ? M : m;
+            int a[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
+            int rem = c;
+            for (int i = 0; i < D; ++i) {
+                a[i] = rem % Mo;
+                rem /= Mo;
+                bmax[i] = (Kv - 1 - a[i]) / 2;
+            }
+            const double* w = FA.w + ((is_u ? 0 : HW_MAXF) + r) * HW_MAXJ;
+            T acc = T(0);
+            for (int b2 = 0; b2 <= bmax[2]; ++b2)
+                for (int b1 = 0; b1 <= bmax[1]; ++b1)
+                    for (int b0 = 0; b0 <= bmax[0]; ++b0) {
+                        double g = P.F[0][a[0]][b0];
+                        if (D > 1) g *= P.F[1][a[1]][b1];
+                        if (D > 2) g *= P.F[2][a[2]][b2];
+                        const int idx = (a[0] + 2 * b0) + Kv * ((a[1] + 2 * b1) + Kv * (a[2] + 2 * b2));
+                        acc += T(g * w[b0 + b1 + b2]) * bufA[idx];
+                    }
+            if (is_u) uo[c] += acc;
+            else vo[c] += acc;
+        }
+    }
 }
 
 template <typename T, int D>
@@ -340,7 +378,7 @@ __device__ void cons_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
 template <typename T, int D>
 __global__ void __launch_bounds__(GW)
 k_half_step(const ProblemDesc* __restrict__ descs, const int64_t* __restrict__ prefix, int nprob,
-            int64_t total, const T* __restrict__ ops)
+            int64_t total, const T* __restrict__ ops, ForcingArgs FA)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = reinterpret_cast<T*>(smem_raw);
@@ -353,7 +391,7 @@ k_half_step(const ProblemDesc* __restrict__ descs, const int64_t* __restrict__ p
         }
         const ProblemDesc& P = descs[lo];
         const int64_t cell = g - prefix[lo];
-        if (P.variant <= HWV_DISS_SIMPLE) diss_cell<T, D>(P, ops, cell, sm, threadIdx.x);
+        if (P.variant <= HWV_DISS_SIMPLE) diss_cell<T, D>(P, ops, cell, sm, threadIdx.x, FA);
         else cons_cell<T, D>(P, ops, cell, sm, threadIdx.x);
         __syncthreads();
     }
@@ -486,7 +524,7 @@ size_t hw_energy_lds_bytes(int d, int m)
 
 template <typename T, int D>
 static hipError_t launch_hs(const ProblemDesc* descs, const int64_t* prefix, int nprob, int64_t total,
-                            const void* ops, size_t lds, int grid, hipStream_t st)
+                            const void* ops, size_t lds, int grid, hipStream_t st, ForcingArgs fa)
 {
     auto kern = k_half_step<T, D>;
     if (lds > 64 * 1024) {
@@ -495,22 +533,24 @@ static hipError_t launch_hs(const ProblemDesc* descs, const int64_t* prefix, int
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(GW), lds, st, descs, prefix, nprob, total,
-                       (const T*)ops);
+                       (const T*)ops, fa);
     return hipGetLastError();
 }
 
 hipError_t hw_launch_generic(int d, bool fp64, const ProblemDesc* descs, const int64_t* prefix,
                              int nprob, int64_t total, const void* ops, size_t lds, int grid,
-                             hipStream_t st)
+                             hipStream_t st, const ForcingArgs* forcing)
 {
+    ForcingArgs fa{nullptr, 0, nullptr};
+    if (forcing) fa = *forcing;
     if (fp64) {
-        if (d == 1) return launch_hs<double, 1>(descs, prefix, nprob, total, ops, lds, grid, st);
-        if (d == 2) return launch_hs<double, 2>(descs, prefix, nprob, total, ops, lds, grid, st);
-        return launch_hs<double, 3>(descs, prefix, nprob, total, ops, lds, grid, st);
+        if (d == 1) return launch_hs<double, 1>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
+        if (d == 2) return launch_hs<double, 2>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
+        return launch_hs<double, 3>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
     }
-    if (d == 1) return launch_hs<float, 1>(descs, prefix, nprob, total, ops, lds, grid, st);
-    if (d == 2) return launch_hs<float, 2>(descs, prefix, nprob, total, ops, lds, grid, st);
-    return launch_hs<float, 3>(descs, prefix, nprob, total, ops, lds, grid, st);
+    if (d == 1) return launch_hs<float, 1>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
+    if (d == 2) return launch_hs<float, 2>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
+    return launch_hs<float, 3>(descs, prefix, nprob, total, ops, lds, grid, st, fa);
 }
 
 template <typename T, int D>

@@ -70,6 +70,7 @@ def test_null_arguments():
     L = B.lib()
     assert L.hw_create(None, None) == B.HW_EINVAL
     assert L.hw_half_steps(None, 1, None) == B.HW_EINVAL
+    assert L.hw_half_step_forced(None, None, 0, None) == B.HW_EINVAL
     assert L.hw_advance(None, 1, None) == B.HW_EINVAL
     assert L.hw_energy(None, None, None) == B.HW_EINVAL
     assert L.hw_state_grid(None) == -1
