@@ -65,7 +65,8 @@ __host__ __device__ constexpr double opX(int r, int c)
 // index neighbouring nodes, edges or cells, fall into different banks.
 constexpr int NUP = 65;  // node stride of u
 constexpr int NVP = 29;  // node stride of v
-constexpr int XUE = 257; // x-edge stride of the u x-pass results: [row][l_y + 4 l_z] + 1
+constexpr int XUR = 20;  // row stride of an edge's u x-pass results (rows 4 apart: 80 words)
+constexpr int XUE = 16 * XUR + 1; // x-edge stride of the u x-pass results: [row][l_y + 4 l_z]
 constexpr int XVE = 55;  // x-edge stride of the v x-pass results: [row][l_y + 3 l_z] + 1
 constexpr int P0S = 65;  // cell stride of p0: [kx + 4 ky + 16 kz]
 constexpr int ZS = 433;  // cell stride of [tau S Q (216) | S R (216) | 0]
@@ -199,7 +200,7 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
         T Eh[4], Oh[4];
 #pragma unroll
         for (int ly = 0; ly < 4; ++ly) {
-            const T a0 = xu0[(10 + kx) * 16 + ly + 4 * lz], a1 = xu1[(10 + kx) * 16 + ly + 4 * lz];
+            const T a0 = xu0[(10 + kx) * XUR + ly + 4 * lz], a1 = xu1[(10 + kx) * XUR + ly + 4 * lz];
             Eh[ly] = a0 + a1;
             Oh[ly] = a0 - a1;
         }
@@ -207,7 +208,7 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
             T Ed[3], Od[3], Eq[3], Oq[3];
 #pragma unroll
             for (int ly = 0; ly < 3; ++ly) {
-                const T d0 = xu0[(4 + kx) * 16 + ly + 4 * lz], d1 = xu1[(4 + kx) * 16 + ly + 4 * lz];
+                const T d0 = xu0[(4 + kx) * XUR + ly + 4 * lz], d1 = xu1[(4 + kx) * XUR + ly + 4 * lz];
                 const T q0 = xv0[kx * 9 + ly + 3 * lz], q1 = xv1[kx * 9 + ly + 3 * lz];
                 Ed[ly] = d0 + d1;
                 Od[ly] = d0 - d1;
@@ -509,7 +510,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                     acc = MF::mac(xa1, b1[i], acc);
                     T* dst = sh.xu + e * XUE + (lane & 15);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * 16] = acc[r];
+                    for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * XUR] = acc[r];
                 }
             }
         }
@@ -544,7 +545,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                 T E[4], O[4];
 #pragma unroll
                 for (int ly = 0; ly < 4; ++ly) {
-                    const T a0 = xu0[kx * 16 + ly + 4 * lz], a1 = xu1[kx * 16 + ly + 4 * lz];
+                    const T a0 = xu0[kx * XUR + ly + 4 * lz], a1 = xu1[kx * XUR + ly + 4 * lz];
                     E[ly] = a0 + a1;
                     O[ly] = a0 - a1;
                 }
@@ -578,36 +579,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         __syncthreads();
 
         // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product ----
-        for (int task = wave; task < 8 * (NC / 16); task += NW) {
-            const int p = task % 8, g = task / 8;
-            const int cell = 16 * g + (lane & 15);
-            const T* zc = sh.z + cell * ZS;
-            typename MF::vec acc = {T(0), T(0), T(0), T(0)};
-            if constexpr (kFixedClass) {
-                // all B operands first: the products then run back to back instead of
-                // each waiting for its own LDS read
-                T bv[TS_KSTEPS];
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[tkv[ks]];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(tav[ks], bv[ks], acc);
-            } else {
-                // the class's operands come from the (cached) constant tables: all of
-                // them are requested at once, so the task waits for memory only once
-                T av[TS_KSTEPS], bv[TS_KSTEPS];
-                int kv[TS_KSTEPS];
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) {
-                    kv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
-                    av[ks] = tabs->ta[p][ks][lane];
-                }
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[kv[ks]];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(av[ks], bv[ks], acc);
-            }
+        auto epilogue = [&](const typename MF::vec& acc, int cell, int p) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int dst;
@@ -622,6 +594,52 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                 const int ai = dst & 0xffff;
                 if (dst >> 16) ov_base[cell * 27 + ai] = sc * acc[r];
                 else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + sc * acc[r];
+            }
+        };
+        if constexpr (kFixedClass) {
+            // the wave's class is fixed; its groups of 16 cells share the A operands, so
+            // their products run as interleaved independent chains, all B operands read
+            // first
+            constexpr int GPW = (8 * (NC / 16)) / NW;
+            T bv[GPW][TS_KSTEPS];
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) {
+                const T* zc = sh.z + (16 * (wave / 8 + k * (NW / 8)) + (lane & 15)) * ZS;
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[k][ks] = zc[tkv[ks]];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            typename MF::vec acc[GPW];
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) acc[k] = typename MF::vec{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ks = 0; ks < TS_KSTEPS; ++ks)
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) acc[k] = MF::mac(tav[ks], bv[k][ks], acc[k]);
+#pragma unroll
+            for (int k = 0; k < GPW; ++k)
+                epilogue(acc[k], 16 * (wave / 8 + k * (NW / 8)) + (lane & 15), wave % 8);
+        } else {
+            for (int task = wave; task < 8 * (NC / 16); task += NW) {
+                const int p = task % 8, g = task / 8;
+                const int cell = 16 * g + (lane & 15);
+                const T* zc = sh.z + cell * ZS;
+                // the class's operands come from the (cached) constant tables: all of
+                // them are requested at once, so the task waits for memory only once
+                T av[TS_KSTEPS], bv[TS_KSTEPS];
+                int kv[TS_KSTEPS];
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) {
+                    kv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
+                    av[ks] = tabs->ta[p][ks][lane];
+                }
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[kv[ks]];
+                __builtin_amdgcn_sched_barrier(0);
+                typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(av[ks], bv[ks], acc);
+                epilogue(acc, cell, p);
             }
         }
     }
