@@ -292,9 +292,14 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     // the padding slot of every cell block reads as zero in the class products
     for (int c = tid; c < NC; c += NT) sh.z[c * ZS + 432] = T(0);
     const T xa0 = tabs->xa[0][lane], xa1 = tabs->xa[1][lane];
-    // with a multiple of 8 waves every wave keeps one parity class for the whole run
-    // and holds that class's operands in registers (no table loads in the loop)
-    constexpr bool kFixedClass = (NW % 8) == 0;
+    // every wave keeps CPW parity classes for the whole run, holds their operands in
+    // registers (no table loads in the loop) and applies each to GPW groups of 16 cells
+    static_assert(NW % 8 == 0 || 8 % NW == 0, "waves and parity classes must tile");
+    constexpr int CPW = NW >= 8 ? 1 : 8 / NW;
+    constexpr int GPW = NW >= 8 ? (NC / 16) / (NW / 8) : NC / 16;
+    static_assert(NW < 8 || (NC / 16) % (NW / 8) == 0, "cell groups must tile the waves");
+    auto cls_of = [&](int c) { return NW >= 8 ? wave % 8 : wave + c * NW; };
+    auto grp_of = [&](int k) { return NW >= 8 ? wave / 8 + k * (NW / 8) : k; };
     const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
     const T invx = T(1.0 / a.lam2[0]), invy = T(1.0 / a.lam2[1]), invz = T(1.0 / a.lam2[2]);
     // output decode of table entry `info`: LDS offset in the staged outputs (u rows
@@ -313,17 +318,18 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         if (info & 0x400) sc *= invz;
         dst = (info & 0x1000) ? (1 << 16) | ai : ai;
     };
-    T tav[kFixedClass ? TS_KSTEPS : 1], rsc[kFixedClass ? 4 : 1];
-    int tkv[kFixedClass ? TS_KSTEPS : 1], rdst[kFixedClass ? 4 : 1];
-    if constexpr (kFixedClass) {
-        const int p = wave % 8;
+    T tav[CPW][TS_KSTEPS], rsc[CPW][4];
+    int tkv[CPW][TS_KSTEPS], rdst[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int p = cls_of(c);
 #pragma unroll
         for (int ks = 0; ks < TS_KSTEPS; ++ks) {
-            tav[ks] = tabs->ta[p][ks][lane];
-            tkv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
+            tav[c][ks] = tabs->ta[p][ks][lane];
+            tkv[c][ks] = tabs->tk[p][4 * ks + (lane >> 4)];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) decode(tabs->tr[p][MF::row(lane, r)], rdst[r], rsc[r]);
+        for (int r = 0; r < 4; ++r) decode(tabs->tr[p][MF::row(lane, r)], rdst[c][r], rsc[c][r]);
     }
 
     // ---- 1. node layers: fetched into registers one layer ahead, then stashed in
@@ -578,35 +584,26 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         if (!emit) continue; // the first layer only primes the registers
         __syncthreads();
 
-        // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product ----
-        auto epilogue = [&](const typename MF::vec& acc, int cell, int p) {
+        // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product.  The
+        //         wave's CPW x GPW products run as interleaved independent chains, all B
+        //         operands read first ----
+        auto epilogue = [&](const typename MF::vec& acc, int cell, int c) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int dst;
-                T sc;
-                if constexpr (kFixedClass) {
-                    dst = rdst[r];
-                    sc = rsc[r];
-                } else {
-                    decode(tabs->tr[p][MF::row(lane, r)], dst, sc);
-                }
+                const int dst = rdst[c][r];
                 if (dst < 0) continue;
                 const int ai = dst & 0xffff;
-                if (dst >> 16) ov_base[cell * 27 + ai] = sc * acc[r];
-                else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + sc * acc[r];
+                if (dst >> 16) ov_base[cell * 27 + ai] = rsc[c][r] * acc[r];
+                else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + rsc[c][r] * acc[r];
             }
         };
-        if constexpr (kFixedClass) {
-            // the wave's class is fixed; its groups of 16 cells share the A operands, so
-            // their products run as interleaved independent chains, all B operands read
-            // first
-            constexpr int GPW = (8 * (NC / 16)) / NW;
+        if constexpr (CPW == 1) {
             T bv[GPW][TS_KSTEPS];
 #pragma unroll
             for (int k = 0; k < GPW; ++k) {
-                const T* zc = sh.z + (16 * (wave / 8 + k * (NW / 8)) + (lane & 15)) * ZS;
+                const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
 #pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[k][ks] = zc[tkv[ks]];
+                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[k][ks] = zc[tkv[0][ks]];
             }
             __builtin_amdgcn_sched_barrier(0);
             typename MF::vec acc[GPW];
@@ -615,32 +612,35 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
 #pragma unroll
             for (int ks = 0; ks < TS_KSTEPS; ++ks)
 #pragma unroll
-                for (int k = 0; k < GPW; ++k) acc[k] = MF::mac(tav[ks], bv[k][ks], acc[k]);
+                for (int k = 0; k < GPW; ++k) acc[k] = MF::mac(tav[0][ks], bv[k][ks], acc[k]);
 #pragma unroll
-            for (int k = 0; k < GPW; ++k)
-                epilogue(acc[k], 16 * (wave / 8 + k * (NW / 8)) + (lane & 15), wave % 8);
+            for (int k = 0; k < GPW; ++k) epilogue(acc[k], 16 * grp_of(k) + (lane & 15), 0);
         } else {
-            for (int task = wave; task < 8 * (NC / 16); task += NW) {
-                const int p = task % 8, g = task / 8;
-                const int cell = 16 * g + (lane & 15);
-                const T* zc = sh.z + cell * ZS;
-                // the class's operands come from the (cached) constant tables: all of
-                // them are requested at once, so the task waits for memory only once
-                T av[TS_KSTEPS], bv[TS_KSTEPS];
-                int kv[TS_KSTEPS];
+            T bv[CPW][GPW][TS_KSTEPS];
 #pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) {
-                    kv[ks] = tabs->tk[p][4 * ks + (lane >> 4)];
-                    av[ks] = tabs->ta[p][ks][lane];
+            for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
+#pragma unroll
+                    for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[c][k][ks] = zc[tkv[c][ks]];
                 }
+            __builtin_amdgcn_sched_barrier(0);
+            typename MF::vec acc[CPW][GPW];
 #pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[ks] = zc[kv[ks]];
-                __builtin_amdgcn_sched_barrier(0);
-                typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+            for (int c = 0; c < CPW; ++c)
 #pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) acc = MF::mac(av[ks], bv[ks], acc);
-                epilogue(acc, cell, p);
-            }
+                for (int k = 0; k < GPW; ++k) acc[c][k] = typename MF::vec{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int ks = 0; ks < TS_KSTEPS; ++ks)
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                    for (int k = 0; k < GPW; ++k) acc[c][k] = MF::mac(tav[c][ks], bv[c][k][ks], acc[c][k]);
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) epilogue(acc[c][k], 16 * grp_of(k) + (lane & 15), c);
         }
     }
     if (nlayers >= 2) {
