@@ -327,11 +327,12 @@ def c4_3d(n=256, m=3, cfl=0.9, steps=200, seed=1806, sigma=0.05, device=None) ->
                     meta={"centres": [c.tolist() for c in centres], "amps": amps, "sigma": sigma})
 
 
-def c5_batch(count=256, steps=500, seed=1807, cfl=0.8, n_lo=64, n_hi=1024) -> List[Workload]:
+def c5_batch(count=256, steps=500, seed=1807, cfl=0.8, n_lo=64, n_hi=1024, device=None) -> List[Workload]:
     """Independent 2-D problems: per problem N ~ round(exp U(ln n_lo, ln n_hi)),
     m ~ U{2..6}, c ~ U(0.5, 2), method ~ {dissipative full, conservative},
     walls ~ {Dirichlet, Neumann, periodic}, 4 pulses (centre, amplitude); v0 = 0.
-    The conservative second level comes from the start-up step (v0 = 0)."""
+    The conservative second level comes from the start-up step (v0 = 0).  With a
+    torch `device` the initial data is built there."""
     rng = np.random.default_rng(seed)
     out = []
     for b in range(count):
@@ -343,8 +344,14 @@ def c5_batch(count=256, steps=500, seed=1807, cfl=0.8, n_lo=64, n_hi=1024) -> Li
         centres, amps = _pulse_draw(rng, 4, 2)
         spec = make_spec(2, m, N, 0.0, 1.0, c, cfl=cfl, bc=bc, method=method)
         sigma = 0.05
-        u0 = pulses_nodal(spec, PRIMAL, m + 1, centres, amps, sigma)
-        v0 = None if method == CONSERVATIVE else np.zeros((spec.nodes(PRIMAL), m ** 2))
+        u0 = pulses_nodal(spec, PRIMAL, m + 1, centres, amps, sigma, device=device)
+        if method == CONSERVATIVE:
+            v0 = None
+        elif device is not None:
+            import torch
+            v0 = torch.zeros((spec.nodes(PRIMAL), m ** 2), dtype=torch.float64, device=device)
+        else:
+            v0 = np.zeros((spec.nodes(PRIMAL), m ** 2))
         out.append(Workload(f"c5_{b}", spec, steps, u0, v0,
                             meta={"centres": [x.tolist() for x in centres], "amps": amps}))
     return out

@@ -1,0 +1,131 @@
+"""The batched workload (256 independent 2-D problems: N, m, c, method and walls drawn
+per problem, one batched launch per half step), against the oracle problem by
+problem: the whole recipe at reduced N, and the full-size batch on sampled nodes."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import oracle_problem, oracle_reference_run, rel_l2, sampled_oracle
+from paper_1802_05246_amd import workloads as W
+from test_gpu_parity import fp32_tol, joint_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _B():
+    from paper_1802_05246_amd import binding as B
+    B.lib()
+    return B
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _start(B, s, works):
+    for i, w in enumerate(works):
+        if w.spec.method == W.CONSERVATIVE:
+            s.cons_startup(w.u0, None, i=i)
+        else:
+            s.set_state(w.u0, w.v0, i=i)
+    torch.cuda.synchronize()
+
+
+def _oracle_roundoff_floor(spec, u, w, n_half, ref, seed=0):
+    """Relative change of the oracle's own result when its input is perturbed at the
+    level of FP64 rounding (relative 2^-52): the floor below which two FP64
+    evaluations in different summation orders cannot be expected to agree."""
+    rng = np.random.default_rng(seed)
+    up = np.asarray(u) * (1.0 + 2.0 ** -52 * rng.standard_normal(np.shape(u)))
+    out = oracle_reference_run(spec, up, w, n_half)
+    return max(rel_l2(out[0], ref[0]), rel_l2(out[1], ref[1]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c5_recipe_reduced_n_every_problem(prec):
+    """All 256 problems of the recipe (every m, method and wall type), N in 6..16:
+    two full steps of the batch against the oracle, every problem, every node.
+    FP64 bar: 1e-10, or ten times the oracle's own round-off floor where the
+    problem's map amplifies rounding more (high m: the Hermite operator H_6 has
+    entries up to 1638 and the four half steps compound it)."""
+    B = _B()
+    works = W.c5_batch(n_lo=6, n_hi=16)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(problems=[w.spec for w in works], precision=precision)
+    _start(B, s, works)
+    ins = [[x.cpu().numpy() for x in s.get_state(i)] for i in range(len(works))]
+    s.advance(2)
+    worst = 0.0
+    for i, w in enumerate(works):
+        gu, gw = (x.cpu().numpy() for x in s.get_state(i))
+        ou, ow = oracle_reference_run(w.spec, ins[i][0], ins[i][1], 4)
+        if precision == B.HW_FP64:
+            err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+            if err > tol:
+                tol = max(tol, 10.0 * _oracle_roundoff_floor(w.spec, ins[i][0], ins[i][1], 4, (ou, ow)))
+        else:
+            err, tol = joint_err(w.spec, gu, gw, ou, ow), fp32_tol(w.spec.m, 4)
+        worst = max(worst, err / tol)
+        assert err <= tol, (i, w.spec, err, tol)
+    _log(f"[c5 reduced] {prec}: worst error / tolerance = {worst:.3f}")
+    s.close()
+
+
+def test_c5_full_size_sampled():
+    """The full batch (N in 64..1024, FP32 state): one batched launch per half step;
+    for a spread of problems the second half step is checked on sampled nodes (wall
+    and wrap-around nodes included) against the oracle on one- or two-cell boxes."""
+    B = _B()
+    t0 = time.time()
+    works = W.c5_batch(device="cuda")
+    _log(f"[c5 full] data built in {time.time() - t0:.1f} s, "
+         f"{sum(w.spec.nodes(W.PRIMAL) for w in works)} primal nodes")
+    s = B.Solver(problems=[w.spec for w in works], precision=B.HW_FP32)
+    _start(B, s, works)
+    specs = [w.spec for w in works]
+    for w in works:
+        w.u0 = w.v0 = None
+    torch.cuda.empty_cache()
+    # a spread of problems: largest N, highest m, each method and wall type
+    pick = {max(range(len(specs)), key=lambda i: specs[i].n[0])}
+    for cond in (lambda sp: sp.m == 6, lambda sp: sp.method == W.CONSERVATIVE and sp.bc[0] == W.DIRICHLET,
+                 lambda sp: sp.method == W.DISS_FULL and sp.bc[0] == W.NEUMANN,
+                 lambda sp: sp.method == W.CONSERVATIVE and sp.bc[0] == W.NEUMANN,
+                 lambda sp: sp.bc[0] == W.PERIODIC):
+        pick.add(next(i for i in range(len(specs)) if cond(specs[i])))
+    s.half_steps(1)
+    torch.cuda.synchronize()
+    xin = {i: s.get_state(i) for i in pick}
+    t1 = time.time()
+    s.half_steps(1)
+    torch.cuda.synchronize()
+    _log(f"[c5 full] one batched half step: {time.time() - t1:.2f} s")
+    rng = np.random.default_rng(55)
+    for i in sorted(pick):
+        spec = specs[i]
+        yu, yw = s.get_state(i)
+        xu, xw = xin[i]
+        if spec.method == W.CONSERVATIVE:
+            to_grid = W.DUAL  # the second half step updates the dual grid from the primal
+        else:
+            to_grid = W.PRIMAL
+        n_out = spec.nodes(to_grid)
+        samples = [0, n_out - 1] + list(rng.choice(n_out, size=24, replace=False))
+        sel = torch.as_tensor(samples, device="cuda")
+        if spec.method == W.CONSERVATIVE:
+            ou, _ = sampled_oracle(spec, to_grid, lambda ix: xu[torch.as_tensor(ix, device="cuda")].cpu().numpy(),
+                                   None, samples,
+                                   u_old=lambda ix: xw[torch.as_tensor(ix, device="cuda")].cpu().numpy())
+            gu, gv, ov = yw[sel].cpu().numpy(), None, None
+        else:
+            ou, ov = sampled_oracle(spec, to_grid, lambda ix: xu[torch.as_tensor(ix, device="cuda")].cpu().numpy(),
+                                    lambda ix: xw[torch.as_tensor(ix, device="cuda")].cpu().numpy(), samples)
+            gu, gv = yu[sel].cpu().numpy(), yw[sel].cpu().numpy()
+        err, tol = joint_err(spec, gu, gv, ou, ov), fp32_tol(spec.m, 1)
+        _log(f"[c5 full] problem {i}: N={spec.n[0]} m={spec.m} method={spec.method} bc={spec.bc[0]} "
+             f"sampled rel err {err:.2e} (tol {tol:.1e})")
+        assert err <= tol
+    s.close()
