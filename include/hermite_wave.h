@@ -67,7 +67,13 @@ typedef enum {
 typedef enum {
     HW_KERNEL_AUTO = 0,    /* tiled MFMA kernel when one exists for the problem, else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
-    HW_KERNEL_TILED = 2    /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
+    HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
+    HW_KERNEL_SPLIT = 3    /* two kernels per half step, as in the paper's two-kernel GPU
+                              design (Sec. 6.1): the first writes each cell's interpolants
+                              (p0, Q, R) to a device workspace, the second reads them and
+                              sums the Taylor series; single dissipative problems only
+                              (HW_EUNSUPPORTED otherwise); for comparison with the fused
+                              kernels */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;

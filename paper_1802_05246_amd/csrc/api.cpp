@@ -2,6 +2,7 @@
 // tables, the half-step sequence and its hipGraph capture, the energy reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -88,6 +89,9 @@ struct hw_solver {
     int grid = 0;
     double* partials = nullptr;
     double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
+    bool split = false;           // two-kernel form
+    void* work = nullptr;         // its interpolant workspace
+    ProblemDesc* split_descs = nullptr; // [phase][stage 1, 2]
     int energy_grid = 0;
     hipStream_t cap_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -107,7 +111,7 @@ hw_status validate(const hw_problem* p)
         return fail(HW_EINVAL, "m = %d outside %d..%d for this method", p->m, mlo, HW_MAXM);
     if (p->precision < HW_FP64 || p->precision > HW_BF16)
         return fail(HW_EINVAL, "unknown precision %d", p->precision);
-    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_TILED)
+    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_SPLIT)
         return fail(HW_EINVAL, "unknown kernel selector %d", p->kernel);
     if (!(p->c > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->c) || !std::isfinite(p->dt))
         return fail(HW_EINVAL, "c and dt must be positive and finite");
@@ -302,6 +306,12 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
     }
     const ProblemDesc* descs = s->descs + (size_t)(phase * 2 + q) * np;
     const int64_t* prefix = s->prefix + (size_t)phase * (np + 1);
+    if (s->split) {
+        for (int st2 = 0; st2 < 2; ++st2)
+            HIP_TRY(hw_launch_generic(s->d, s->fp64, s->split_descs + phase * 2 + st2, prefix, 1,
+                                      s->total_cells[phase], s->ops, s->lds, s->grid, st));
+        return HW_OK;
+    }
     HIP_TRY(hw_launch_generic(s->d, s->fp64, descs, prefix, np, s->total_cells[phase], s->ops, s->lds,
                               s->grid, st));
     return HW_OK;
@@ -326,6 +336,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
                     p0.m, p0.method, p0.precision);
+    if (p0.kernel == HW_KERNEL_SPLIT && (count != 1 || p0.method == HW_CONSERVATIVE))
+        return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
     if (p0.precision == HW_BF16 && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel");
     for (int i = 0; i < count; ++i)
@@ -337,7 +349,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     s->precision = p0.precision;
     s->fp64 = (p0.precision == HW_FP64);
     s->elem = s->fp64 ? 8 : 4;
-    s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.taylor_stages == 0;
+    s->split = p0.kernel == HW_KERNEL_SPLIT;
+    s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && !s->split && p0.taylor_stages == 0;
     s->probs.resize(count);
     auto cleanup = [&](hw_status st) {
         hw_destroy(s);
@@ -410,6 +423,32 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         hipMemcpy(s->prefix, s->h_prefix.data(), s->h_prefix.size() * sizeof(int64_t),
                   hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(HW_EHIP, "descriptor upload failed"));
+    if (s->split) {
+        // workspace of the two-kernel form: per output cell p0 | Q | R
+        const int m = p0.m, d = p0.d;
+        const bool simple = p0.method == HW_DISS_SIMPLE || d == 1;
+        const int P0E = simple ? 2 * m + 2 : m + 1, E = simple ? 2 * m + 2 : 2 * m;
+        int stride = 1, ed = 1;
+        for (int i = 0; i < d; ++i) {
+            stride *= P0E;
+            ed *= E;
+        }
+        stride += 2 * ed;
+        const int64_t cells = std::max(s->total_cells[0], s->total_cells[1]);
+        if (hipMalloc(&s->work, (size_t)cells * stride * s->elem) != hipSuccess ||
+            hipMalloc((void**)&s->split_descs, 4 * sizeof(ProblemDesc)) != hipSuccess)
+            return cleanup(fail(HW_ENOMEM, "two-kernel workspace allocation failed"));
+        ProblemDesc sd[4];
+        for (int ph = 0; ph < 2; ++ph)
+            for (int st = 0; st < 2; ++st) {
+                sd[ph * 2 + st] = s->h_descs[(size_t)(ph * 2) * count];
+                sd[ph * 2 + st].split = st + 1;
+                sd[ph * 2 + st].work = s->work;
+                sd[ph * 2 + st].work_stride = stride;
+            }
+        if (hipMemcpy(s->split_descs, sd, sizeof sd, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "descriptor upload failed"));
+    }
     if (count == 1 && p0.method != HW_CONSERVATIVE) {
         // forcing weights: u: tau^(r+2) j!/(2j+r+2)!, v: tau^(r+1) j!/(2j+r+1)!, zero for
         // terms beyond a stage truncation (the term enters stage 2j+r+2 / 2j+r+1)
@@ -484,6 +523,8 @@ void hw_destroy(hw_solver* s)
     if (s->prefix) (void)hipFree(s->prefix);
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
+    if (s->work) (void)hipFree(s->work);
+    if (s->split_descs) (void)hipFree(s->split_descs);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }

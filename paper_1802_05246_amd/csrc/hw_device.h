@@ -42,6 +42,12 @@ struct ProblemDesc {
     //   dissipative: uQ = tau j!/(2j+1)!, uR = j!/(2j+2)!, vQ = j!/(2j)!, vR = j!/(tau (2j+1)!)
     //   conservative: uQ = j!/(2j)! (even sum), uR = tau j!/(2j+1)! (start-up odd sum)
     double cuQ[HW_MAXJ], cuR[HW_MAXJ], cvQ[HW_MAXJ], cvR[HW_MAXJ];
+    // two-kernel form (dissipative): 0 = fused; 1 = interpolate only, writing the
+    // cell's p0 | Q | R blocks to work + cell * work_stride; 2 = time evolution only,
+    // reading them back
+    int split;
+    int work_stride;
+    void* work;
 };
 
 // Forcing of one dissipative half step (u_tt = c^2 Lap u + f): for every output node,

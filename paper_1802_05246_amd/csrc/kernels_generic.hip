@@ -175,6 +175,18 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
     T* Rr = Q + ED;
     T* P0 = Rr + ED; // M^D (full variant) or Pn^D (simple)
 
+    const int P0E = simple ? Pn : M;
+    const int n_p0 = ipow(P0E, D);
+    T* wk = (T*)P.work + cell * (int64_t)P.work_stride; // split form: p0 | Q | R
+    if (P.split == 2) {
+        // time evolution only: the interpolants come from the first kernel
+        for (int e = lane; e < n_p0; e += GW) P0[e] = wk[e];
+        for (int e = lane; e < ED; e += GW) {
+            Q[e] = wk[n_p0 + e];
+            Rr[e] = wk[n_p0 + ED + e];
+        }
+        __syncthreads();
+    } else {
     Corners cr;
     const Geom G = geom_of<D>(P);
     find_corners<D>(G, cell, cr);
@@ -240,12 +252,21 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
         }
         __syncthreads();
     }
+    if (P.split == 1) {
+        // interpolation only: hand p0, Q and R to the second kernel through memory
+        for (int e = lane; e < n_p0; e += GW) wk[e] = P0[e];
+        for (int e = lane; e < ED; e += GW) {
+            wk[n_p0 + e] = Q[e];
+            wk[n_p0 + ED + e] = Rr[e];
+        }
+        return;
+    }
+    }
 
     // time sums at tau = dt/2, one output coefficient per lane
     const int Mu_tot = ipow(M, D), Mv_tot = ipow(m, D);
     T* uo = (T*)P.u_out + cell * Mu_tot;
     T* vo = (T*)P.v_out + cell * Mv_tot;
-    const int P0E = simple ? Pn : M;
     for (int o = lane; o < Mu_tot + Mv_tot; o += GW) {
         const bool is_u = o < Mu_tot;
         const int c = is_u ? o : o - Mu_tot;

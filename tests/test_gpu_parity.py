@@ -388,3 +388,29 @@ def test_tiled_equals_generic(prec):
         assert joint_err(spec, ua, wa, ub, wb) < fp32_tol(3, 6)
     a.close()
     b.close()
+
+
+SPLIT_CASES = [(1, 3, [9], [W.NEUMANN], W.DISS_FULL), (2, 3, [7, 6], [W.PERIODIC, W.DIRICHLET], W.DISS_FULL),
+               (2, 4, [6, 5], [W.DIRICHLET, W.PERIODIC], W.DISS_SIMPLE),
+               (3, 3, [5, 4, 3], [W.PERIODIC, W.NEUMANN, W.DIRICHLET], W.DISS_FULL),
+               (3, 2, [4, 4, 4], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_SIMPLE)]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=lambda c: f"d{c[0]}-m{c[1]}-meth{c[4]}")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_two_kernel_form_equals_fused_bitwise(case, prec):
+    """The two-kernel form (interpolants through memory in the state precision) does
+    the same arithmetic as the fused generic kernel: identical results."""
+    B = _B()
+    d, m, n, bc, meth = case
+    spec = W.make_spec(d, m, n, 0.0, 1.0, 1.3, cfl=0.9, bc=bc, method=meth)
+    u, w = _state(spec, 31 + d + m)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    out = []
+    for kernel in (B.HW_KERNEL_GENERIC, B.HW_KERNEL_SPLIT):
+        s = B.Solver(spec, precision=precision, kernel=kernel)
+        s.set_state(u, w)
+        s.advance(3)
+        out.append(s.get_state())
+        s.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
