@@ -42,9 +42,9 @@ BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "227edf7e37d4a3f5749849ff2d2c98a0373623ca342ea703bedab0c69d8513ed",
-    "fetch_bytes": 8517886028,  # FETCH_SIZE 4159244.2 KiB x 2.0000 (copy: 524303.1 KiB for 1 GiB)
-    "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1.0000 (copy: 1048576.0 KiB for 1 GiB)
+    "source_sha256": "388fbef3ce64bebf66b487021c6f3b595e29c510cbbf2e2fa03c8f3eb3a78edf",
+    "fetch_bytes": 8518450861,  # FETCH_SIZE 4159539.0 KiB x 1048576/524305.5 (copy: 1 GiB read)
+    "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_tiled3d_m3-diss3d_m3_256cube-hbm_bytes.md",
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_tiled3d.hip")
