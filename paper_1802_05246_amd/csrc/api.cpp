@@ -338,8 +338,10 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
                     p0.m, p0.method, p0.precision);
     if (p0.kernel == HW_KERNEL_SPLIT && (count != 1 || p0.method == HW_CONSERVATIVE))
         return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
-    if (p0.precision == HW_BF16 && !tiled_ok)
-        return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel");
+    if (p0.precision == HW_BF16 &&
+        (!tiled_ok || p0.kernel == HW_KERNEL_GENERIC || p0.kernel == HW_KERNEL_SPLIT || p0.taylor_stages != 0))
+        return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel (3-D dissipative full "
+                                     "method, m = 3, exact series)");
     for (int i = 0; i < count; ++i)
         if (ps[i].taylor_stages > 0 && ps[i].method == HW_CONSERVATIVE)
             return fail(HW_EINVAL, "taylor_stages applies to the dissipative method only");
@@ -620,6 +622,7 @@ hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, 
     if (n_orders < 0 || n_orders > HW_MAXF)
         return fail(HW_EINVAL, "n_orders must be in 0..%d", HW_MAXF);
     if (n_orders > 0 && !f_coef) return fail(HW_EINVAL, "null forcing coefficients");
+    if (s->precision == HW_BF16) return fail(HW_EUNSUPPORTED, "no forced steps with BF16 operands");
     if (!s->state_set) return fail(HW_ESTATE, "state not set");
     hipStream_t st = (hipStream_t)stream;
     const int phase = (int)(s->half_steps & 1);

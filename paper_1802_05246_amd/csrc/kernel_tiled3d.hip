@@ -125,7 +125,24 @@ struct Tables {
     T ta[8][TS_KSTEPS][64];
     int tk[8][TS_KSTEPS * 4];
     int tr[8][16];
+    // BF16-operand form (16x16x32 products, 8 operands per lane, k = 8 (lane / 16) + e):
+    //   xb[64][8]        x-pass A operand: opX[l % 16][k] for k < 8, else 0
+    //   tb[8][2][64][8]  class-block A operand, K-block kb: W[l % 16][32 kb + k]
+    //   kb8[8][2][4][8]  LDS offset of input 32 kb + 8 g + e of a class (padding: zero slot)
+    unsigned short xb[64][8];
+    unsigned short tb[8][2][64][8];
+    int kb8[8][2][4][8];
 };
+
+// bf16 bit pattern of x, rounded to nearest even
+inline unsigned short to_bf16(double x)
+{
+    float f = (float)x;
+    unsigned int u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
 
 struct Map1 {
     int j, ghost;
@@ -263,10 +280,21 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
     for (int i = 0; i < 12; ++i) pB[i] = curB[i];
 }
 
-template <typename T, int TY>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// one 16x16x32 product with BF16 operands, FP32 accumulation (same result layout as the
+// FP32 16x16x4 product)
+__device__ inline Mfma<float>::vec mac_bf16(bf16x8 a, bf16x8 b, Mfma<float>::vec c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// BF (float only): the matrix-core stages (x-pass, time sums) take BF16 operands
+template <typename T, int TY, bool BF>
 __global__ void __launch_bounds__(16 * TX * TY)
 k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
 {
+    static_assert(!BF || sizeof(T) == 4, "BF16 operands with FP32 storage only");
     using S = Shared<T, TY>;
     using MF = Mfma<T>;
     constexpr int NT = 16 * TX * TY;
@@ -292,6 +320,18 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     // the padding slot of every cell block reads as zero in the class products
     for (int c = tid; c < NC; c += NT) sh.z[c * ZS + 432] = T(0);
     const T xa0 = tabs->xa[0][lane], xa1 = tabs->xa[1][lane];
+    bf16x8 xb, tb[2];
+    int kb8[2][8];
+    if constexpr (BF) {
+        xb = *(const bf16x8*)tabs->xb[lane];
+        const int p = wave % 8;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            tb[kb] = *(const bf16x8*)tabs->tb[p][kb][lane];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) kb8[kb][e] = tabs->kb8[p][kb][lane >> 4][e];
+        }
+    }
     // every wave keeps CPW parity classes for the whole run, holds their operands in
     // registers (no table loads in the loop) and applies each to GPW groups of 16 cells
     static_assert(NW % 8 == 0 || 8 % NW == 0, "waves and parity classes must tile");
@@ -493,7 +533,35 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
         // ---- 2. x-pass: u on the matrix cores (one edge per wave), v on the VALU ----
-        {
+        if constexpr (BF) {
+            // one 16x16x32 product per edge: lanes 0-15 hold the 8 inputs (s, l_x) of
+            // line j = lane, the other lanes the zero padding of K
+            constexpr int EPW = (NEDGE + NW - 1) / NW;
+            bf16x8 bb[EPW];
+#pragma unroll
+            for (int i = 0; i < EPW; ++i) {
+                const int e = wave + i * NW;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bb[i][q] = (__bf16)0.0f;
+                if (e < NEDGE && lane < 16) {
+                    const int n0 = e % TX + NXL * (e / TX);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        bb[i][q] = (__bf16)sh.nu[(n0 + q / 4) * NUP + (q % 4) + 4 * lane];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < EPW; ++i) {
+                const int e = wave + i * NW;
+                if (e < NEDGE) {
+                    typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+                    acc = mac_bf16(xb, bb[i], acc);
+                    T* dst = sh.xu + e * XUE + (lane & 15);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dst[MF::row(lane, r) * XUR] = acc[r];
+                }
+            }
+        } else {
             // B[k][j] = input (s, l_x = k) of line j = l_y + 4 l_z: nu[node][l_x + 4 j];
             // the operands of all of the wave's edges are read before the products
             constexpr int EPW = (NEDGE + NW - 1) / NW;
@@ -597,7 +665,27 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                 else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + rsc[c][r] * acc[r];
             }
         };
-        if constexpr (CPW == 1) {
+        if constexpr (BF) {
+            static_assert(CPW == 1, "BF16 path: one class per wave");
+            bf16x8 bb[GPW][2];
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) {
+                const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bb[k][kb][e] = (__bf16)zc[kb8[kb][e]];
+            }
+            typename MF::vec acc[GPW];
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) acc[k] = typename MF::vec{T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) acc[k] = mac_bf16(tb[kb], bb[k][kb], acc[k]);
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) epilogue(acc[k], 16 * grp_of(k) + (lane & 15), 0);
+        } else if constexpr (CPW == 1) {
             T bv[GPW][TS_KSTEPS];
 #pragma unroll
             for (int k = 0; k < GPW; ++k) {
@@ -719,7 +807,20 @@ void build_tables(Tables<T>& t)
         }
         for (int ks = 0; ks < TS_KSTEPS; ++ks)
             for (int l = 0; l < 64; ++l) t.ta[p][ks][l] = (T)W[l % 16][4 * ks + l / 16];
+        for (int kb = 0; kb < 2; ++kb)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 8; ++e) {
+                    const int k = 32 * kb + 8 * (l / 16) + e;
+                    t.tb[p][kb][l][e] = to_bf16(k < TS_KSTEPS * 4 ? W[l % 16][k] : 0.0);
+                    if (l < 4 * 16 && l % 16 == 0)
+                        t.kb8[p][kb][l / 16][e] = k < TS_KSTEPS * 4 ? t.tk[p][k] : 432;
+                }
     }
+    for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * (l / 16) + e;
+            t.xb[l][e] = to_bf16(k < 8 ? opX(l % 16, k) : 0.0);
+        }
 }
 
 template <typename T>
@@ -741,7 +842,7 @@ const Tables<T>* device_tables(hipError_t* err)
     return dev;
 }
 
-template <typename T, int TY>
+template <typename T, int TY, bool BF = false>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
     constexpr int NT = 16 * TX * TY;
@@ -749,7 +850,7 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
     const Tables<T>* tabs = device_tables<T>(&e);
     if (!tabs) return e;
     const size_t lds = sizeof(Shared<T, TY>);
-    auto kern = k_tiled3d_m3<T, TY>;
+    auto kern = k_tiled3d_m3<T, TY, BF>;
     e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int tz = 64;
@@ -763,7 +864,7 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
 
 bool hw_tiled_supported(int d, int m, int method, int precision)
 {
-    return d == 3 && m == 3 && method == 0 && (precision == 0 || precision == 1);
+    return d == 3 && m == 3 && method == 0 && (precision == 0 || precision == 1 || precision == 2);
 }
 
 hipError_t hw_tiled_prepare(int precision)
@@ -779,5 +880,6 @@ hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st)
     for (int i = 0; i < 3; ++i)
         if (!(a.lam2[i] >= 2.5e-7) || a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
     if (precision == 0) return launch<double, 4>(a, st);
+    if (precision == 2) return launch<float, 8, true>(a, st);
     return launch<float, 8>(a, st);
 }

@@ -414,3 +414,29 @@ def test_two_kernel_form_equals_fused_bitwise(case, prec):
         out.append(s.get_state())
         s.close()
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+BF16_U = 2.0 ** -9  # unit roundoff of a BF16 operand
+
+
+@pytest.mark.parametrize("n,bc", TILED_CASES[:3], ids=[f"{'x'.join(map(str, n))}-bc{''.join(map(str, b))}" for n, b in TILED_CASES[:3]])
+def test_tiled_bf16_operands_match_oracle(n, bc):
+    """The BF16-operand form of the tiled kernel (FP32 storage and accumulation, BF16
+    operands of the matrix-core stages) against the oracle, in the polynomial L2 norm
+    of the joint [u, tau v]: the error is that of rounding the operands to 8-bit
+    mantissas (reported, not a parity claim at FP32 level)."""
+    B = _B()
+    spec = W.make_spec(3, 3, n, 0.0, [1.0, 0.8, 0.9], 1.2, cfl=0.85, bc=bc, method=W.DISS_FULL)
+    u, w = _state(spec, 31 + sum(n))
+    s = B.Solver(spec, precision=B.HW_BF16, kernel=B.HW_KERNEL_TILED)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    n_half = 4
+    s.half_steps(n_half)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    s.close()
+    ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
+    err = joint_err(spec, gu, gw, ou, ow)
+    tol = 20.0 * BF16_U * n_half
+    _log(f"[bf16] n={n} bc={bc} joint rel err {err:.3e} (tol {tol:.3g})")
+    assert err <= tol
