@@ -1,6 +1,6 @@
 """Benchmark: cell-updates/s of the 3-D dissipative Hermite method, m = 3, on the
 256^3 periodic unit cube with 8 Gaussian pulses (lambda = c dt/h = 0.9), FP32 form
-against the FP64 form, with the L2 error reached.
+against the FP64 form (and the BF16-operand form), with the L2 error reached.
 
 One step = one full time step = two half steps over all 256^3 cells (two
 cell-updates per node).  The timed region is `hw_advance(K)`: a hipGraph of 2K
@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--kernel", choices=["auto", "generic", "tiled"], default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-operand form")
     ap.add_argument("--cpu-layers", type=int, default=40,
                     help="z-layers of the grid in the oracle's timed sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -233,6 +234,20 @@ def main():
         else:
             err64, rel64, _ = l2_errors(torch, W, w, s64, (K64 + Wm) * spec.dt)
     s64.close()
+
+    # BF16-operand form (FP32 storage and accumulation), reported beside the others
+    bf16 = None
+    if not args.no_bf16:
+        log(f"[bench] bf16-operand form: warmup {Wm}, timed {K} steps")
+        s16, el16, ev16 = run_form(torch, B, W, w, B.HW_BF16, B.HW_KERNEL_TILED, K, Wm)
+        bf16 = {"value": cells_per_step * K / el16, "unit": "cell-updates/s", "steps": K,
+                "ms_per_step": el16 / K * 1e3, "kernel_avg_ms": ev16 / (2 * K)}
+        if not args.no_error:
+            err16, rel16, val16 = l2_errors(torch, W, w, s16, t_final)
+            bf16.update({"l2_abs": err16, "l2_rel": rel16})
+            if K64 == K:
+                bf16["vs_fp64_rel"] = float(torch.linalg.norm(val16 - val64) / torch.linalg.norm(val64))
+        s16.close()
     del w
     torch.cuda.empty_cache()
 
@@ -270,6 +285,7 @@ def main():
         "fp64_form": {"value": rate64, "unit": "cell-updates/s", "steps": K64,
                       "ms_per_step": el64 / K64 * 1e3, "speedup_fp32_over_fp64": rate32 / rate64,
                       "kernel_avg_ms": ev64 / (2 * K64)},
+        "bf16_form": bf16,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
