@@ -190,7 +190,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the Hermite half step shards by slabs with a "
-              "one-node halo exchange, which this build does not implement; use --gpus 1",
+              "one-node halo exchange, which this library does not implement; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     import torch
