@@ -1,11 +1,15 @@
 // LDS-tiled half-step kernel for the 3-D dissipative method with the modified first
-// step (Sec. 3.3, d = 3), nodal degree m = 3, element type T = float or double.
+// step (Sec. 3.3, d = 3), nodal degree m = 3, element type T = float or double, and a
+// BF16-operand form (FP32 storage and accumulation, BF16 operands of the matrix-core
+// stages).
 //
-// A workgroup owns a column of 4 x TY cells and walks it upwards in z, one node
-// layer of the input grid at a time.  Per layer:
-//   1. the (4+1) x (TY+1) nodes of the layer (u: 64, v: 27 coefficients) are
-//      staged in LDS; ghost nodes outside non-periodic walls are mirrored with the
-//      odd / even coefficient signs of Sec. 3.1.3;
+// A workgroup owns a column of 4 x TY cells (TY = 8 for float, 4 for double) and walks
+// it upwards in z, one node layer of the input grid at a time.  Per layer:
+//   1. the (4+1) x (TY+1) nodes of the layer (u: 64, v: 27 coefficients), loaded into
+//      registers during the previous layer, are stashed in LDS; ghost nodes outside
+//      non-periodic walls are mirrored with the odd / even coefficient signs of
+//      Sec. 3.1.3; the cell layer finished in the previous pass is stored and the loads
+//      of the next node layer are issued;
 //   2. x-pass, once per x-edge of the layer (shared by the cells on both sides), on
 //      the matrix cores: the 16 stacked rows [H_3 rows 0..3 | rows 2..7 of H_3 times
 //      (k+2)(k+1) | H_{m-1} on l <= 2] times the 8 inputs (side s, l_x) of the 16
@@ -23,8 +27,8 @@
 //      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!, j = |b|, k = a + 2b.  Only k with
 //      the parity of a enter, so the sums split into 8 parity classes, each a dense
 //      (<= 16 outputs) x (27 Q + 27 R inputs) block applied to 16 cells at a time on
-//      the matrix cores;
-//   5. the outputs of the cells are written back coalesced, row by row.
+//      the matrix cores; the outputs are staged in LDS for the coalesced 16-byte
+//      stores of step 1 of the next pass.
 // Every node of the input grid is read from HBM once per column (plus the one-node
 // halo shared with the neighbouring columns), every output node written once.
 #include <hip/hip_runtime.h>
