@@ -659,14 +659,18 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product.  The
         //         wave's CPW x GPW products run as interleaved independent chains, all B
         //         operands read first ----
+        // lanes 0-31 hold u rows and lanes 32-63 v rows of a class block: the target and
+        // the p0 term are selected per lane, so both kinds share one instruction stream
         auto epilogue = [&](const typename MF::vec& acc, int cell, int c) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int dst = rdst[c][r];
-                if (dst < 0) continue;
-                const int ai = dst & 0xffff;
-                if (dst >> 16) ov_base[cell * 27 + ai] = rsc[c][r] * acc[r];
-                else ou_base[cell * OUS + ai] = sh.p0[cell * P0S + ai] + rsc[c][r] * acc[r];
+                const bool used = dst >= 0, isv = dst >= (1 << 16);
+                const int ai = used ? (dst & 0xffff) : 0;
+                const T pz = sh.p0[cell * P0S + (isv ? 0 : ai)];
+                const T val = rsc[c][r] * acc[r] + (isv ? T(0) : pz);
+                const int o = isv ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
+                if (used) ou_base[o] = val;
             }
         };
         if constexpr (BF) {
