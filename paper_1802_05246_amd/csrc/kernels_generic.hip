@@ -159,8 +159,30 @@ __device__ void gather(const Geom& P, const Corners& cr, const T* __restrict__ d
     }
 }
 
+// Tables of the current problem staged in LDS (ahead of the cell scratch): the block of
+// 1-D operators of its m (H_m, scaled second-derivative rows, H_{m-1} on u and on v)
+// and the time-sum weights F[3][8][8], cuQ, cuR, cvQ, cvR (FP64).
+constexpr int TAB_OPS = 680; // >= operator block of m = 6: 14*14 + 2*12*14 + 12*12
+constexpr int TAB_W = 3 * (HW_MAXM + 2) * (HW_MAXM + 2) + 4 * HW_MAXJ;
+__host__ __device__ constexpr int ops_len(int m)
+{
+    return (2 * m + 2) * (2 * m + 2) + 2 * m * (2 * m + 2) + (m >= 1 ? 2 * m * (2 * m + 2) + 4 * m * m : 0);
+}
+template <typename T>
+__host__ __device__ constexpr size_t tab_bytes()
+{
+    return ((TAB_OPS * sizeof(T) + 15) / 16) * 16 + TAB_W * sizeof(double);
+}
+static_assert(ops_len(HW_MAXM) <= TAB_OPS, "operator block must fit its LDS region");
+
+struct WTab {
+    const double* F; // [3][HW_MAXM + 2][HW_MAXM + 2]
+    const double *cuQ, *cuR, *cvQ, *cvR;
+    __device__ double f(int i, int a, int b) const { return F[(i * (HW_MAXM + 2) + a) * (HW_MAXM + 2) + b]; }
+};
+
 template <typename T, int D>
-__device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64_t cell, T* sm,
+__device__ void diss_cell(const ProblemDesc& P, const T* lops, const WTab& WT, int64_t cell, T* sm,
                           int lane, const ForcingArgs& FA)
 {
     const int m = P.m, M = m + 1, Pn = 2 * m + 2, K = Pn, Kv = 2 * m;
@@ -194,10 +216,10 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
     gather<T, D>(G, cr, (const T*)P.v_in, m, Xv, lane);
     __syncthreads();
 
-    const T* full = ops + P.op.full;
-    const T* d2 = ops + P.op.d2;
-    const T* tr = ops + P.op.trunc;
-    const T* vop = ops + P.op.vop;
+    const T* full = lops;
+    const T* d2 = lops + (P.op.d2 - P.op.full);
+    const T* tr = lops + (P.op.trunc - P.op.full);
+    const T* vop = lops + (P.op.vop - P.op.full);
     const T* o3[3];
     int R3[3];
 
@@ -287,15 +309,15 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
             }
             acc = P0[off];
         }
-        const double* cq = is_u ? P.cuQ : P.cvQ;
-        const double* crr = is_u ? P.cuR : P.cvR;
+        const double* cq = is_u ? WT.cuQ : WT.cvQ;
+        const double* crr = is_u ? WT.cuR : WT.cvR;
         for (int b2 = 0; b2 <= bmax[2]; ++b2)
             for (int b1 = 0; b1 <= bmax[1]; ++b1)
                 for (int b0 = 0; b0 <= bmax[0]; ++b0) {
                     const int j = b0 + b1 + b2;
-                    double g = P.F[0][a[0]][b0];
-                    if (D > 1) g *= P.F[1][a[1]][b1];
-                    if (D > 2) g *= P.F[2][a[2]][b2];
+                    double g = WT.f(0, a[0], b0);
+                    if (D > 1) g *= WT.f(1, a[1], b1);
+                    if (D > 2) g *= WT.f(2, a[2], b2);
                     const int idx = (a[0] + 2 * b0) + E * ((a[1] + 2 * b1) + E * (a[2] + 2 * b2));
                     acc += T(g * cq[j]) * Q[idx] + T(g * crr[j]) * Rr[idx];
                 }
@@ -330,9 +352,9 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
             for (int b2 = 0; b2 <= bmax[2]; ++b2)
                 for (int b1 = 0; b1 <= bmax[1]; ++b1)
                     for (int b0 = 0; b0 <= bmax[0]; ++b0) {
-                        double g = P.F[0][a[0]][b0];
-                        if (D > 1) g *= P.F[1][a[1]][b1];
-                        if (D > 2) g *= P.F[2][a[2]][b2];
+                        double g = WT.f(0, a[0], b0);
+                        if (D > 1) g *= WT.f(1, a[1], b1);
+                        if (D > 2) g *= WT.f(2, a[2], b2);
                         const int idx = (a[0] + 2 * b0) + Kv * ((a[1] + 2 * b1) + Kv * (a[2] + 2 * b2));
                         acc += T(g * w[b0 + b1 + b2]) * bufA[idx];
                     }
@@ -343,7 +365,7 @@ __device__ void diss_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
 }
 
 template <typename T, int D>
-__device__ void cons_cell(const ProblemDesc& P, const T* __restrict__ ops, int64_t cell, T* sm,
+__device__ void cons_cell(const ProblemDesc& P, const T* lops, const WTab& WT, int64_t cell, T* sm,
                           int lane)
 {
     const int m = P.m, M = m + 1, Pn = 2 * m + 2, K = Pn;
@@ -362,7 +384,7 @@ __device__ void cons_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
     gather<T, D>(G, cr, (const T*)P.u_in, M, Xu, lane);
     if (startup) gather<T, D>(G, cr, (const T*)P.v_in, M, Xv, lane);
     __syncthreads();
-    const T* full = ops + P.op.full;
+    const T* full = lops;
     const T* o3[3] = {full, full, full};
     const int R3[3] = {Pn, Pn, Pn};
     tensor_apply<T, D>(Xu, K, o3, R3, bufA, bufB, A, T(1), false, lane);
@@ -384,12 +406,12 @@ __device__ void cons_cell(const ProblemDesc& P, const T* __restrict__ ops, int64
             for (int b1 = 0; b1 <= bmax[1]; ++b1)
                 for (int b0 = 0; b0 <= bmax[0]; ++b0) {
                     const int j = b0 + b1 + b2;
-                    double g = P.F[0][a[0]][b0];
-                    if (D > 1) g *= P.F[1][a[1]][b1];
-                    if (D > 2) g *= P.F[2][a[2]][b2];
+                    double g = WT.f(0, a[0], b0);
+                    if (D > 1) g *= WT.f(1, a[1], b1);
+                    if (D > 2) g *= WT.f(2, a[2], b2);
                     const int idx = (a[0] + 2 * b0) + Pn * ((a[1] + 2 * b1) + Pn * (a[2] + 2 * b2));
-                    acc += T(g * P.cuQ[j]) * A[idx];
-                    if (startup) acc += T(g * P.cuR[j]) * B[idx];
+                    acc += T(g * WT.cuQ[j]) * A[idx];
+                    if (startup) acc += T(g * WT.cuR[j]) * B[idx];
                 }
         if (P.variant == HWV_CONS) uo[c] = T(2) * acc - uold[cell * Mu_tot + c];
         else uo[c] = acc;
@@ -402,7 +424,14 @@ k_half_step(const ProblemDesc* __restrict__ descs, const int64_t* __restrict__ p
             int64_t total, const T* __restrict__ ops, ForcingArgs FA)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
+    T* lops = reinterpret_cast<T*>(smem_raw);
+    double* lw = reinterpret_cast<double*>(smem_raw + ((TAB_OPS * sizeof(T) + 15) / 16) * 16);
+    T* sm = reinterpret_cast<T*>(smem_raw + tab_bytes<T>());
+    const WTab WT{lw, lw + 3 * (HW_MAXM + 2) * (HW_MAXM + 2), lw + 3 * (HW_MAXM + 2) * (HW_MAXM + 2) + HW_MAXJ,
+                  lw + 3 * (HW_MAXM + 2) * (HW_MAXM + 2) + 2 * HW_MAXJ,
+                  lw + 3 * (HW_MAXM + 2) * (HW_MAXM + 2) + 3 * HW_MAXJ};
+    const int lane = threadIdx.x;
+    int cur = -1;
     for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
         int lo = 0, hi = nprob;
         while (hi - lo > 1) {
@@ -411,9 +440,27 @@ k_half_step(const ProblemDesc* __restrict__ descs, const int64_t* __restrict__ p
             else hi = mid;
         }
         const ProblemDesc& P = descs[lo];
+        if (lo != cur) {
+            // stage the problem's operators and weights (the previous cell is finished:
+            // the loop ends with a barrier)
+            const T* src = ops + P.op.full;
+            const int len = ops_len(P.m);
+            for (int i = lane; i < len; i += GW) lops[i] = src[i];
+            const double* F = &P.F[0][0][0];
+            for (int i = lane; i < 3 * (HW_MAXM + 2) * (HW_MAXM + 2); i += GW) lw[i] = F[i];
+            for (int i = lane; i < HW_MAXJ; i += GW) {
+                const int o = 3 * (HW_MAXM + 2) * (HW_MAXM + 2);
+                lw[o + i] = P.cuQ[i];
+                lw[o + HW_MAXJ + i] = P.cuR[i];
+                lw[o + 2 * HW_MAXJ + i] = P.cvQ[i];
+                lw[o + 3 * HW_MAXJ + i] = P.cvR[i];
+            }
+            __syncthreads();
+            cur = lo;
+        }
         const int64_t cell = g - prefix[lo];
-        if (P.variant <= HWV_DISS_SIMPLE) diss_cell<T, D>(P, ops, cell, sm, threadIdx.x, FA);
-        else cons_cell<T, D>(P, ops, cell, sm, threadIdx.x);
+        if (P.variant <= HWV_DISS_SIMPLE) diss_cell<T, D>(P, lops, WT, cell, sm, lane, FA);
+        else cons_cell<T, D>(P, lops, WT, cell, sm, lane);
         __syncthreads();
     }
 }
@@ -529,7 +576,7 @@ size_t hw_generic_lds_bytes(int d, int m, int variant, int elem_size)
     } else {
         n = 6 * pw(K, d);
     }
-    return n * (size_t)elem_size;
+    return n * (size_t)elem_size + (elem_size == 8 ? tab_bytes<double>() : tab_bytes<float>());
 }
 
 size_t hw_energy_lds_bytes(int d, int m)
