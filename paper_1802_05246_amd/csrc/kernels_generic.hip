@@ -61,7 +61,18 @@ __device__ void tensor_apply(const T* in, int K, const T* const* ops, const int*
             const T* s = src + lo + hi * stride * Kd;
             const T* o = op + r * Kd;
             T a = T(0);
-            for (int k = 0; k < Kd; ++k) a += o[k] * s[k * stride];
+            // four terms per round: their LDS reads are in flight together
+            int k = 0;
+            for (; k + 4 <= Kd; k += 4) {
+                const T o0 = o[k], o1 = o[k + 1], o2 = o[k + 2], o3 = o[k + 3];
+                const T s0 = s[k * stride], s1 = s[(k + 1) * stride], s2 = s[(k + 2) * stride],
+                        s3 = s[(k + 3) * stride];
+                a += o0 * s0;
+                a += o1 * s1;
+                a += o2 * s2;
+                a += o3 * s3;
+            }
+            for (; k < Kd; ++k) a += o[k] * s[k * stride];
             if (last) {
                 if (accumulate) dst[e] += scale * a;
                 else dst[e] = scale * a;
