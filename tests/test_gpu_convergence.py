@@ -1,0 +1,155 @@
+"""End-to-end accuracy through the library: convergence rates against exact solutions
+(Sec. 3.4 / Sec. 6 design orders), the conservation experiment of Sec. 5.2, and the
+conservative 2-D workload at its full size."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1802_05246_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _B():
+    from paper_1802_05246_amd import binding as B
+    B.lib()
+    return B
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_standing_waves_1d_rate(m):
+    """1-D periodic standing waves at c dt / h = 0.8: order 2m - 1 (dissipative)."""
+    B = _B()
+    errs = []
+    ns = (48, 64, 96)
+    for n in ns:
+        w = W.c1_1d(n=n, m=m, cfl=0.8)
+        s = B.Solver(w.spec, precision=B.HW_FP64)
+        s.set_state(w.u0, w.v0)
+        s.advance(w.steps)
+        u, _ = s.get_state()
+        s.close()
+        val = u[:, 0].cpu().numpy()
+        ex = w.exact(w.steps * w.spec.dt)
+        errs.append(W.nodal_l2(w.spec, val, ex))
+    rate = math.log(errs[-2] / errs[-1]) / math.log(ns[-1] / ns[-2])
+    _log(f"[conv 1-D m={m}] errors {errs} rate {rate:.2f}")
+    assert rate >= 2 * m - 1 - 0.3
+
+
+def _c4_error(B, n, steps, precision):
+    w = W.c4_3d(n=n, device="cuda")
+    s = B.Solver(w.spec, precision=precision)
+    s.set_state(w.u0, w.v0)
+    s.advance(steps)
+    u, _ = s.get_state()
+    s.close()
+    val = u[:, 0]
+    pts = torch.as_tensor(w.spec.points(W.PRIMAL), device="cuda")
+    ex = torch.empty_like(val)
+    chunk = 1 << 20
+    t = steps * w.spec.dt
+    for a in range(0, pts.shape[0], chunk):
+        ex[a:a + chunk] = w.exact(t, points=pts[a:a + chunk], xp=torch)
+    h3 = w.spec.h(0) ** 3
+    return math.sqrt(h3 * float(((val - ex) ** 2).sum())), t
+
+
+def test_pulses_3d_tiled_rate():
+    """The 3-D benchmark problem (8 Gaussian pulses, m = 3, c dt / h = 0.9) through the
+    tiled kernel on 64^3, 128^3 and 256^3 to the same final time, against the exact
+    radial solution: the error falls at the dissipative order 2m - 1 = 5 (slope fitted over the
+    fourfold refinement)."""
+    B = _B()
+    errs = []
+    for n, steps in ((64, 4), (128, 8), (256, 16)):
+        e, t = _c4_error(B, n, steps, B.HW_FP64)
+        errs.append(e)
+        _log(f"[conv 3-D] n={n} t={t:.4f} L2 error {e:.3e}")
+    rate = math.log(errs[0] / errs[-1]) / math.log(4.0)
+    _log(f"[conv 3-D] rate {rate:.2f} (pairwise {math.log2(errs[0] / errs[1]):.2f}, "
+         f"{math.log2(errs[1] / errs[2]):.2f})")
+    assert abs(rate - 5) < 0.3
+
+
+def _oracle_drift(spec, up, ud, steps, every):
+    """Largest relative energy change of the FP64 oracle on the same run, sampled at the
+    same half steps as the library run below."""
+    import oracle
+    p = oracle.make_problem(spec.d, spec.m, spec.n, spec.xl, spec.xr, spec.c, spec.dt,
+                            spec.bc, spec.method, spec.taylor_stages)
+    new = oracle.cons_half(p, W.PRIMAL, ud, up)
+    e0 = oracle.cons_energy(p, W.DUAL, ud, new, up)
+    up = new
+    ud = oracle.cons_half(p, W.DUAL, up, ud)
+    worst = 0.0
+    for k in range(steps):
+        up = oracle.cons_half(p, W.PRIMAL, ud, up)
+        new = oracle.cons_half(p, W.DUAL, up, ud)
+        if (k + 1) % every == 0:
+            worst = max(worst, abs(oracle.cons_energy(p, W.PRIMAL, up, new, ud) - e0) / abs(e0))
+        ud = new
+    return worst
+
+
+@pytest.mark.parametrize("m", [1, 3, 5])
+@pytest.mark.parametrize("data", ["smooth", "random"])
+def test_conservation_long_run_1d(m, data):
+    """The conservation experiment of Sec. 5.2, shortened from 10^6 to 2 * 10^4 steps:
+    periodic [-pi, pi], h = 2 pi / 30, dt = h / 2, u = sin(x) cos(t) or coefficients drawn
+    from U(0, 1) on both time levels; the energy is sampled every 100 steps.  Only rounding
+    moves it, more for larger m (the paper's observation; 1e-13 at m = 1 up to 1e-4
+    relative at m = 5 for the smooth data, in FP64).  The library's drift must stay within
+    ten times the FP64 oracle's on the same run."""
+    B = _B()
+    steps, every = 20000, 100
+    spec = W.make_spec(1, m, 30, -math.pi, math.pi, 1.0, cfl=0.5, bc=W.PERIODIC,
+                       method=W.CONSERVATIVE)
+    if data == "smooth":
+        def level(grid, t):
+            return W.separable_nodal(spec, grid, m + 1, [
+                lambda i, x, L, h: W.sine_derivs(x, 1.0, 0.0, L, h) * math.cos(t)])
+        u0, uh = level(W.PRIMAL, 0.0), level(W.DUAL, 0.5 * spec.dt)
+    else:
+        rng = np.random.default_rng(1852 + m)
+        u0 = rng.uniform(0.0, 1.0, (spec.nodes(W.PRIMAL), m + 1))
+        uh = rng.uniform(0.0, 1.0, (spec.nodes(W.DUAL), m + 1))
+    s = B.Solver(spec, precision=B.HW_FP64)
+    s.set_state(u0, uh)
+    s.half_steps(1)
+    e0 = s.energy()
+    s.half_steps(1)
+    B.hw_prepare_advance(s.h, every)
+    worst = 0.0
+    for _ in range(steps // every):
+        s.advance(every)
+        worst = max(worst, abs(s.energy() - e0) / abs(e0))
+    s.close()
+    ref = _oracle_drift(spec, u0, uh, steps, every)
+    _log(f"[conservation 1-D m={m} {data}] E0 {e0:.6e} largest relative change over {steps} "
+         f"steps: library {worst:.2e}, oracle {ref:.2e}")
+    assert worst <= 10.0 * ref + 1e-12
+
+
+def test_conservative_full_size_accuracy():
+    """2048^2, m = 4, Dirichlet, c dt = h (the conservative 2-D workload): 200 steps from
+    the exact time levels stay on the exact standing wave (rate 2m + 2 at lambda = 1,
+    Sec. 5.3, so only rounding is left at this resolution)."""
+    B = _B()
+    w = W.c3_2d()
+    for prec, name, tol in ((B.HW_FP64, "fp64", 1e-11), (B.HW_FP32, "fp32", 1e-4)):
+        s = B.Solver(w.spec, precision=prec)
+        s.set_state(w.u0, w.u_half)
+        s.advance(200)
+        t = s.time()
+        u, _ = s.get_state()
+        s.close()
+        err = W.nodal_l2(w.spec, u[:, 0].cpu().numpy(), w.exact(t))
+        _log(f"[c3 2048^2 m=4] {name}: t {t:.5f} nodal L2 error {err:.3e}")
+        assert err <= tol
