@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 #include <mutex>
 
 #include "hermite_tables.h"
@@ -197,12 +198,12 @@ __device__ inline T sym(Op op, int row, int parity, const T* E, const T* O, T ac
 //   Ay[ky][lz <= 2] = f (l_x/2)^2 H2t_y d2_x + f (l_y/2)^2 d2_y H2t_x   (z operator H_2),
 //   By[ky][lz <= 3] = f (l_z/2)^2 H2t_y H2t_x                         (z operator d2),
 //   Cy[ky][lz <= 2] = f tau H2_y H2_x v.
-// The z-pass combines the previous layer (pA, pB, pC, side s = 0) with this one
-// (side s = 1) and stores tau S Q and S R of the cell (S_z(k_z) applied last).
+// yz_y computes this layer's y-pass (cA: 9 of its 16 entries, cB, cC); yz_z combines the
+// previous layer (pA, pB, pC, side s = 0) with this one (side s = 1), stores tau S Q and
+// S R of the cell (S_z(k_z) applied last) and moves this layer's results into pA, pB, pC.
 template <int KH, typename T>
-__device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* xv1, int kx, bool emit,
-                             T (&pA)[16], T (&pB)[12], T (&pC)[9], T* zc, T l2x, T l2y, T l2z,
-                             const T (&sz)[3], T tau)
+__device__ inline void yz_y(const T* xu0, const T* xu1, const T* xv0, const T* xv1, int kx,
+                            T (&cA)[16], T (&cB)[12], T (&cC)[9], T l2x, T l2y, T l2z, T tau)
 {
     const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
     T fx[3], fy[3], fb[3], fc[3];
@@ -215,7 +216,6 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
         fb[j] = f * l2z;
         fc[j] = f * tau;
     }
-    T curA[9], curB[12], curC[9];
 #pragma unroll
     for (int lz = 0; lz < 4; ++lz) {
         T Eh[4], Oh[4];
@@ -241,13 +241,19 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
                 const int ky = KH + j;
                 const T ax_ = sym<3>(opH2, ky, ky, Ed, Od);
                 const T ay_ = sym<4>(opD2, ky, ky + 2, Eh, Oh);
-                curA[j + 3 * lz] = fx[j] * ax_ + fy[j] * ay_;
-                curC[j + 3 * lz] = fc[j] * sym<3>(opH2, ky, ky, Eq, Oq);
+                cA[j + 3 * lz] = fx[j] * ax_ + fy[j] * ay_;
+                cC[j + 3 * lz] = fc[j] * sym<3>(opH2, ky, ky, Eq, Oq);
             }
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) curB[j + 3 * lz] = fb[j] * sym<3>(opH2, KH + j, KH + j, Eh, Oh);
+        for (int j = 0; j < 3; ++j) cB[j + 3 * lz] = fb[j] * sym<3>(opH2, KH + j, KH + j, Eh, Oh);
     }
+}
+
+template <int KH, typename T>
+__device__ inline void yz_z(bool emit, int kx, T (&pA)[16], T (&pB)[12], T (&pC)[9], const T (&cA)[16],
+                            const T (&cB)[12], const T (&cC)[9], T* zc, const T (&sz)[3])
+{
     if (emit) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -255,15 +261,15 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
             T EA[3], OA[3], EC[3], OC[3], EB[4], OB[4];
 #pragma unroll
             for (int lz = 0; lz < 3; ++lz) {
-                EA[lz] = pA[j + 3 * lz] + curA[j + 3 * lz];
-                OA[lz] = pA[j + 3 * lz] - curA[j + 3 * lz];
-                EC[lz] = pC[j + 3 * lz] + curC[j + 3 * lz];
-                OC[lz] = pC[j + 3 * lz] - curC[j + 3 * lz];
+                EA[lz] = pA[j + 3 * lz] + cA[j + 3 * lz];
+                OA[lz] = pA[j + 3 * lz] - cA[j + 3 * lz];
+                EC[lz] = pC[j + 3 * lz] + cC[j + 3 * lz];
+                OC[lz] = pC[j + 3 * lz] - cC[j + 3 * lz];
             }
 #pragma unroll
             for (int lz = 0; lz < 4; ++lz) {
-                EB[lz] = pB[j + 3 * lz] + curB[j + 3 * lz];
-                OB[lz] = pB[j + 3 * lz] - curB[j + 3 * lz];
+                EB[lz] = pB[j + 3 * lz] + cB[j + 3 * lz];
+                OB[lz] = pB[j + 3 * lz] - cB[j + 3 * lz];
             }
 #pragma unroll
             for (int kz = 0; kz < 6; ++kz) {
@@ -277,11 +283,50 @@ __device__ inline void yz_rq(const T* xu0, const T* xu1, const T* xv0, const T* 
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        pA[i] = curA[i];
-        pC[i] = curC[i];
+        pA[i] = cA[i];
+        pC[i] = cC[i];
     }
 #pragma unroll
-    for (int i = 0; i < 12; ++i) pB[i] = curB[i];
+    for (int i = 0; i < 12; ++i) pB[i] = cB[i];
+}
+
+// p0 (centre rows) of one (cell, k_x): y-pass Y[ky][lz] = sum_{s,ly} H3[ky][s,ly]
+// xu[e_s][kx][ly + 4 lz] of this layer, z-pass with the previous layer's (pA)
+template <typename T>
+__device__ inline void p0_y(const T* xu0, const T* xu1, int kx, T (&cur)[16])
+{
+#pragma unroll
+    for (int lz = 0; lz < 4; ++lz) {
+        T E[4], O[4];
+#pragma unroll
+        for (int ly = 0; ly < 4; ++ly) {
+            const T a0 = xu0[kx * XUR + ly + 4 * lz], a1 = xu1[kx * XUR + ly + 4 * lz];
+            E[ly] = a0 + a1;
+            O[ly] = a0 - a1;
+        }
+#pragma unroll
+        for (int ky = 0; ky < 4; ++ky) cur[ky + 4 * lz] = sym<4>(opH3, ky, ky, E, O);
+    }
+}
+
+template <typename T>
+__device__ inline void p0_z(bool emit, T (&pA)[16], const T (&cur)[16], T* dst)
+{
+    if (emit) {
+#pragma unroll
+        for (int ky = 0; ky < 4; ++ky) {
+            T E[4], O[4];
+#pragma unroll
+            for (int lz = 0; lz < 4; ++lz) {
+                E[lz] = pA[ky + 4 * lz] + cur[ky + 4 * lz];
+                O[lz] = pA[ky + 4 * lz] - cur[ky + 4 * lz];
+            }
+#pragma unroll
+            for (int kz = 0; kz < 4; ++kz) dst[4 * ky + 16 * kz] = sym<4>(opH3, kz, kz, E, O);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) pA[i] = cur[i];
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -525,6 +570,66 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         }
     };
 
+    // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product.  The
+    //         wave's CPW x GPW products run as interleaved independent chains, all B
+    //         operands read first.  Lanes 0-31 hold u rows and lanes 32-63 v rows of a
+    //         class block: the target and the p0 term are selected per lane, so both
+    //         kinds share one instruction stream ----
+    using Acc = typename MF::vec;
+    using BOp = typename std::conditional<BF, bf16x8, T>::type;
+    constexpr int NB = BF ? 2 : TS_KSTEPS; // operand registers per (class, cell group)
+    auto ts_load = [&](BOp (&bv)[CPW][GPW][NB]) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) {
+                const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
+                if constexpr (BF) {
+#pragma unroll
+                    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) bv[c][k][kb][e] = (__bf16)zc[kb8[kb][e]];
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[c][k][ks] = zc[tkv[c][ks]];
+                }
+            }
+    };
+    auto ts_mac = [&](const BOp (&bv)[CPW][GPW][NB], Acc (&acc)[CPW][GPW]) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) acc[c][k] = Acc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < NB; ++ks)
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                for (int k = 0; k < GPW; ++k) {
+                    if constexpr (BF)
+                        acc[c][k] = mac_bf16(tb[ks], bv[c][k][ks], acc[c][k]);
+                    else
+                        acc[c][k] = MF::mac(tav[c][ks], bv[c][k][ks], acc[c][k]);
+                }
+    };
+    auto ts_out = [&](const Acc (&acc)[CPW][GPW]) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int k = 0; k < GPW; ++k) {
+                const int cell = 16 * grp_of(k) + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int dst = rdst[c][r];
+                    const bool used = dst >= 0, isv = dst >= (1 << 16);
+                    const int ai = used ? (dst & 0xffff) : 0;
+                    const T pz = sh.p0[cell * P0S + (isv ? 0 : ai)];
+                    const T val = rsc[c][r] * acc[c][k][r] + (isv ? T(0) : pz);
+                    const int o = isv ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
+                    if (used) ou_base[o] = val;
+                }
+            }
+    };
     // Per node layer: stash it, store the cell layer finished in the previous pass,
     // issue the loads of the next node layer, then the x-, y/z- and time passes.  The
     // stores go out before the loads, so the in-order memory counter that the next
@@ -615,129 +720,29 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
         const bool emit = step > 0;
         const T* xu0 = sh.xu + e0 * XUE;
         const T* xu1 = sh.xu + e1 * XUE;
+        const T* xv0 = sh.xv + e0 * XVE;
+        const T* xv1 = sh.xv + e1 * XVE;
+        T cA[16], cB[12], cC[9];
         if (is_p0) {
-            // p0: Y[ky][lz] = sum_{s,ly} H3[ky][s,ly] xu[e_s][kx][ly + 4 lz]
-            T cur[16];
-#pragma unroll
-            for (int lz = 0; lz < 4; ++lz) {
-                T E[4], O[4];
-#pragma unroll
-                for (int ly = 0; ly < 4; ++ly) {
-                    const T a0 = xu0[kx * XUR + ly + 4 * lz], a1 = xu1[kx * XUR + ly + 4 * lz];
-                    E[ly] = a0 + a1;
-                    O[ly] = a0 - a1;
-                }
-#pragma unroll
-                for (int ky = 0; ky < 4; ++ky) cur[ky + 4 * lz] = sym<4>(opH3, ky, ky, E, O);
-            }
-            if (emit) {
-#pragma unroll
-                for (int ky = 0; ky < 4; ++ky) {
-                    T E[4], O[4];
-#pragma unroll
-                    for (int lz = 0; lz < 4; ++lz) {
-                        E[lz] = pA[ky + 4 * lz] + cur[ky + 4 * lz];
-                        O[lz] = pA[ky + 4 * lz] - cur[ky + 4 * lz];
-                    }
-#pragma unroll
-                    for (int kz = 0; kz < 4; ++kz)
-                        sh.p0[cell3 * P0S + kx + 4 * ky + 16 * kz] = sym<4>(opH3, kz, kz, E, O);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) pA[i] = cur[i];
+            p0_y(xu0, xu1, kx, cA);
+            p0_z(emit, pA, cA, sh.p0 + cell3 * P0S + kx);
         } else if (!hi) {
-            yz_rq<0>(xu0, xu1, sh.xv + e0 * XVE, sh.xv + e1 * XVE, kx, emit, pA, pB, pC,
-                     sh.z + cell3 * ZS, l2x, l2y, l2z, sz, tau);
+            yz_y<0>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, l2x, l2y, l2z, tau);
+            yz_z<0>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, sz);
         } else {
-            yz_rq<3>(xu0, xu1, sh.xv + e0 * XVE, sh.xv + e1 * XVE, kx, emit, pA, pB, pC,
-                     sh.z + cell3 * ZS, l2x, l2y, l2z, sz, tau);
+            yz_y<3>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, l2x, l2y, l2z, tau);
+            yz_z<3>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, sz);
         }
         if (!emit) continue; // the first layer only primes the registers
         __syncthreads();
 
-        // ---- 4. time sums: class blocks on the matrix cores, 16 cells per product.  The
-        //         wave's CPW x GPW products run as interleaved independent chains, all B
-        //         operands read first ----
-        // lanes 0-31 hold u rows and lanes 32-63 v rows of a class block: the target and
-        // the p0 term are selected per lane, so both kinds share one instruction stream
-        auto epilogue = [&](const typename MF::vec& acc, int cell, int c) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int dst = rdst[c][r];
-                const bool used = dst >= 0, isv = dst >= (1 << 16);
-                const int ai = used ? (dst & 0xffff) : 0;
-                const T pz = sh.p0[cell * P0S + (isv ? 0 : ai)];
-                const T val = rsc[c][r] * acc[r] + (isv ? T(0) : pz);
-                const int o = isv ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
-                if (used) ou_base[o] = val;
-            }
-        };
-        if constexpr (BF) {
-            static_assert(CPW == 1, "BF16 path: one class per wave");
-            bf16x8 bb[GPW][2];
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) {
-                const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
-#pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) bb[k][kb][e] = (__bf16)zc[kb8[kb][e]];
-            }
-            typename MF::vec acc[GPW];
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) acc[k] = typename MF::vec{T(0), T(0), T(0), T(0)};
-#pragma unroll
-            for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) acc[k] = mac_bf16(tb[kb], bb[k][kb], acc[k]);
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) epilogue(acc[k], 16 * grp_of(k) + (lane & 15), 0);
-        } else if constexpr (CPW == 1) {
-            T bv[GPW][TS_KSTEPS];
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) {
-                const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
-#pragma unroll
-                for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[k][ks] = zc[tkv[0][ks]];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            typename MF::vec acc[GPW];
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) acc[k] = typename MF::vec{T(0), T(0), T(0), T(0)};
-#pragma unroll
-            for (int ks = 0; ks < TS_KSTEPS; ++ks)
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) acc[k] = MF::mac(tav[0][ks], bv[k][ks], acc[k]);
-#pragma unroll
-            for (int k = 0; k < GPW; ++k) epilogue(acc[k], 16 * grp_of(k) + (lane & 15), 0);
-        } else {
-            T bv[CPW][GPW][TS_KSTEPS];
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) {
-                    const T* zc = sh.z + (16 * grp_of(k) + (lane & 15)) * ZS;
-#pragma unroll
-                    for (int ks = 0; ks < TS_KSTEPS; ++ks) bv[c][k][ks] = zc[tkv[c][ks]];
-                }
-            __builtin_amdgcn_sched_barrier(0);
-            typename MF::vec acc[CPW][GPW];
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) acc[c][k] = typename MF::vec{T(0), T(0), T(0), T(0)};
-#pragma unroll
-            for (int ks = 0; ks < TS_KSTEPS; ++ks)
-#pragma unroll
-                for (int c = 0; c < CPW; ++c)
-#pragma unroll
-                    for (int k = 0; k < GPW; ++k) acc[c][k] = MF::mac(tav[c][ks], bv[c][k][ks], acc[c][k]);
-#pragma unroll
-            for (int c = 0; c < CPW; ++c)
-#pragma unroll
-                for (int k = 0; k < GPW; ++k) epilogue(acc[c][k], 16 * grp_of(k) + (lane & 15), c);
-        }
+        // ---- 4. time sums of the cell layer just emitted ----
+        BOp bv[CPW][GPW][NB];
+        Acc acc[CPW][GPW];
+        ts_load(bv);
+        if constexpr (!BF) __builtin_amdgcn_sched_barrier(0); // FP32/FP64: every operand read before the products
+        ts_mac(bv, acc);
+        ts_out(acc);
     }
     if (nlayers >= 2) {
         __syncthreads();
