@@ -89,6 +89,7 @@ struct hw_solver {
     int grid = 0;
     double* partials = nullptr;
     double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
+    void* tiled_tables = nullptr; // weights of the tiled kernel for this problem's lam2 and tau
     bool split = false;           // two-kernel form
     void* work = nullptr;         // its interpolant workspace
     ProblemDesc* split_descs = nullptr; // [phase][stage 1, 2]
@@ -300,6 +301,7 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         a.u_out = D.u_out;
         a.v_out = D.v_out;
         a.tau = D.tau;
+        a.tables = s->tiled_tables;
         (void)P;
         HIP_TRY(hw_launch_tiled(a, s->precision, st));
         return HW_OK;
@@ -471,8 +473,11 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             hipSuccess)
             return cleanup(fail(HW_EHIP, "forcing table upload failed"));
     }
-    if (s->use_tiled && hw_tiled_prepare(s->precision) != hipSuccess)
-        return cleanup(fail(HW_EHIP, "tiled kernel table setup failed"));
+    if (s->use_tiled) {
+        const ProblemDesc& D = s->h_descs[0];
+        if (hw_tiled_tables_create(s->precision, D.lam2, D.tau, &s->tiled_tables) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "tiled kernel table setup failed"));
+    }
     if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail(HW_EHIP, "stream creation failed"));
     *out = s;
@@ -525,6 +530,7 @@ void hw_destroy(hw_solver* s)
     if (s->prefix) (void)hipFree(s->prefix);
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
+    if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

@@ -26,7 +26,12 @@ struct TiledArgs {
     void* u_out;
     void* v_out;
     double tau, lam2[3];
+    const void* tables; // from hw_tiled_tables_create with the same precision, lam2 and tau
 };
 bool hw_tiled_supported(int d, int m, int method, int precision);
-hipError_t hw_tiled_prepare(int precision); // builds the constant tables (call outside capture)
+// Device tables of the kernel for one (precision, lam2, tau): the time-sum weights carry
+// the scalings in lam2 and tau.  Allocates and uploads synchronously (call outside
+// capture); the caller frees them with hw_tiled_tables_destroy.
+hipError_t hw_tiled_tables_create(int precision, const double lam2[3], double tau, void** out);
+void hw_tiled_tables_destroy(void* tables);
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st);

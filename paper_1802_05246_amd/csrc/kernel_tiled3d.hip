@@ -18,24 +18,24 @@
 //   3. y- and z-passes per (cell, k_x, half of the k_y range): the y-pass of this
 //      layer is combined with the previous layer's (kept in registers) into the
 //      z-pass, giving for the cell between the two layers p0 (centre rows),
-//      Q = I_{m-1}^3 v and R = sum_i (lambda_i/2)^2 d_i^2 c^(i) (modified first step);
+//      Q = I_{m-1}^3 v and R = sum_i (lambda_i/2)^2 d_i^2 c^(i) (modified first step),
+//      the latter divided by (lambda_z/2)^2;
 //   4. the Taylor series in time is summed in closed form (Sec. 3.1.2).  With
-//      S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2) the weights are constants: Q and R
-//      are stored pre-scaled by S and each output is scaled by 1/S(alpha),
-//        u' = p0 + (1/S(a)) sum_b W(a,b) [tau S Q/(2j+1)! + S R/(2j+2)!]
-//        v' = (1/(tau S(a))) sum_b W(a,b) [tau S Q/(2j)!  + S R/(2j+1)!]
-//      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!, j = |b|, k = a + 2b.  Only k with
-//      the parity of a enter, so the sums split into 8 parity classes, each a dense
-//      (<= 16 outputs) x (27 Q + 27 R inputs) block applied to 16 cells at a time on
-//      the matrix cores; the outputs are staged in LDS for the coalesced 16-byte
-//      stores of step 1 of the next pass.
+//      S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2), k = a + 2b and j = |b|,
+//        u' = p0 + sum_b W(a,b) S(k)/S(a) [tau Q/(2j+1)! + R/(2j+2)!]
+//        v' =      sum_b W(a,b) S(k)/S(a) [Q/(2j)! + R/(tau (2j+1)!)]
+//      W(a,b) = j!/prod b_i! prod (a_i+2b_i)!/a_i!.  For a given lambda and tau every
+//      factor is a constant, so each input's weight is one table entry built on the
+//      host.  Only k with the parity of a enter, so the sums split into 8 parity
+//      classes, each a dense (<= 16 outputs) x (27 Q + 27 R inputs) block applied to
+//      16 cells at a time on the matrix cores; the outputs are staged in LDS for the
+//      coalesced 16-byte stores of step 1 of the next pass.
 // Every node of the input grid is read from HBM once per column (plus the one-node
 // halo shared with the neighbouring columns), every output node written once.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 #include <type_traits>
-#include <mutex>
 
 #include "hermite_tables.h"
 #include "hw_kernels.h"
@@ -118,11 +118,12 @@ struct Mfma<double> {
     static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
 };
 
-// Device tables (per element type), built once on the host:
+// Device tables (per element type and per lambda, tau: the class-block weights carry the
+// scalings), built on the host:
 //   xa[2][64]          A operand of the x-pass (K-step, lane): opX[l%16][4 ks + l/16]
 //   ta[8][14][64]      A operand of the class blocks (class, K-step, lane)
 //   tk[8][56]          LDS offset in the cell block [Q|R|0] of input kk of a class
-//   tr[8][16]          output decode of (class, row): -1 unused, else
+//   tr[8][16]          output of (class, row): -1 unused, else
 //                      is_v << 12 | scale mask (alpha_i >= 2) << 8 | flat alpha index
 template <typename T>
 struct Tables {
@@ -132,7 +133,8 @@ struct Tables {
     int tr[8][16];
     // BF16-operand form (16x16x32 products, 8 operands per lane, k = 8 (lane / 16) + e):
     //   xb[64][8]        x-pass A operand: opX[l % 16][k] for k < 8, else 0
-    //   tb[8][2][64][8]  class-block A operand, K-block kb: W[l % 16][32 kb + k]
+    //   tb[8][2][64][8]  class-block A operand, K-block kb: W[l % 16][32 kb + k] without the
+//                    lambda and tau factors (the BF16 form scales in the kernel)
     //   kb8[8][2][4][8]  LDS offset of input 32 kb + 8 g + e of a class (padding: zero slot)
     unsigned short xb[64][8];
     unsigned short tb[8][2][64][8];
@@ -194,27 +196,38 @@ __device__ inline T sym(Op op, int row, int parity, const T* E, const T* O, T ac
 }
 
 // y- and z-passes of the R and Q paths for rows k_y = KH .. KH+2 of one (cell, k_x).
-// With f = S_x(k_x) S_y(k_y) (the x and y factors of the scaling S(k)):
-//   Ay[ky][lz <= 2] = f (l_x/2)^2 H2t_y d2_x + f (l_y/2)^2 d2_y H2t_x   (z operator H_2),
-//   By[ky][lz <= 3] = f (l_z/2)^2 H2t_y H2t_x                         (z operator d2),
-//   Cy[ky][lz <= 2] = f tau H2_y H2_x v.
-// yz_y computes this layer's y-pass (cA: 9 of its 16 entries, cB, cC); yz_z combines the
-// previous layer (pA, pB, pC, side s = 0) with this one (side s = 1), stores tau S Q and
-// S R of the cell (S_z(k_z) applied last) and moves this layer's results into pA, pB, pC.
-template <int KH, typename T>
+// Unscaled form (the factors S(k), (lambda_z/2)^2 and tau are part of the time-sum weights):
+//   Ay[ky][lz <= 2] = gx H2t_y d2_x + gy d2_y H2t_x,  gx,y = (l_x,y/2)^2 / (l_z/2)^2   (z operator H_2),
+//   By[ky][lz <= 3] = H2t_y H2t_x                                                    (z operator d2),
+//   Cy[ky][lz <= 2] = H2_y H2_x v,
+// so that the z-pass gives Q = I_{m-1}^3 v and R / (l_z/2)^2 (scaled form: below).  yz_y computes this
+// layer's y-pass (cA: 9 of its 16 entries, cB, cC); yz_z combines the previous layer
+// (pA, pB, pC, side s = 0) with this one (side s = 1), stores Q and R / (l_z/2)^2 of
+// the cell and moves this layer's results into pA, pB, pC.
+// Scalings of the y/z-passes.  Unscaled form: gx, gy only.  Scaled form (BF16 operands,
+// whose weights must stay free of lambda and tau, see the table builder): the row
+// factors f = S_x(k_x) S_y(k_y) times l_x, l_y, l_z (the (lambda/2)^2) and tau, the
+// z-factors S_z applied at the end, as Q and R are then stored pre-scaled by S(k)
+// (tau S Q and S R).
+template <typename T>
+struct YzScale {
+    T gx, gy, l2x, l2y, l2z, tau;
+};
+
+template <int KH, bool SC, typename T>
 __device__ inline void yz_y(const T* xu0, const T* xu1, const T* xv0, const T* xv1, int kx,
-                            T (&cA)[16], T (&cB)[12], T (&cC)[9], T l2x, T l2y, T l2z, T tau)
+                            T (&cA)[16], T (&cB)[12], T (&cC)[9], const YzScale<T>& sc)
 {
-    const T skx = kx < 2 ? T(1) : (kx < 4 ? l2x : l2x * l2x);
     T fx[3], fy[3], fb[3], fc[3];
+    const T skx = kx < 2 ? T(1) : (kx < 4 ? sc.l2x : sc.l2x * sc.l2x);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const int ky = KH + j;
-        const T f = (ky / 2 == 0) ? skx : ((ky / 2 == 1) ? skx * l2y : skx * (l2y * l2y));
-        fx[j] = f * l2x;
-        fy[j] = f * l2y;
-        fb[j] = f * l2z;
-        fc[j] = f * tau;
+        const T f = (ky / 2 == 0) ? skx : ((ky / 2 == 1) ? skx * sc.l2y : skx * (sc.l2y * sc.l2y));
+        fx[j] = SC ? f * sc.l2x : sc.gx;
+        fy[j] = SC ? f * sc.l2y : sc.gy;
+        fb[j] = f * sc.l2z;
+        fc[j] = f * sc.tau;
     }
 #pragma unroll
     for (int lz = 0; lz < 4; ++lz) {
@@ -239,21 +252,24 @@ __device__ inline void yz_y(const T* xu0, const T* xu1, const T* xv0, const T* x
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int ky = KH + j;
-                const T ax_ = sym<3>(opH2, ky, ky, Ed, Od);
-                const T ay_ = sym<4>(opD2, ky, ky + 2, Eh, Oh);
-                cA[j + 3 * lz] = fx[j] * ax_ + fy[j] * ay_;
-                cC[j + 3 * lz] = fc[j] * sym<3>(opH2, ky, ky, Eq, Oq);
+                cA[j + 3 * lz] = fx[j] * sym<3>(opH2, ky, ky, Ed, Od) + fy[j] * sym<4>(opD2, ky, ky + 2, Eh, Oh);
+                const T c = sym<3>(opH2, ky, ky, Eq, Oq);
+                cC[j + 3 * lz] = SC ? fc[j] * c : c;
             }
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) cB[j + 3 * lz] = fb[j] * sym<3>(opH2, KH + j, KH + j, Eh, Oh);
+        for (int j = 0; j < 3; ++j) {
+            const T b = sym<3>(opH2, KH + j, KH + j, Eh, Oh);
+            cB[j + 3 * lz] = SC ? fb[j] * b : b;
+        }
     }
 }
 
-template <int KH, typename T>
+template <int KH, bool SC, typename T>
 __device__ inline void yz_z(bool emit, int kx, T (&pA)[16], T (&pB)[12], T (&pC)[9], const T (&cA)[16],
-                            const T (&cB)[12], const T (&cC)[9], T* zc, const T (&sz)[3])
+                            const T (&cB)[12], const T (&cC)[9], T* zc, T l2z)
 {
+    const T sz[3] = {T(1), l2z, l2z * l2z};
     if (emit) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -273,11 +289,11 @@ __device__ inline void yz_z(bool emit, int kx, T (&pA)[16], T (&pB)[12], T (&pC)
             }
 #pragma unroll
             for (int kz = 0; kz < 6; ++kz) {
-                const T r = sym<4>(opD2, kz, kz + 2, EB, OB, sym<3>(opH2, kz, kz, EA, OA));
-                const T q = sym<3>(opH2, kz, kz, EC, OC);
                 const int k = kx + 6 * ky + 36 * kz;
-                zc[k] = kz < 2 ? q : q * sz[kz / 2];
-                zc[216 + k] = kz < 2 ? r : r * sz[kz / 2];
+                const T q = sym<3>(opH2, kz, kz, EC, OC);
+                const T r = sym<4>(opD2, kz, kz + 2, EB, OB, sym<3>(opH2, kz, kz, EA, OA));
+                zc[k] = (SC && kz >= 2) ? q * sz[kz / 2] : q;
+                zc[216 + k] = (SC && kz >= 2) ? r * sz[kz / 2] : r;
             }
         }
     }
@@ -361,8 +377,10 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     const int cz1 = min(cz0 + tz, a.ext_to[2]);
     const int off = (a.to_grid == 1) ? 0 : -1; // input node of corner s = cell + off + s
 
-    const T l2x = T(a.lam2[0]), l2y = T(a.lam2[1]), l2z = T(a.lam2[2]);
-    const T sz[3] = {T(1), l2z, l2z * l2z};
+    // BF16 operands: the scalings stay in FP32 arithmetic (SC), see the table builder
+    constexpr bool SC = BF;
+    const YzScale<T> ysc{T(a.lam2[0] / a.lam2[2]), T(a.lam2[1] / a.lam2[2]), T(a.lam2[0]),
+                         T(a.lam2[1]), T(a.lam2[2]), T(a.tau)};
     const T* __restrict__ gu = (const T*)a.u_in;
     const T* __restrict__ gv = (const T*)a.v_in;
 
@@ -389,26 +407,13 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
     static_assert(NW < 8 || (NC / 16) % (NW / 8) == 0, "cell groups must tile the waves");
     auto cls_of = [&](int c) { return NW >= 8 ? wave % 8 : wave + c * NW; };
     auto grp_of = [&](int k) { return NW >= 8 ? wave / 8 + k * (NW / 8) : k; };
-    const T tau = T(a.tau), inv_tau = T(1.0 / a.tau);
-    const T invx = T(1.0 / a.lam2[0]), invy = T(1.0 / a.lam2[1]), invz = T(1.0 / a.lam2[2]);
-    // output decode of table entry `info`: LDS offset in the staged outputs (u rows
-    // relative to the cell's u block, v rows offset by the v region) and scale 1/S(a),
-    // times 1/tau for v
-    auto decode = [&](int info, int& dst, T& sc) {
-        if (info < 0) {
-            dst = -1;
-            sc = T(0);
-            return;
-        }
-        const int ai = info & 0xff;
-        sc = (info & 0x1000) ? inv_tau : T(1);
-        if (info & 0x100) sc *= invx;
-        if (info & 0x200) sc *= invy;
-        if (info & 0x400) sc *= invz;
-        dst = (info & 0x1000) ? (1 << 16) | ai : ai;
-    };
-    T tav[CPW][TS_KSTEPS], rsc[CPW][4];
+    // output target of each result row: LDS offset in the staged outputs (u rows relative
+    // to the cell's u block, v rows flagged by 1 << 16), -1 for an unused row; in the
+    // scaled form (SC) also the output scale 1/S(alpha), times 1/tau for v
     int tkv[CPW][TS_KSTEPS], rdst[CPW][4];
+    T tav[CPW][TS_KSTEPS], rsc[CPW][4];
+    const T inv_tau = T(1.0 / a.tau);
+    const T inv_l2[3] = {T(1.0 / a.lam2[0]), T(1.0 / a.lam2[1]), T(1.0 / a.lam2[2])};
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         const int p = cls_of(c);
@@ -418,7 +423,16 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             tkv[c][ks] = tabs->tk[p][4 * ks + (lane >> 4)];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) decode(tabs->tr[p][MF::row(lane, r)], rdst[c][r], rsc[c][r]);
+        for (int r = 0; r < 4; ++r) {
+            const int info = tabs->tr[p][MF::row(lane, r)];
+            const bool isv = info >= 0 && (info & 0x1000);
+            rdst[c][r] = info < 0 ? -1 : (isv ? (1 << 16) | (info & 0xff) : (info & 0xff));
+            T sc = isv ? inv_tau : T(1);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (info >= 0 && (info & (0x100 << i))) sc *= inv_l2[i];
+            rsc[c][r] = sc;
+        }
     }
 
     // ---- 1. node layers: fetched into registers one layer ahead, then stashed in
@@ -624,7 +638,7 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                     const bool used = dst >= 0, isv = dst >= (1 << 16);
                     const int ai = used ? (dst & 0xffff) : 0;
                     const T pz = sh.p0[cell * P0S + (isv ? 0 : ai)];
-                    const T val = rsc[c][r] * acc[c][k][r] + (isv ? T(0) : pz);
+                    const T val = (SC ? rsc[c][r] * acc[c][k][r] : acc[c][k][r]) + (isv ? T(0) : pz);
                     const int o = isv ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
                     if (used) ou_base[o] = val;
                 }
@@ -727,11 +741,11 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
             p0_y(xu0, xu1, kx, cA);
             p0_z(emit, pA, cA, sh.p0 + cell3 * P0S + kx);
         } else if (!hi) {
-            yz_y<0>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, l2x, l2y, l2z, tau);
-            yz_z<0>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, sz);
+            yz_y<0, SC>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, ysc);
+            yz_z<0, SC>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, ysc.l2z);
         } else {
-            yz_y<3>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, l2x, l2y, l2z, tau);
-            yz_z<3>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, sz);
+            yz_y<3, SC>(xu0, xu1, xv0, xv1, kx, cA, cB, cC, ysc);
+            yz_z<3, SC>(emit, kx, pA, pB, pC, cA, cB, cC, sh.z + cell3 * ZS, ysc.l2z);
         }
         if (!emit) continue; // the first layer only primes the registers
         __syncthreads();
@@ -759,8 +773,17 @@ double weight(int ax, int ay, int az, int bx, int by, int bz)
            kFact[ax] * kFact[ay + 2 * by] / kFact[ay] * kFact[az + 2 * bz] / kFact[az];
 }
 
+// S(k) = prod_i ((lambda_i/2)^2)^floor(k_i/2)
+double scale_s(const int k[3], const double lam2[3])
+{
+    double s = 1.0;
+    for (int i = 0; i < 3; ++i)
+        for (int e = 0; e < k[i] / 2; ++e) s *= lam2[i];
+    return s;
+}
+
 template <typename T>
-void build_tables(Tables<T>& t)
+void build_tables(Tables<T>& t, const double lam2[3], double tau)
 {
     std::memset(&t, 0, sizeof t);
     for (int ks = 0; ks < 2; ++ks)
@@ -797,7 +820,11 @@ void build_tables(Tables<T>& t)
             t.tr[p][row] = (rv[row] ? 0x1000 : 0) | (mask << 8) | flat;
         }
         // inputs kk: 0..26 Q, 27..53 R, 54..55 padding (zero slot)
-        double W[16][TS_KSTEPS * 4] = {};
+        // W: weights of the unscaled form (FP32 and FP64 operands); W0: without the
+        // scalings, for the BF16 operands, whose rounding of lambda- and tau-dependent
+        // weights would perturb the scheme itself (a time-step error that accumulates
+        // over the steps), so the BF16 form applies the scalings in FP32 instead
+        double W[16][TS_KSTEPS * 4] = {}, W0[16][TS_KSTEPS * 4] = {};
         for (int kk = 0; kk < TS_KSTEPS * 4; ++kk) {
             if (kk >= 54) {
                 t.tk[p][kk] = 432;
@@ -813,9 +840,14 @@ void build_tables(Tables<T>& t)
                 const int bx = (k[0] - al[0]) / 2, by = (k[1] - al[1]) / 2, bz = (k[2] - al[2]) / 2;
                 const int j = bx + by + bz;
                 const double w = weight(al[0], al[1], al[2], bx, by, bz);
-                // u: Q/(2j+1)!, R/(2j+2)!;  v: Q/(2j)!, R/(2j+1)!
+                // u: tau Q/(2j+1)!, R/(2j+2)!;  v: Q/(2j)!, R/(2j+1)! / tau.  The inputs
+                // arrive unscaled (Q, R / (l_z/2)^2), the outputs as they are stored,
+                // so the weight carries S(k) / S(alpha), (l_z/2)^2 for R, tau for Q
                 const int fq = rv[row] ? 2 * j : 2 * j + 1;
-                W[row][kk] = w / kFact[isr ? fq + 1 : fq];
+                const double sc = scale_s(k, lam2) / scale_s(al, lam2) * (isr ? lam2[2] : tau) /
+                                  (rv[row] ? tau : 1.0);
+                W0[row][kk] = w / kFact[isr ? fq + 1 : fq];
+                W[row][kk] = W0[row][kk] * sc;
             }
         }
         for (int ks = 0; ks < TS_KSTEPS; ++ks)
@@ -824,7 +856,7 @@ void build_tables(Tables<T>& t)
             for (int l = 0; l < 64; ++l)
                 for (int e = 0; e < 8; ++e) {
                     const int k = 32 * kb + 8 * (l / 16) + e;
-                    t.tb[p][kb][l][e] = to_bf16(k < TS_KSTEPS * 4 ? W[l % 16][k] : 0.0);
+                    t.tb[p][kb][l][e] = to_bf16(k < TS_KSTEPS * 4 ? W0[l % 16][k] : 0.0);
                     if (l < 4 * 16 && l % 16 == 0)
                         t.kb8[p][kb][l / 16][e] = k < TS_KSTEPS * 4 ? t.tk[p][k] : 432;
                 }
@@ -837,34 +869,30 @@ void build_tables(Tables<T>& t)
 }
 
 template <typename T>
-const Tables<T>* device_tables(hipError_t* err)
+hipError_t create_tables(const double lam2[3], double tau, void** out)
 {
-    static std::mutex mu;
-    static Tables<T>* dev = nullptr;
-    std::lock_guard<std::mutex> lock(mu);
-    *err = hipSuccess;
-    if (dev) return dev;
     Tables<T>* h = new Tables<T>();
-    build_tables(*h);
+    build_tables(*h, lam2, tau);
     void* p = nullptr;
-    *err = hipMalloc(&p, sizeof(Tables<T>));
-    if (*err == hipSuccess) *err = hipMemcpy(p, h, sizeof(Tables<T>), hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc(&p, sizeof(Tables<T>));
+    if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(Tables<T>), hipMemcpyHostToDevice);
     delete h;
-    if (*err != hipSuccess) return nullptr;
-    dev = (Tables<T>*)p;
-    return dev;
+    if (e != hipSuccess) {
+        if (p) (void)hipFree(p);
+        return e;
+    }
+    *out = p;
+    return hipSuccess;
 }
 
 template <typename T, int TY, bool BF = false>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
     constexpr int NT = 16 * TX * TY;
-    hipError_t e;
-    const Tables<T>* tabs = device_tables<T>(&e);
-    if (!tabs) return e;
+    const Tables<T>* tabs = static_cast<const Tables<T>*>(a.tables);
     const size_t lds = sizeof(Shared<T, TY>);
     auto kern = k_tiled3d_m3<T, TY, BF>;
-    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int tz = 64;
     const int tiles = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + TY - 1) / TY);
@@ -880,16 +908,23 @@ bool hw_tiled_supported(int d, int m, int method, int precision)
     return d == 3 && m == 3 && method == 0 && (precision == 0 || precision == 1 || precision == 2);
 }
 
-hipError_t hw_tiled_prepare(int precision)
+hipError_t hw_tiled_tables_create(int precision, const double lam2[3], double tau, void** out)
 {
-    hipError_t e;
-    if (precision == 0) device_tables<double>(&e);
-    else device_tables<float>(&e);
-    return e;
+    *out = nullptr;
+    for (int i = 0; i < 3; ++i)
+        if (!(lam2[i] >= 2.5e-7)) return hipErrorInvalidValue;
+    if (!(tau > 0.0)) return hipErrorInvalidValue;
+    return precision == 0 ? create_tables<double>(lam2, tau, out) : create_tables<float>(lam2, tau, out);
+}
+
+void hw_tiled_tables_destroy(void* tables)
+{
+    if (tables) (void)hipFree(tables);
 }
 
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st)
 {
+    if (!a.tables) return hipErrorInvalidValue;
     for (int i = 0; i < 3; ++i)
         if (!(a.lam2[i] >= 2.5e-7) || a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
     if (precision == 0) return launch<double, 4>(a, st);
