@@ -42,8 +42,8 @@ BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "388fbef3ce64bebf66b487021c6f3b595e29c510cbbf2e2fa03c8f3eb3a78edf",
-    "fetch_bytes": 8518450861,  # FETCH_SIZE 4159539.0 KiB x 1048576/524305.5 (copy: 1 GiB read)
+    "source_sha256": "351ac8a9299cab3c037eff56ae65667f521af8a912245c9fb94ae3ababb8c44d",
+    "fetch_bytes": 8564629998,  # FETCH_SIZE 4182068.7 KiB x 1048576/524303.1 (copy: 1 GiB read)
     "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_tiled3d_m3-diss3d_m3_256cube-hbm_bytes.md",
 }
