@@ -75,7 +75,8 @@ constexpr int XUE = 16 * XUR + 1; // x-edge stride of the u x-pass results: [row
 constexpr int XVE = 55;  // x-edge stride of the v x-pass results: [row][l_y + 3 l_z] + 1
 constexpr int P0S = 65;  // cell stride of p0: [kx + 4 ky + 16 kz]
 constexpr int ZS = 433;  // cell stride of [tau S Q (216) | S R (216) | 0]
-constexpr int OUS = 68;  // cell stride of the staged u outputs (16-byte rows for the stores)
+constexpr int OUS = 68;  // cell stride of the staged u outputs (16-byte rows for the stores;
+                         // word 64 takes the writes of unused time-sum rows)
 
 // time-sum blocks: 8 classes x 14 K-steps of 4 (54 inputs padded to 56)
 constexpr int TS_KSTEPS = 14;
@@ -634,13 +635,16 @@ k_tiled3d_m3(TiledArgs a, int tz, const Tables<T>* __restrict__ tabs)
                 const int cell = 16 * grp_of(k) + (lane & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    // unused rows write to the padding word 64 of the cell's u block (never
+                    // stored), so every lane stores and the epilogue has no branches: its
+                    // p0 reads and stores are issued back to back
                     const int dst = rdst[c][r];
                     const bool used = dst >= 0, isv = dst >= (1 << 16);
-                    const int ai = used ? (dst & 0xffff) : 0;
-                    const T pz = sh.p0[cell * P0S + (isv ? 0 : ai)];
+                    const int ai = used ? (dst & 0xffff) : 64;
+                    const T pz = sh.p0[cell * P0S + (isv || !used ? 0 : ai)];
                     const T val = (SC ? rsc[c][r] * acc[c][k][r] : acc[c][k][r]) + (isv ? T(0) : pz);
                     const int o = isv ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
-                    if (used) ou_base[o] = val;
+                    ou_base[o] = val;
                 }
             }
     };
