@@ -65,15 +65,21 @@ typedef enum {
 } hw_precision;
 
 typedef enum {
-    HW_KERNEL_AUTO = 0,    /* tiled MFMA kernel when one exists for the problem, else generic */
+    HW_KERNEL_AUTO = 0,    /* tiled MFMA kernel when one exists for the problem, else the dense
+                              kernel when one exists, else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
     HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
-    HW_KERNEL_SPLIT = 3    /* two kernels per half step, as in the paper's two-kernel GPU
+    HW_KERNEL_SPLIT = 3,   /* two kernels per half step, as in the paper's two-kernel GPU
                               design (Sec. 6.1): the first writes each cell's interpolants
                               (p0, Q, R) to a device workspace, the second reads them and
                               sums the Taylor series; single dissipative problems only
                               (HW_EUNSUPPORTED otherwise); for comparison with the fused
                               kernels */
+    HW_KERNEL_DENSE = 4    /* one lane per cell, d <= 2: the cell's half step as one dense
+                              matrix (built once per problem from the same operators and
+                              time-sum weights) applied to its corner nodes; single problems
+                              with d = 1 (any m), d = 2 dissipative m <= 3, d = 2
+                              conservative m <= 4, FP64 or FP32 (HW_EUNSUPPORTED otherwise) */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;

@@ -90,6 +90,8 @@ struct hw_solver {
     double* partials = nullptr;
     double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
     void* tiled_tables = nullptr; // weights of the tiled kernel for this problem's lam2 and tau
+    bool use_dense = false;       // per-lane dense kernel (d <= 2)
+    void* dense_G = nullptr;      // its cell matrix in the state precision
     bool split = false;           // two-kernel form
     void* work = nullptr;         // its interpolant workspace
     ProblemDesc* split_descs = nullptr; // [phase][stage 1, 2]
@@ -112,7 +114,7 @@ hw_status validate(const hw_problem* p)
         return fail(HW_EINVAL, "m = %d outside %d..%d for this method", p->m, mlo, HW_MAXM);
     if (p->precision < HW_FP64 || p->precision > HW_BF16)
         return fail(HW_EINVAL, "unknown precision %d", p->precision);
-    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_SPLIT)
+    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_DENSE)
         return fail(HW_EINVAL, "unknown kernel selector %d", p->kernel);
     if (!(p->c > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->c) || !std::isfinite(p->dt))
         return fail(HW_EINVAL, "c and dt must be positive and finite");
@@ -306,6 +308,25 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         HIP_TRY(hw_launch_tiled(a, s->precision, st));
         return HW_OK;
     }
+    if (s->use_dense) {
+        const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np];
+        DenseArgs a;
+        for (int i = 0; i < 3; ++i) {
+            a.ext_from[i] = D.ext_from[i];
+            a.ext_to[i] = D.ext_to[i];
+            a.bc[i] = D.bc[i];
+        }
+        a.to_grid = D.to_grid;
+        a.u_in = D.u_in;
+        a.v_in = D.v_in;
+        a.u_old = D.u_old;
+        a.u_out = D.u_out;
+        a.v_out = D.v_out;
+        a.G = s->dense_G;
+        a.n_cells = D.n_out;
+        HIP_TRY(hw_launch_dense(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
+        return HW_OK;
+    }
     const ProblemDesc* descs = s->descs + (size_t)(phase * 2 + q) * np;
     const int64_t* prefix = s->prefix + (size_t)phase * (np + 1);
     if (s->split) {
@@ -338,10 +359,15 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
                     p0.m, p0.method, p0.precision);
+    const bool dense_ok = count == 1 && hw_dense_supported(p0.d, p0.m, p0.method, p0.precision);
+    if (p0.kernel == HW_KERNEL_DENSE && !dense_ok)
+        return fail(HW_EUNSUPPORTED, "no dense kernel for d=%d m=%d method=%d precision=%d (or a batch)",
+                    p0.d, p0.m, p0.method, p0.precision);
     if (p0.kernel == HW_KERNEL_SPLIT && (count != 1 || p0.method == HW_CONSERVATIVE))
         return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
     if (p0.precision == HW_BF16 &&
-        (!tiled_ok || p0.kernel == HW_KERNEL_GENERIC || p0.kernel == HW_KERNEL_SPLIT || p0.taylor_stages != 0))
+        (!tiled_ok || p0.kernel == HW_KERNEL_GENERIC || p0.kernel == HW_KERNEL_SPLIT ||
+         p0.kernel == HW_KERNEL_DENSE || p0.taylor_stages != 0))
         return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel (3-D dissipative full "
                                      "method, m = 3, exact series)");
     for (int i = 0; i < count; ++i)
@@ -354,7 +380,9 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     s->fp64 = (p0.precision == HW_FP64);
     s->elem = s->fp64 ? 8 : 4;
     s->split = p0.kernel == HW_KERNEL_SPLIT;
-    s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && !s->split && p0.taylor_stages == 0;
+    s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.kernel != HW_KERNEL_DENSE && !s->split &&
+                   p0.taylor_stages == 0;
+    s->use_dense = dense_ok && !s->use_tiled && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE);
     s->probs.resize(count);
     auto cleanup = [&](hw_status st) {
         hw_destroy(s);
@@ -473,6 +501,23 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             hipSuccess)
             return cleanup(fail(HW_EHIP, "forcing table upload failed"));
     }
+    if (s->use_dense) {
+        std::vector<double> G;
+        int n_in = 0, n_out = 0;
+        hw_cell_map(s->h_descs[0], G, n_in, n_out);
+        std::vector<float> Gf;
+        const void* src = G.data();
+        size_t bytes = G.size() * sizeof(double);
+        if (!s->fp64) {
+            Gf.assign(G.begin(), G.end());
+            src = Gf.data();
+            bytes = Gf.size() * sizeof(float);
+        }
+        if (hipMalloc(&s->dense_G, bytes) != hipSuccess)
+            return cleanup(fail(HW_ENOMEM, "cell matrix allocation failed"));
+        if (hipMemcpy(s->dense_G, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "cell matrix upload failed"));
+    }
     if (s->use_tiled) {
         const ProblemDesc& D = s->h_descs[0];
         if (hw_tiled_tables_create(s->precision, D.lam2, D.tau, &s->tiled_tables) != hipSuccess)
@@ -531,6 +576,7 @@ void hw_destroy(hw_solver* s)
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
     if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
+    if (s->dense_G) (void)hipFree(s->dense_G);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

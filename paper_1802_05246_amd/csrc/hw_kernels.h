@@ -6,6 +6,8 @@
 
 #include "hw_device.h"
 
+#include <vector>
+
 size_t hw_generic_lds_bytes(int d, int m, int variant, int elem_size);
 size_t hw_energy_lds_bytes(int d, int m);
 
@@ -28,6 +30,23 @@ struct TiledArgs {
     double tau, lam2[3];
     const void* tables; // from hw_tiled_tables_create with the same precision, lam2 and tau
 };
+// Per-lane dense kernel for d <= 2 (kernel_dense.hip): each output node is the product
+// of the problem's cell matrix G (hw_cell_map, FP64 on the host, uploaded in the state
+// precision) with its 2^d corner nodes; ghost corners mirrored as in the other kernels.
+struct DenseArgs {
+    int ext_from[3], ext_to[3], bc[3], to_grid;
+    const void* u_in;
+    const void* v_in;  // dissipative
+    const void* u_old; // conservative: old level on the grid written
+    void* u_out;
+    void* v_out;       // dissipative
+    const void* G;     // [n_in][n_out], input-major
+    int64_t n_cells;
+};
+bool hw_dense_supported(int d, int m, int method, int precision);
+void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
+hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
+
 bool hw_tiled_supported(int d, int m, int method, int precision);
 // Device tables of the kernel for one (precision, lam2, tau): the time-sum weights carry
 // the scalings in lam2 and tau.  Allocates and uploads synchronously (call outside

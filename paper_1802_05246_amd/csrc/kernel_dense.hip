@@ -1,0 +1,197 @@
+// Per-lane dense half-step kernel for d <= 2: one lane per output node ("cell").
+//
+// The half step of one cell is a fixed linear map of its 2^d corner nodes (composed on
+// the host into the matrix G, see cellmap.cpp); every lane gathers its corners from
+// global memory, mirrors ghost corners outside non-periodic walls with the odd / even
+// signs of Sec. 3.1.3, and accumulates the product with G in registers, one input at a
+// time against all outputs.  G is the same for every lane, so its entries are read
+// through the scalar unit and enter the FMAs as scalar operands.  Dissipative: the
+// outputs are u' and v' of the node; conservative (Sec. 4.1): the even time sum S,
+// and u_new = 2 S - u_old.
+#include <hip/hip_runtime.h>
+
+#include "hw_kernels.h"
+
+namespace {
+
+constexpr int DENSE_BLOCK = 256;
+
+constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+// sign of coefficient l of a node mirrored across a wall of type bc (1: Dirichlet,
+// odd extension: (-1)^(l+1); 2: Neumann, even extension: (-1)^l)
+__device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
+
+template <typename T, int D, int MU, bool CONS>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
+{
+    constexpr int MV = CONS ? 0 : MU - 1;
+    constexpr int NU = cpow(MU, D), NV = CONS ? 0 : cpow(MV, D);
+    constexpr int NI = NU + NV, NO = CONS ? NU : NU + NV;
+    // 1-D: consecutive cells per workgroup; 2-D: a tile of 64 x 4 cells, so that the
+    // rows of corner nodes a workgroup reads are shared by its own cells
+    int64_t cell;
+    if constexpr (D == 1) {
+        cell = (int64_t)blockIdx.x * DENSE_BLOCK + threadIdx.x;
+        if (cell >= a.n_cells) return;
+    } else {
+        const int tiles_x = (a.ext_to[0] + 63) / 64;
+        const int x = (blockIdx.x % tiles_x) * 64 + (threadIdx.x & 63);
+        const int y = (blockIdx.x / tiles_x) * (DENSE_BLOCK / 64) + (threadIdx.x >> 6);
+        if (x >= a.ext_to[0] || y >= a.ext_to[1]) return;
+        cell = x + (int64_t)a.ext_to[0] * y;
+    }
+
+    // corners: input node per dimension and side, and whether it is a ghost image
+    int node[2][2];
+    bool ghost[2][2];
+    int64_t rem = cell;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const int oi = (int)(rem % a.ext_to[i]);
+        rem /= a.ext_to[i];
+        const int ext = a.ext_from[i];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            int j;
+            bool gh = false;
+            if (a.to_grid == 1) { // dual node i+1/2: primal nodes i, i+1
+                j = oi + s;
+                if (a.bc[i] == 0 && j >= ext) j -= ext;
+            } else {              // primal node i: dual nodes i-1/2, i+1/2
+                j = oi - 1 + s;
+                if (a.bc[i] == 0) {
+                    if (j < 0) j += ext;
+                } else if (j < 0) {
+                    j = 0;
+                    gh = true;
+                } else if (j >= ext) {
+                    j = ext - 1;
+                    gh = true;
+                }
+            }
+            node[i][s] = j;
+            ghost[i][s] = gh;
+        }
+    }
+
+    const T* __restrict__ G = static_cast<const T*>(a.G);
+    const T* __restrict__ uin = static_cast<const T*>(a.u_in);
+    const T* __restrict__ vin = static_cast<const T*>(a.v_in);
+    // conservative: the old level is read first, so that its latency overlaps the products
+    T uold[CONS ? NU : 1];
+    if constexpr (CONS) {
+#pragma unroll
+        for (int o = 0; o < NU; ++o) uold[o] = static_cast<const T*>(a.u_old)[cell * NU + o];
+    }
+    T acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = T(0);
+
+#pragma unroll
+    for (int c = 0; c < (1 << D); ++c) {
+        int64_t nd = 0, st = 1;
+        bool gx[2] = {false, false};
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int s = (c >> i) & 1;
+            nd += node[i][s] * st;
+            st *= a.ext_from[i];
+            gx[i] = ghost[i][s];
+        }
+        // one block (u: extent MU per dimension, v: MV) of corner c against G
+        auto block = [&](const T* __restrict__ src, auto md_tag, int in0) {
+            constexpr int MD = decltype(md_tag)::value;
+            constexpr int NB = cpow(MD, D);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                bool neg = false;
+                if (gx[0] && flips(a.bc[0], l % MD)) neg = !neg;
+                if (D > 1 && gx[1] && flips(a.bc[1], (l / MD) % MD)) neg = !neg;
+                const T x = neg ? -src[l] : src[l];
+                const T* g = G + (int64_t)(in0 + l) * NO;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) acc[o] += g[o] * x;
+            }
+        };
+        block(uin + nd * NU, std::integral_constant<int, MU>{}, c * NI);
+        if constexpr (!CONS) block(vin + nd * NV, std::integral_constant<int, MV>{}, c * NI + NU);
+    }
+
+    T* __restrict__ uo = static_cast<T*>(a.u_out) + cell * NU;
+    if constexpr (CONS) {
+#pragma unroll
+        for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - uold[o];
+    } else {
+        T* __restrict__ vo = static_cast<T*>(a.v_out) + cell * NV;
+#pragma unroll
+        for (int o = 0; o < NU; ++o) uo[o] = acc[o];
+#pragma unroll
+        for (int o = 0; o < NV; ++o) vo[o] = acc[NU + o];
+    }
+}
+
+template <typename T, int D, int MU, bool CONS>
+hipError_t launch(const DenseArgs& a, hipStream_t st)
+{
+    const int64_t blocks = D == 1 ? (a.n_cells + DENSE_BLOCK - 1) / DENSE_BLOCK
+                                  : (int64_t)((a.ext_to[0] + 63) / 64) *
+                                        ((a.ext_to[1] + DENSE_BLOCK / 64 - 1) / (DENSE_BLOCK / 64));
+    hipLaunchKernelGGL((k_dense<T, D, MU, CONS>), dim3((unsigned)blocks), dim3(DENSE_BLOCK), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(const DenseArgs& a, int d, int m, bool cons, hipStream_t st)
+{
+    if (d == 1) {
+        if (cons) {
+            switch (m) {
+            case 0: return launch<T, 1, 1, true>(a, st);
+            case 1: return launch<T, 1, 2, true>(a, st);
+            case 2: return launch<T, 1, 3, true>(a, st);
+            case 3: return launch<T, 1, 4, true>(a, st);
+            case 4: return launch<T, 1, 5, true>(a, st);
+            case 5: return launch<T, 1, 6, true>(a, st);
+            case 6: return launch<T, 1, 7, true>(a, st);
+            }
+        } else {
+            switch (m) {
+            case 1: return launch<T, 1, 2, false>(a, st);
+            case 2: return launch<T, 1, 3, false>(a, st);
+            case 3: return launch<T, 1, 4, false>(a, st);
+            case 4: return launch<T, 1, 5, false>(a, st);
+            case 5: return launch<T, 1, 6, false>(a, st);
+            case 6: return launch<T, 1, 7, false>(a, st);
+            }
+        }
+    } else if (d == 2) {
+        if (cons) {
+            switch (m) {
+            case 0: return launch<T, 2, 1, true>(a, st);
+            case 1: return launch<T, 2, 2, true>(a, st);
+            case 2: return launch<T, 2, 3, true>(a, st);
+            case 3: return launch<T, 2, 4, true>(a, st);
+            case 4: return launch<T, 2, 5, true>(a, st);
+            }
+        } else {
+            switch (m) {
+            case 1: return launch<T, 2, 2, false>(a, st);
+            case 2: return launch<T, 2, 3, false>(a, st);
+            case 3: return launch<T, 2, 4, false>(a, st);
+            }
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+} // namespace
+
+hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
+{
+    if (!a.G || a.n_cells < 0) return hipErrorInvalidValue;
+    if (a.n_cells == 0) return hipSuccess;
+    for (int i = 0; i < d; ++i)
+        if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
+    return fp64 ? dispatch<double>(a, d, m, cons, st) : dispatch<float>(a, d, m, cons, st);
+}

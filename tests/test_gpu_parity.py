@@ -129,6 +129,50 @@ def test_small_grids_match_oracle(case, prec):
     s.close()
 
 
+def _dense_supported(d, m, meth):
+    if d == 1:
+        return True
+    return d == 2 and (m <= 4 if meth == W.CONSERVATIVE else m <= 3)
+
+
+DENSE_CASES = [c for c in CASES if _dense_supported(c[0], c[1], c[4])] + [
+    (2, 1, [5, 4], [W.DIRICHLET, W.NEUMANN], W.DISS_FULL, 0),
+    (2, 3, [6, 7], [W.DIRICHLET, W.DIRICHLET], W.DISS_FULL, 0),
+    (2, 2, [4, 6], [W.NEUMANN, W.NEUMANN], W.DISS_SIMPLE, 0),
+    (2, 0, [6, 5], [W.PERIODIC, W.DIRICHLET], W.CONSERVATIVE, 0),
+    (2, 3, [5, 6], [W.NEUMANN, W.NEUMANN], W.CONSERVATIVE, 0),
+    (1, 2, [6], [W.NEUMANN], W.DISS_SIMPLE, 5),
+]
+
+
+@pytest.mark.parametrize("case", DENSE_CASES, ids=[_case_id(c) for c in DENSE_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_kernel_matches_oracle(case, prec):
+    """The per-lane dense kernel (d <= 2: each cell's half step as one matrix applied to
+    its corners) against the oracle, same bars as the generic kernel."""
+    B = _B()
+    d, m, n, bc, meth, stages = case
+    _log(f"[parity dense] {_case_id(case)} {prec}")
+    spec = W.make_spec(d, m, n, 0.0, [1.0, 0.9, 0.8][:d], 1.1, cfl=0.9, bc=bc, method=meth,
+                       taylor_stages=stages)
+    u, w = _state(spec, 29 + d + m)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_DENSE)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    n_half = 6
+    s.half_steps(n_half)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
+    if prec == "fp64":
+        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+    else:
+        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(m, n_half)
+    _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
+    assert err <= tol
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_graph_advance_equals_plain_launches_bitwise(prec):
     B = _B()

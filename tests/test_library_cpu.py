@@ -41,7 +41,7 @@ def test_validation_codes():
     p.dt = 1.01 * min(good.h(0), good.h(1)) / good.c
     assert _err(p) == B.HW_ECFL
     for field, val in [("d", 0), ("d", 4), ("m", 0), ("m", 7), ("method", 5), ("precision", 9),
-                       ("kernel", 4), ("taylor_stages", -1)]:
+                       ("kernel", 5), ("taylor_stages", -1)]:
         p = B.make_problem(good)
         setattr(p, field, val)
         assert _err(p) == B.HW_EINVAL, field
@@ -50,6 +50,11 @@ def test_validation_codes():
     assert _err(p) == B.HW_EINVAL
     # the two-kernel form serves single dissipative problems only
     p = B.make_problem(W.make_spec(2, 3, [8, 8], cfl=0.9, method=W.CONSERVATIVE), kernel=B.HW_KERNEL_SPLIT)
+    assert _err(p) == B.HW_EUNSUPPORTED
+    # the dense kernel serves single problems with d <= 2 only (and no BF16)
+    p = B.make_problem(W.make_spec(3, 3, [4, 4, 4], cfl=0.9), kernel=B.HW_KERNEL_DENSE)
+    assert _err(p) == B.HW_EUNSUPPORTED
+    p = B.make_problem(W.make_spec(2, 5, [6, 6], cfl=0.9), kernel=B.HW_KERNEL_DENSE)
     assert _err(p) == B.HW_EUNSUPPORTED
     p = B.make_problem(good)
     p.bc[0] = 7
