@@ -77,9 +77,11 @@ typedef enum {
                               kernels */
     HW_KERNEL_DENSE = 4    /* one lane per cell, d <= 2: the cell's half step as one dense
                               matrix (built once per problem from the same operators and
-                              time-sum weights) applied to its corner nodes; single problems
-                              with d = 1 (any m), d = 2 dissipative m <= 3, d = 2
-                              conservative m <= 4, FP64 or FP32 (HW_EUNSUPPORTED otherwise) */
+                              time-sum weights) applied to its corner nodes, one launch per
+                              problem of a batch; d = 1 (any m), d = 2 dissipative (any m),
+                              d = 2 conservative m <= 5, FP64 or FP32 (HW_EUNSUPPORTED
+                              otherwise; with HW_KERNEL_AUTO the other problems of a batch
+                              share one generic launch) */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;

@@ -90,8 +90,12 @@ struct hw_solver {
     double* partials = nullptr;
     double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
     void* tiled_tables = nullptr; // weights of the tiled kernel for this problem's lam2 and tau
-    bool use_dense = false;       // per-lane dense kernel (d <= 2)
-    void* dense_G = nullptr;      // its cell matrix in the state precision
+    std::vector<char> dense;      // per problem: served by the per-lane dense kernel (d <= 2)
+    std::vector<const void*> dense_G;  // per problem: its cell matrix in the state precision
+    std::vector<void*> dense_alloc;    // the distinct cell matrices (problems with equal maps share)
+    int64_t* gen_prefix = nullptr;     // prefix sums of the generic kernel's cells (dense problems: 0)
+    int64_t gen_total[2]{};
+    bool any_generic = true;
     bool split = false;           // two-kernel form
     void* work = nullptr;         // its interpolant workspace
     ProblemDesc* split_descs = nullptr; // [phase][stage 1, 2]
@@ -308,23 +312,30 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         HIP_TRY(hw_launch_tiled(a, s->precision, st));
         return HW_OK;
     }
-    if (s->use_dense) {
-        const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np];
-        DenseArgs a;
-        for (int i = 0; i < 3; ++i) {
-            a.ext_from[i] = D.ext_from[i];
-            a.ext_to[i] = D.ext_to[i];
-            a.bc[i] = D.bc[i];
+    if (!s->dense.empty()) {
+        for (int i = 0; i < np; ++i) {
+            if (!s->dense[i]) continue;
+            const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np + i];
+            DenseArgs a;
+            for (int k = 0; k < 3; ++k) {
+                a.ext_from[k] = D.ext_from[k];
+                a.ext_to[k] = D.ext_to[k];
+                a.bc[k] = D.bc[k];
+            }
+            a.to_grid = D.to_grid;
+            a.u_in = D.u_in;
+            a.v_in = D.v_in;
+            a.u_old = D.u_old;
+            a.u_out = D.u_out;
+            a.v_out = D.v_out;
+            a.G = s->dense_G[i];
+            a.n_cells = D.n_out;
+            HIP_TRY(hw_launch_dense(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
         }
-        a.to_grid = D.to_grid;
-        a.u_in = D.u_in;
-        a.v_in = D.v_in;
-        a.u_old = D.u_old;
-        a.u_out = D.u_out;
-        a.v_out = D.v_out;
-        a.G = s->dense_G;
-        a.n_cells = D.n_out;
-        HIP_TRY(hw_launch_dense(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
+        if (!s->any_generic) return HW_OK;
+        HIP_TRY(hw_launch_generic(s->d, s->fp64, s->descs + (size_t)(phase * 2 + q) * np,
+                                  s->gen_prefix + (size_t)phase * (np + 1), np, s->gen_total[phase], s->ops,
+                                  s->lds, s->grid, st));
         return HW_OK;
     }
     const ProblemDesc* descs = s->descs + (size_t)(phase * 2 + q) * np;
@@ -359,10 +370,11 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
                     p0.m, p0.method, p0.precision);
-    const bool dense_ok = count == 1 && hw_dense_supported(p0.d, p0.m, p0.method, p0.precision);
-    if (p0.kernel == HW_KERNEL_DENSE && !dense_ok)
-        return fail(HW_EUNSUPPORTED, "no dense kernel for d=%d m=%d method=%d precision=%d (or a batch)",
-                    p0.d, p0.m, p0.method, p0.precision);
+    if (p0.kernel == HW_KERNEL_DENSE)
+        for (int i = 0; i < count; ++i)
+            if (!hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision))
+                return fail(HW_EUNSUPPORTED, "no dense kernel for d=%d m=%d method=%d precision=%d (problem %d)",
+                            ps[i].d, ps[i].m, ps[i].method, ps[i].precision, i);
     if (p0.kernel == HW_KERNEL_SPLIT && (count != 1 || p0.method == HW_CONSERVATIVE))
         return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
     if (p0.precision == HW_BF16 &&
@@ -382,7 +394,12 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     s->split = p0.kernel == HW_KERNEL_SPLIT;
     s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.kernel != HW_KERNEL_DENSE && !s->split &&
                    p0.taylor_stages == 0;
-    s->use_dense = dense_ok && !s->use_tiled && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE);
+    if (!s->use_tiled && !s->split && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE)) {
+        s->dense.assign(count, 0);
+        for (int i = 0; i < count; ++i)
+            s->dense[i] = hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision) ? 1 : 0;
+        if (std::find(s->dense.begin(), s->dense.end(), 1) == s->dense.end()) s->dense.clear();
+    }
     s->probs.resize(count);
     auto cleanup = [&](hw_status st) {
         hw_destroy(s);
@@ -501,22 +518,50 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             hipSuccess)
             return cleanup(fail(HW_EHIP, "forcing table upload failed"));
     }
-    if (s->use_dense) {
-        std::vector<double> G;
-        int n_in = 0, n_out = 0;
-        hw_cell_map(s->h_descs[0], G, n_in, n_out);
-        std::vector<float> Gf;
-        const void* src = G.data();
-        size_t bytes = G.size() * sizeof(double);
-        if (!s->fp64) {
-            Gf.assign(G.begin(), G.end());
-            src = Gf.data();
-            bytes = Gf.size() * sizeof(float);
+    if (!s->dense.empty()) {
+        // cell matrices (problems with identical maps share one), and the generic kernel's
+        // work list without the dense problems
+        std::map<std::vector<double>, void*> made;
+        s->dense_G.assign(count, nullptr);
+        for (int i = 0; i < count; ++i) {
+            if (!s->dense[i]) continue;
+            std::vector<double> G;
+            int n_in = 0, n_out = 0;
+            hw_cell_map(s->h_descs[i], G, n_in, n_out);
+            auto it = made.find(G);
+            if (it != made.end()) {
+                s->dense_G[i] = it->second;
+                continue;
+            }
+            std::vector<float> Gf;
+            const void* src = G.data();
+            size_t bytes = G.size() * sizeof(double);
+            if (!s->fp64) {
+                Gf.assign(G.begin(), G.end());
+                src = Gf.data();
+                bytes = Gf.size() * sizeof(float);
+            }
+            void* dev = nullptr;
+            if (hipMalloc(&dev, bytes) != hipSuccess) return cleanup(fail(HW_ENOMEM, "cell matrix allocation failed"));
+            s->dense_alloc.push_back(dev);
+            if (hipMemcpy(dev, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(HW_EHIP, "cell matrix upload failed"));
+            made.emplace(std::move(G), dev);
+            s->dense_G[i] = dev;
         }
-        if (hipMalloc(&s->dense_G, bytes) != hipSuccess)
-            return cleanup(fail(HW_ENOMEM, "cell matrix allocation failed"));
-        if (hipMemcpy(s->dense_G, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
-            return cleanup(fail(HW_EHIP, "cell matrix upload failed"));
+        std::vector<int64_t> gp((size_t)2 * (count + 1), 0);
+        for (int ph = 0; ph < 2; ++ph) {
+            for (int i = 0; i < count; ++i) {
+                const int64_t n = s->dense[i] ? 0 : s->h_descs[(size_t)(ph * 2) * count + i].n_out;
+                gp[ph * (count + 1) + i + 1] = gp[ph * (count + 1) + i] + n;
+            }
+            s->gen_total[ph] = gp[ph * (count + 1) + count];
+        }
+        s->any_generic = std::find(s->dense.begin(), s->dense.end(), 0) != s->dense.end();
+        if (hipMalloc((void**)&s->gen_prefix, gp.size() * sizeof(int64_t)) != hipSuccess)
+            return cleanup(fail(HW_ENOMEM, "descriptor allocation failed"));
+        if (hipMemcpy(s->gen_prefix, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(HW_EHIP, "descriptor upload failed"));
     }
     if (s->use_tiled) {
         const ProblemDesc& D = s->h_descs[0];
@@ -576,7 +621,8 @@ void hw_destroy(hw_solver* s)
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
     if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
-    if (s->dense_G) (void)hipFree(s->dense_G);
+    for (void* g : s->dense_alloc) (void)hipFree(g);
+    if (s->gen_prefix) (void)hipFree(s->gen_prefix);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

@@ -103,8 +103,7 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
         auto block = [&](const T* __restrict__ src, auto md_tag, int in0) {
             constexpr int MD = decltype(md_tag)::value;
             constexpr int NB = cpow(MD, D);
-#pragma unroll
-            for (int l = 0; l < NB; ++l) {
+            auto one = [&](int l) {
                 bool neg = false;
                 if (gx[0] && flips(a.bc[0], l % MD)) neg = !neg;
                 if (D > 1 && gx[1] && flips(a.bc[1], (l / MD) % MD)) neg = !neg;
@@ -112,6 +111,15 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
                 const T* g = G + (int64_t)(in0 + l) * NO;
 #pragma unroll
                 for (int o = 0; o < NO; ++o) acc[o] += g[o] * x;
+            };
+            // small blocks unrolled completely; large ones (2-D, m >= 4) as a loop over the
+            // inputs, so that the code stays within the instruction cache
+            if constexpr (NB * NO <= 1024) {
+#pragma unroll
+                for (int l = 0; l < NB; ++l) one(l);
+            } else {
+#pragma unroll 2
+                for (int l = 0; l < NB; ++l) one(l);
             }
         };
         block(uin + nd * NU, std::integral_constant<int, MU>{}, c * NI);
@@ -173,12 +181,16 @@ hipError_t dispatch(const DenseArgs& a, int d, int m, bool cons, hipStream_t st)
             case 2: return launch<T, 2, 3, true>(a, st);
             case 3: return launch<T, 2, 4, true>(a, st);
             case 4: return launch<T, 2, 5, true>(a, st);
+            case 5: return launch<T, 2, 6, true>(a, st);
             }
         } else {
             switch (m) {
             case 1: return launch<T, 2, 2, false>(a, st);
             case 2: return launch<T, 2, 3, false>(a, st);
             case 3: return launch<T, 2, 4, false>(a, st);
+            case 4: return launch<T, 2, 5, false>(a, st);
+            case 5: return launch<T, 2, 6, false>(a, st);
+            case 6: return launch<T, 2, 7, false>(a, st);
             }
         }
     }

@@ -44,17 +44,21 @@ def _oracle_roundoff_floor(spec, u, w, n_half, ref, seed=0):
     return max(rel_l2(out[0], ref[0]), rel_l2(out[1], ref[1]))
 
 
+@pytest.mark.parametrize("kernel", ["auto", "generic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c5_recipe_reduced_n_every_problem(prec):
+def test_c5_recipe_reduced_n_every_problem(prec, kernel):
     """All 256 problems of the recipe (every m, method and wall type), N in 6..16:
-    two full steps of the batch against the oracle, every problem, every node.
+    two full steps of the batch against the oracle, every problem, every node, through
+    the default kernel choice (the per-lane dense kernel, one launch per problem) and
+    through the generic kernel (one batched launch per half step).
     FP64 bar: 1e-10, or ten times the oracle's own round-off floor where the
     problem's map amplifies rounding more (high m: the Hermite operator H_6 has
     entries up to 1638 and the four half steps compound it)."""
     B = _B()
     works = W.c5_batch(n_lo=6, n_hi=16)
     precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
-    s = B.Solver(problems=[w.spec for w in works], precision=precision)
+    s = B.Solver(problems=[w.spec for w in works], precision=precision,
+                 kernel=B.HW_KERNEL_AUTO if kernel == "auto" else B.HW_KERNEL_GENERIC)
     _start(B, s, works)
     ins = [[x.cpu().numpy() for x in s.get_state(i)] for i in range(len(works))]
     s.advance(2)
@@ -70,7 +74,7 @@ def test_c5_recipe_reduced_n_every_problem(prec):
             err, tol = joint_err(w.spec, gu, gw, ou, ow), fp32_tol(w.spec.m, 4)
         worst = max(worst, err / tol)
         assert err <= tol, (i, w.spec, err, tol)
-    _log(f"[c5 reduced] {prec}: worst error / tolerance = {worst:.3f}")
+    _log(f"[c5 reduced] {prec} {kernel}: worst error / tolerance = {worst:.3f}")
     s.close()
 
 

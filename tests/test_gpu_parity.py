@@ -130,9 +130,7 @@ def test_small_grids_match_oracle(case, prec):
 
 
 def _dense_supported(d, m, meth):
-    if d == 1:
-        return True
-    return d == 2 and (m <= 4 if meth == W.CONSERVATIVE else m <= 3)
+    return d == 1 or (d == 2 and not (meth == W.CONSERVATIVE and m >= 6))
 
 
 DENSE_CASES = [c for c in CASES if _dense_supported(c[0], c[1], c[4])] + [
@@ -142,6 +140,10 @@ DENSE_CASES = [c for c in CASES if _dense_supported(c[0], c[1], c[4])] + [
     (2, 0, [6, 5], [W.PERIODIC, W.DIRICHLET], W.CONSERVATIVE, 0),
     (2, 3, [5, 6], [W.NEUMANN, W.NEUMANN], W.CONSERVATIVE, 0),
     (1, 2, [6], [W.NEUMANN], W.DISS_SIMPLE, 5),
+    (2, 4, [5, 4], [W.PERIODIC, W.NEUMANN], W.DISS_FULL, 0),
+    (2, 6, [4, 4], [W.DIRICHLET, W.PERIODIC], W.DISS_FULL, 0),
+    (2, 6, [4, 5], [W.NEUMANN, W.DIRICHLET], W.DISS_SIMPLE, 0),
+    (2, 5, [5, 4], [W.DIRICHLET, W.NEUMANN], W.CONSERVATIVE, 0),
 ]
 
 

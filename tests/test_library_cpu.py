@@ -54,7 +54,9 @@ def test_validation_codes():
     # the dense kernel serves single problems with d <= 2 only (and no BF16)
     p = B.make_problem(W.make_spec(3, 3, [4, 4, 4], cfl=0.9), kernel=B.HW_KERNEL_DENSE)
     assert _err(p) == B.HW_EUNSUPPORTED
-    p = B.make_problem(W.make_spec(2, 5, [6, 6], cfl=0.9), kernel=B.HW_KERNEL_DENSE)
+    p = B.make_problem(W.make_spec(2, 3, [6, 6], cfl=0.9), precision=B.HW_BF16, kernel=B.HW_KERNEL_DENSE)
+    assert _err(p) == B.HW_EUNSUPPORTED
+    p = B.make_problem(W.make_spec(2, 6, [6, 6], cfl=0.9, method=W.CONSERVATIVE), kernel=B.HW_KERNEL_DENSE)
     assert _err(p) == B.HW_EUNSUPPORTED
     p = B.make_problem(good)
     p.bc[0] = 7
