@@ -528,6 +528,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             std::vector<double> G;
             int n_in = 0, n_out = 0;
             hw_cell_map(s->h_descs[i], G, n_in, n_out);
+            // the kernel uses corner 0's rows; the others follow by reflection symmetry
+            G.resize((size_t)(n_in >> s->d) * n_out);
             auto it = made.find(G);
             if (it != made.end()) {
                 s->dense_G[i] = it->second;

@@ -40,7 +40,7 @@ struct DenseArgs {
     const void* u_old; // conservative: old level on the grid written
     void* u_out;
     void* v_out;       // dissipative
-    const void* G;     // [n_in][n_out], input-major
+    const void* G;     // rows of corner 0 of the cell matrix: [n_in / 2^d][n_out], input-major
     int64_t n_cells;
 };
 bool hw_dense_supported(int d, int m, int method, int precision);

@@ -4,7 +4,8 @@
 // the host into the matrix G, see cellmap.cpp); every lane gathers its corners from
 // global memory, mirrors ghost corners outside non-periodic walls with the odd / even
 // signs of Sec. 3.1.3, and accumulates the product with G in registers, one input at a
-// time against all outputs.  G is the same for every lane, so its entries are read
+// time against all outputs (corners first combined by the reflection symmetry, so that
+// G holds one corner's rows).  G is the same for every lane, so its entries are read
 // through the scalar unit and enter the FMAs as scalar operands.  Dissipative: the
 // outputs are u' and v' of the node; conservative (Sec. 4.1): the even time sum S,
 // and u_new = 2 S - u_old.
@@ -27,7 +28,7 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
 {
     constexpr int MV = CONS ? 0 : MU - 1;
     constexpr int NU = cpow(MU, D), NV = CONS ? 0 : cpow(MV, D);
-    constexpr int NI = NU + NV, NO = CONS ? NU : NU + NV;
+    constexpr int NO = CONS ? NU : NU + NV;
     // 1-D: consecutive cells per workgroup; 2-D: a tile of 64 x 4 cells, so that the
     // rows of corner nodes a workgroup reads are shared by its own cells
     int64_t cell;
@@ -75,6 +76,12 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
         }
     }
 
+    // G holds the rows of corner 0 only: by the reflection symmetry of the Hermite
+    // operators about the cell centre (which the time sums keep, as they preserve the
+    // parity of every index), corner c = (s_0, s_1) enters output a with
+    // (-1)^(sum_i s_i (a_i + l_i)) times corner 0's entry, so the corners are first
+    // combined into the 2^d sums S_p = sum_c (-1)^(p . s) x_c and each entry of G
+    // multiplies the one S_p whose parities p = a + l (mod 2) it needs
     const T* __restrict__ G = static_cast<const T*>(a.G);
     const T* __restrict__ uin = static_cast<const T*>(a.u_in);
     const T* __restrict__ vin = static_cast<const T*>(a.v_in);
@@ -88,43 +95,75 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = T(0);
 
+    int64_t nd[1 << D];
+    bool gx[1 << D][2];
 #pragma unroll
     for (int c = 0; c < (1 << D); ++c) {
-        int64_t nd = 0, st = 1;
-        bool gx[2] = {false, false};
+        int64_t st = 1;
+        nd[c] = 0;
+        gx[c][1] = false;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const int s = (c >> i) & 1;
-            nd += node[i][s] * st;
+            nd[c] += node[i][s] * st;
             st *= a.ext_from[i];
-            gx[i] = ghost[i][s];
+            gx[c][i] = ghost[i][s];
         }
-        // one block (u: extent MU per dimension, v: MV) of corner c against G
-        auto block = [&](const T* __restrict__ src, auto md_tag, int in0) {
-            constexpr int MD = decltype(md_tag)::value;
-            constexpr int NB = cpow(MD, D);
-            auto one = [&](int l) {
+    }
+    // parity of output o along dimension i
+    auto opar = [](int o, int i) {
+        const int md = o < NU ? MU : MV, oo = o < NU ? o : o - NU;
+        return (i == 0 ? oo % md : (oo / md) % md) & 1;
+    };
+    // one block (u: extent MU per dimension, v: MV) of the corners against G
+    auto block = [&](const T* __restrict__ base, auto md_tag, int in0) {
+        constexpr int MD = decltype(md_tag)::value;
+        constexpr int NB = cpow(MD, D);
+        // input l = lx + MD ly; ly_odd: the y parity of l when it is not known at compile time
+        auto one = [&](int l, int lx, int ly, bool ly_odd) {
+            T x[1 << D];
+#pragma unroll
+            for (int c = 0; c < (1 << D); ++c) {
                 bool neg = false;
-                if (gx[0] && flips(a.bc[0], l % MD)) neg = !neg;
-                if (D > 1 && gx[1] && flips(a.bc[1], (l / MD) % MD)) neg = !neg;
-                const T x = neg ? -src[l] : src[l];
-                const T* g = G + (int64_t)(in0 + l) * NO;
-#pragma unroll
-                for (int o = 0; o < NO; ++o) acc[o] += g[o] * x;
-            };
-            // small blocks unrolled completely; large ones (2-D, m >= 4) as a loop over the
-            // inputs, so that the code stays within the instruction cache
-            if constexpr (NB * NO <= 1024) {
-#pragma unroll
-                for (int l = 0; l < NB; ++l) one(l);
+                if (gx[c][0] && flips(a.bc[0], lx)) neg = !neg;
+                if (D > 1 && gx[c][1] && flips(a.bc[1], ly)) neg = !neg;
+                const T v = base[nd[c] * NB + l];
+                x[c] = neg ? -v : v;
+            }
+            T S[1 << D];
+            if constexpr (D == 1) {
+                S[0] = x[0] + x[1];
+                S[1] = x[0] - x[1];
             } else {
-#pragma unroll 2
-                for (int l = 0; l < NB; ++l) one(l);
+                const T p = x[0] + x[1], q = x[0] - x[1], r = x[2] + x[3], t = x[2] - x[3];
+                // S[px + 2 py]; with ly odd the roles of py = 0 and 1 swap
+                S[0] = ly_odd ? p - r : p + r;
+                S[1] = ly_odd ? q - t : q + t;
+                S[2] = ly_odd ? p + r : p - r;
+                S[3] = ly_odd ? q + t : q - t;
+            }
+            const T* g = G + (int64_t)(in0 + l) * NO;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const int px = (opar(o, 0) + lx) & 1;
+                const int py = D > 1 ? opar(o, 1) : 0;
+                acc[o] += g[o] * S[px + 2 * py];
             }
         };
-        block(uin + nd * NU, std::integral_constant<int, MU>{}, c * NI);
-        if constexpr (!CONS) block(vin + nd * NV, std::integral_constant<int, MV>{}, c * NI + NU);
-    }
+        if constexpr (D == 1) {
+#pragma unroll
+            for (int l = 0; l < NB; ++l) one(l, l, 0, false);
+        } else {
+            // a loop over the rows l_y: keeps the loads of one row in flight at a time (few
+            // registers, many waves) and the code within the instruction cache
+#pragma unroll 1
+            for (int ly = 0; ly < MD; ++ly)
+#pragma unroll
+                for (int lx = 0; lx < MD; ++lx) one(lx + MD * ly, lx, ly, (ly & 1) != 0);
+        }
+    };
+    block(uin, std::integral_constant<int, MU>{}, 0);
+    if constexpr (!CONS) block(vin, std::integral_constant<int, MV>{}, NU);
 
     T* __restrict__ uo = static_cast<T*>(a.u_out) + cell * NU;
     if constexpr (CONS) {
