@@ -65,8 +65,9 @@ typedef enum {
 } hw_precision;
 
 typedef enum {
-    HW_KERNEL_AUTO = 0,    /* tiled MFMA kernel when one exists for the problem, else the dense
-                              kernel when one exists, else generic */
+    HW_KERNEL_AUTO = 0,    /* 3-D dissipative m = 3: tiled for the FP32 / BF16 full variant
+                              with the exact series, composed otherwise; d <= 2: dense where
+                              it exists; else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
     HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
     HW_KERNEL_SPLIT = 3,   /* two kernels per half step, as in the paper's two-kernel GPU
@@ -75,13 +76,18 @@ typedef enum {
                               sums the Taylor series; single dissipative problems only
                               (HW_EUNSUPPORTED otherwise); for comparison with the fused
                               kernels */
-    HW_KERNEL_DENSE = 4    /* one lane per cell, d <= 2: the cell's half step as one dense
+    HW_KERNEL_DENSE = 4,   /* one lane per cell, d <= 2: the cell's half step as one dense
                               matrix (built once per problem from the same operators and
                               time-sum weights) applied to its corner nodes, one launch per
                               problem of a batch; d = 1 (any m), d = 2 dissipative (any m),
                               d = 2 conservative m <= 5, FP64 or FP32 (HW_EUNSUPPORTED
                               otherwise; with HW_KERNEL_AUTO the other problems of a batch
                               share one generic launch) */
+    HW_KERNEL_COMPOSED = 5 /* 3-D dissipative (full or simple variant, any truncation), m = 3,
+                              FP64 or FP32, single problems: each cell's half step as its
+                              composed matrix, corners combined by the reflection symmetry
+                              of the Hermite operators, applied per output parity class to 16
+                              cells at a time on the matrix cores (HW_EUNSUPPORTED otherwise) */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;

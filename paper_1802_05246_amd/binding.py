@@ -17,7 +17,7 @@ HW_OK, HW_EINVAL, HW_ECFL, HW_ENOMEM, HW_EUNSUPPORTED, HW_EHIP, HW_ESTATE = 0, -
 HW_DISS_FULL, HW_DISS_SIMPLE, HW_CONSERVATIVE = 0, 1, 2
 HW_PERIODIC, HW_DIRICHLET, HW_NEUMANN = 0, 1, 2
 HW_FP64, HW_FP32, HW_BF16 = 0, 1, 2
-HW_KERNEL_AUTO, HW_KERNEL_GENERIC, HW_KERNEL_TILED, HW_KERNEL_SPLIT, HW_KERNEL_DENSE = 0, 1, 2, 3, 4
+HW_KERNEL_AUTO, HW_KERNEL_GENERIC, HW_KERNEL_TILED, HW_KERNEL_SPLIT, HW_KERNEL_DENSE, HW_KERNEL_COMPOSED = 0, 1, 2, 3, 4, 5
 HW_PRIMAL, HW_DUAL = 0, 1
 
 STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",

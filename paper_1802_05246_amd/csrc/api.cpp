@@ -71,6 +71,8 @@ struct hw_solver {
     bool fp64 = true;
     int precision = HW_FP64;
     bool use_tiled = false;
+    bool use_cmap = false;        // composed-map MFMA kernel (3-D dissipative, m = 3)
+    void* cmap_tables = nullptr;
     bool state_set = false;
     int64_t half_steps = 0;
     size_t elem = 8;
@@ -118,7 +120,7 @@ hw_status validate(const hw_problem* p)
         return fail(HW_EINVAL, "m = %d outside %d..%d for this method", p->m, mlo, HW_MAXM);
     if (p->precision < HW_FP64 || p->precision > HW_BF16)
         return fail(HW_EINVAL, "unknown precision %d", p->precision);
-    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_DENSE)
+    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_COMPOSED)
         return fail(HW_EINVAL, "unknown kernel selector %d", p->kernel);
     if (!(p->c > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->c) || !std::isfinite(p->dt))
         return fail(HW_EINVAL, "c and dt must be positive and finite");
@@ -291,7 +293,7 @@ hw_status check_solver(const hw_solver* s)
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
 {
     const int np = (int)s->probs.size();
-    if (s->use_tiled) {
+    if (s->use_tiled || s->use_cmap) {
         const Prob& P = s->probs[0];
         const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np];
         TiledArgs a;
@@ -307,9 +309,10 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         a.u_out = D.u_out;
         a.v_out = D.v_out;
         a.tau = D.tau;
-        a.tables = s->tiled_tables;
+        a.tables = s->use_cmap ? s->cmap_tables : s->tiled_tables;
         (void)P;
-        HIP_TRY(hw_launch_tiled(a, s->precision, st));
+        if (s->use_cmap) HIP_TRY(hw_launch_cmap3d(a, s->fp64, st));
+        else HIP_TRY(hw_launch_tiled(a, s->precision, st));
         return HW_OK;
     }
     if (!s->dense.empty()) {
@@ -370,6 +373,11 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
                     p0.m, p0.method, p0.precision);
+    const bool cmap_ok = count == 1 && p0.d == 3 && p0.m == 3 && p0.method != HW_CONSERVATIVE &&
+                         (p0.precision == HW_FP64 || p0.precision == HW_FP32);
+    if (p0.kernel == HW_KERNEL_COMPOSED && !cmap_ok)
+        return fail(HW_EUNSUPPORTED, "the composed-map kernel serves single 3-D dissipative problems with "
+                                     "m = 3 in FP64 or FP32");
     if (p0.kernel == HW_KERNEL_DENSE)
         for (int i = 0; i < count; ++i)
             if (!hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision))
@@ -379,7 +387,7 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
     if (p0.precision == HW_BF16 &&
         (!tiled_ok || p0.kernel == HW_KERNEL_GENERIC || p0.kernel == HW_KERNEL_SPLIT ||
-         p0.kernel == HW_KERNEL_DENSE || p0.taylor_stages != 0))
+         p0.kernel == HW_KERNEL_DENSE || p0.kernel == HW_KERNEL_COMPOSED || p0.taylor_stages != 0))
         return fail(HW_EUNSUPPORTED, "BF16 operands exist only in the tiled kernel (3-D dissipative full "
                                      "method, m = 3, exact series)");
     for (int i = 0; i < count; ++i)
@@ -392,9 +400,16 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     s->fp64 = (p0.precision == HW_FP64);
     s->elem = s->fp64 ? 8 : 4;
     s->split = p0.kernel == HW_KERNEL_SPLIT;
+    // automatic choice in 3-D, m = 3: the tiled kernel for the FP32 (and BF16) form of the
+    // full variant with the exact series, the composed-map kernel for FP64, the simple
+    // variant and truncated series (measured faster there, and the tiled kernel serves
+    // only the first case)
+    s->use_cmap = cmap_ok && (p0.kernel == HW_KERNEL_COMPOSED ||
+                              (p0.kernel == HW_KERNEL_AUTO &&
+                               (p0.precision == HW_FP64 || p0.method == HW_DISS_SIMPLE || p0.taylor_stages != 0)));
     s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.kernel != HW_KERNEL_DENSE && !s->split &&
-                   p0.taylor_stages == 0;
-    if (!s->use_tiled && !s->split && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE)) {
+                   !s->use_cmap && p0.taylor_stages == 0;
+    if (!s->use_tiled && !s->use_cmap && !s->split && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE)) {
         s->dense.assign(count, 0);
         for (int i = 0; i < count; ++i)
             s->dense[i] = hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision) ? 1 : 0;
@@ -565,6 +580,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         if (hipMemcpy(s->gen_prefix, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(HW_EHIP, "descriptor upload failed"));
     }
+    if (s->use_cmap && hw_cmap3d_tables_create(s->h_descs[0], s->fp64, &s->cmap_tables) != hipSuccess)
+        return cleanup(fail(HW_EHIP, "composed-map table setup failed"));
     if (s->use_tiled) {
         const ProblemDesc& D = s->h_descs[0];
         if (hw_tiled_tables_create(s->precision, D.lam2, D.tau, &s->tiled_tables) != hipSuccess)
@@ -623,6 +640,7 @@ void hw_destroy(hw_solver* s)
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
     if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
+    if (s->cmap_tables) (void)hipFree(s->cmap_tables);
     for (void* g : s->dense_alloc) (void)hipFree(g);
     if (s->gen_prefix) (void)hipFree(s->gen_prefix);
     if (s->work) (void)hipFree(s->work);

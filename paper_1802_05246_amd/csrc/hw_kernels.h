@@ -47,6 +47,12 @@ bool hw_dense_supported(int d, int m, int method, int precision);
 void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
 
+// Composed-map MFMA kernel for the 3-D dissipative method, m = 3 (kernel_cmap3d.hip):
+// the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are
+// passed in TiledArgs::tables.
+hipError_t hw_cmap3d_tables_create(const ProblemDesc& D, bool fp64, void** out);
+hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st);
+
 bool hw_tiled_supported(int d, int m, int method, int precision);
 // Device tables of the kernel for one (precision, lam2, tau): the time-sum weights carry
 // the scalings in lam2 and tau.  Allocates and uploads synchronously (call outside

@@ -1,0 +1,418 @@
+// Composed-map half-step kernel for the 3-D dissipative method (Sec. 3.3, d = 3; the
+// modified first step or the straightforward variant, exact or truncated series), nodal
+// degree m = 3, element type T = float or double.
+//
+// One half step maps a cell's 8 corner nodes (u: 64, v: 27 coefficients each) linearly
+// to its output node (Sec. 3.1: interpolate, sum the Taylor series in time, evaluate at
+// the centre).  The host composes that map into a matrix (cellmap.cpp).  Because the
+// Hermite operators are symmetric under reflection about the cell centre and the time
+// sums keep the parity of every index, corner s = (s_x, s_y, s_z) enters output a with
+// (-1)^(sum_i s_i (a_i + l_i)) times corner 0's entry.  So the corners are first combined
+// into the eight sums S_p[l] = sum_s (-1)^(p . s) x_s[l], and output a needs, for each
+// input l, only S_{pi(a) xor pi(l)}[l] (pi: the parity vector).  Grouped by the output
+// parity class q = pi(a), the outputs of a class (8 of u, <= 8 of v) are one dense
+// (<= 16) x 91 product with the class's column of selected sums, applied to 16 cells at a
+// time on the matrix cores.
+//
+// A workgroup owns a column of 4 x CY cells (CY = 8 in FP32, 4 in FP64) and walks it
+// upwards in z, one node layer of the input grid at a time.  Per layer:
+//   1. the layer's 5 x (CY+1) nodes, loaded into registers during the previous layer, are
+//      stashed in LDS (ghost nodes outside non-periodic walls mirrored with the odd /
+//      even signs of Sec. 3.1.3); the cell layer finished in the previous pass is stored
+//      and the loads of the next node layer are issued;
+//   2. x/y butterflies: per cell and input l, the four sums over the cell's corners of
+//      this layer, T_{pxy}[l] (kept for the next layer as well);
+//   3. the class products: S_p[l] = T_{pxy}(lower layer)[l] +- T_{pxy}(upper layer)[l]
+//      read as the B operand, the class block of the composed map as the A operand
+//      (registers), one 16x16x4 product chain of 23 steps per class and group of 16
+//      cells (FP32: one class and two groups per wave, FP64: two classes, one group);
+//      the outputs are staged in LDS for the coalesced stores of step 1.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "hw_kernels.h"
+
+namespace {
+
+constexpr int CX = 4;                         // cells along x of a workgroup's column
+constexpr int NXL = CX + 1;
+constexpr int NI = 91;                        // inputs per node: u 64 + v 27
+constexpr int NDP = 93;                       // LDS node stride (odd: spreads the banks)
+constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded to 92)
+constexpr int TL = 92;                        // stride of one butterfly sum over l
+constexpr int TSZ = 8 * TL + 2;               // cell stride of the butterfly sums [pxy][l][layer]
+constexpr int OUS = 68;                       // cell stride of the staged u outputs
+
+template <typename T>
+struct Mf;
+template <>
+struct Mf<float> {
+    typedef float vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(float a, float b, vec c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mf<double> {
+    typedef double vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(double a, double b, vec c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Tables per problem (lambda and tau are inside the composed map):
+//   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, input k = 4 ks + lane / 16)
+//   tb[8][KS][4]   per (class, K-step, lane / 16): offset of the selected butterfly sum in a
+//                  cell's block (pxy * TL + l), bit 15 set when the upper layer enters with
+//                  a minus sign (p_z = 1); input 91 (padding) reads a zero slot
+//   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
+template <typename T>
+struct CTables {
+    T ta[8][KS][64];
+    int tb[8][KS][4];
+    int tr[8][16];
+};
+
+// column of CX x CY cells: NC cells per layer, 16 NC threads
+// the butterfly sums of the two node layers of a cell layer sit side by side (layer
+// parity fastest), so that one 2-element read gives both
+template <typename T, int CY>
+struct CShared {
+    static constexpr int NC = CX * CY, NNODE = NXL * (CY + 1);
+    alignas(16) T tsum[NC * TSZ];
+    alignas(16) T out[NC * (OUS + 27)];
+    T nd[NNODE * NDP];
+};
+
+struct Map1 {
+    int j, ghost;
+};
+
+__device__ inline Map1 map_node(int gi, int ext, int bc)
+{
+    Map1 m;
+    m.ghost = 0;
+    if (bc == 0) {
+        int j = gi;
+        while (j < 0) j += ext;
+        while (j >= ext) j -= ext;
+        m.j = j;
+    } else if (gi < 0) {
+        m.j = 0;
+        m.ghost = 1;
+    } else if (gi >= ext) {
+        m.j = ext - 1;
+        m.ghost = 1;
+    } else {
+        m.j = gi;
+    }
+    return m;
+}
+
+__device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
+
+// coefficient (l_x, l_y, l_z) of input c of a node (u: 4^3, then v: 3^3)
+__host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
+{
+    if (c < 64) {
+        lx = c & 3;
+        ly = (c >> 2) & 3;
+        lz = c >> 4;
+    } else {
+        const int v = c - 64;
+        lx = v % 3;
+        ly = (v / 3) % 3;
+        lz = v / 9;
+    }
+}
+
+template <typename T, int CY>
+__global__ void __launch_bounds__(16 * CX * CY) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
+{
+    using MF = Mf<T>;
+    using SH = CShared<T, CY>;
+    constexpr int NC = SH::NC, NNODE = SH::NNODE, NT = 16 * NC, NW = NT / 64;
+    constexpr int CPW = 8 / NW;   // parity classes per wave
+    constexpr int GPW = NC / 16;  // groups of 16 cells per wave
+    constexpr int NLOAD = (NNODE * NI + NT - 1) / NT;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SH& sh = *reinterpret_cast<SH*>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    const int tiles_x = (a.ext_to[0] + CX - 1) / CX;
+    const int x0 = (blockIdx.x % tiles_x) * CX, y0 = (blockIdx.x / tiles_x) * CY;
+    const int cz0 = blockIdx.y * tz, cz1 = min(cz0 + tz, a.ext_to[2]);
+    const int off = (a.to_grid == 1) ? 0 : -1; // input node of corner s = cell + off + s
+    const T* __restrict__ gu = (const T*)a.u_in;
+    const T* __restrict__ gv = (const T*)a.v_in;
+
+    // padding input 91 of every cell block reads zero in both layers
+    for (int i = tid; i < 2 * NC * 4; i += NT) {
+        const int b = i / (NC * 4), r = i % (NC * 4);
+        sh.tsum[(r >> 2) * TSZ + ((r & 3) * TL + 91) * 2 + b] = T(0);
+    }
+
+    // the wave's classes: A operands, B offsets, output targets (registers)
+    T ta[CPW][KS];
+    int tb[CPW][KS], rdst[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int q = (wave % 8) + NW * c;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            ta[c][ks] = tabs->ta[q][ks][lane];
+            tb[c][ks] = tabs->tb[q][ks][lane >> 4];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int info = tabs->tr[q][MF::row(lane, r)];
+            // unused rows write to the padding word 64 of the cell's u block (never stored)
+            rdst[c][r] = info < 0 ? 64 : ((info & 0x1000) ? (1 << 16) | (info & 0xff) : (info & 0xff));
+        }
+    }
+
+    // ---- node loads: slot i of this thread = element tid + i NT of the layer's
+    //      NNODE x 91 block; the xy part and the xy ghost signs are fixed per column ----
+    const long long plane = (long long)a.ext_from[0] * a.ext_from[1];
+    int ld_off[NLOAD], ld_msk[NLOAD];
+    T rl[NLOAD];
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+        const int e = tid + i * NT;
+        ld_off[i] = 0;
+        ld_msk[i] = 4; // idle slot: reads u of node 0 of the layer, never stashed
+        if (e >= NNODE * NI) continue;
+        const int node = e / NI, c = e % NI;
+        int lx, ly, lz;
+        coef3(c, lx, ly, lz);
+        const Map1 mx = map_node(x0 + off + node % NXL, a.ext_from[0], a.bc[0]);
+        const Map1 my = map_node(y0 + off + node / NXL, a.ext_from[1], a.bc[1]);
+        const int nxy = mx.j + a.ext_from[0] * my.j;
+        ld_off[i] = c < 64 ? nxy * 64 + c : nxy * 27 + (c - 64);
+        bool neg = false;
+        if (mx.ghost && flips(a.bc[0], lx)) neg = !neg;
+        if (my.ghost && flips(a.bc[1], ly)) neg = !neg;
+        ld_msk[i] = 1 | (neg ? 2 : 0) | (c < 64 ? 4 : 0) | ((lz & 1) << 3);
+    }
+    int zghost = 0;
+    auto fetch = [&](int layer_gz) {
+        const Map1 mz = map_node(layer_gz, a.ext_from[2], a.bc[2]);
+        zghost = mz.ghost;
+        const long long zn = plane * mz.j;
+        // every slot loads (idle slots from node 0 of u): no branches, so the loads
+        // stay in flight until the stash of the next pass
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const T* src = (ld_msk[i] & 4) ? gu + zn * 64 : gv + zn * 27;
+            rl[i] = src[ld_off[i]];
+        }
+    };
+    auto stash = [&]() {
+        // the z flip of a ghost layer: Dirichlet flips even l_z, Neumann odd l_z
+        const bool zflip_odd = a.bc[2] != 1;
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const int e = tid + i * NT;
+            if (e >= NNODE * NI) break;
+            const int m = ld_msk[i];
+            bool neg = (m & 2) != 0;
+            if (zghost && (((m >> 3) & 1) != 0) == zflip_odd) neg = !neg;
+            sh.nd[(e / NI) * NDP + e % NI] = neg ? -rl[i] : rl[i];
+        }
+    };
+
+    // ---- staged outputs of a cell layer, stored coalesced ----
+    const int nlayers = cz1 - cz0 + 1;
+    T* const ou_base = sh.out;
+    T* const ov_base = sh.out + NC * OUS;
+    const long long plane_to = (long long)a.ext_to[0] * a.ext_to[1];
+    auto store_layer = [&](int cz) {
+        T* __restrict__ out_u = (T*)a.u_out;
+        T* __restrict__ out_v = (T*)a.v_out;
+        for (int i = tid; i < NC * 64; i += NT) {
+            const int c = i >> 6, coef = i & 63;
+            const int gx = x0 + c % CX, gy = y0 + c / CX;
+            if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+            out_u[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 64 + coef] = ou_base[c * OUS + coef];
+        }
+        for (int i = tid; i < NC * 27; i += NT) {
+            const int c = i / 27, coef = i % 27;
+            const int gx = x0 + c % CX, gy = y0 + c / CX;
+            if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+            out_v[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 27 + coef] = ov_base[c * 27 + coef];
+        }
+    };
+
+    fetch(cz0 + off);
+    for (int step = 0; step < nlayers; ++step) {
+        stash();
+        __syncthreads();
+        if (step >= 2) store_layer(cz0 + step - 2);
+        if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
+
+        // ---- 2. x/y butterflies of this layer: T_p[l], p = px + 2 py ----
+        T* tcur = sh.tsum + (step & 1);
+        for (int t = tid; t < NC * NI; t += NT) {
+            const int cell = t % NC, l = t / NC;
+            const int n00 = (cell % CX) + NXL * (cell / CX);
+            const T x00 = sh.nd[n00 * NDP + l], x10 = sh.nd[(n00 + 1) * NDP + l];
+            const T x01 = sh.nd[(n00 + NXL) * NDP + l], x11 = sh.nd[(n00 + NXL + 1) * NDP + l];
+            const T p = x00 + x10, q = x00 - x10, r = x01 + x11, s = x01 - x11;
+            T* dst = tcur + cell * TSZ + 2 * l;
+            dst[0] = p + r;
+            dst[2 * TL] = q + s;
+            dst[4 * TL] = p - r;
+            dst[6 * TL] = q - s;
+        }
+        __syncthreads();
+        if (step == 0) continue; // the first layer only primes the sums
+
+        // ---- 3. class products for the cell layer between the two node layers ----
+        typedef T T2 __attribute__((ext_vector_type(2)));
+        const bool lo_odd = ((step - 1) & 1) != 0; // layer parity of the lower node layer
+        T bv[CPW][GPW][KS];
+        auto load_b = [&](int ks0, int ks1) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                for (int g = 0; g < GPW; ++g)
+#pragma unroll
+                    for (int ks = ks0; ks < ks1; ++ks) {
+                        const int info = tb[c][ks];
+                        const int o = (16 * g + (lane & 15)) * TSZ + 2 * (info & 0x7fff);
+                        const T2 v = *reinterpret_cast<const T2*>(sh.tsum + o);
+                        const T lo = lo_odd ? v.y : v.x, hi = lo_odd ? v.x : v.y;
+                        bv[c][g][ks] = (info & 0x8000) ? lo - hi : lo + hi;
+                    }
+        };
+        typename MF::vec acc[CPW][GPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int g = 0; g < GPW; ++g) acc[c][g] = typename MF::vec{T(0), T(0), T(0), T(0)};
+        auto products = [&](int ks0, int ks1) {
+#pragma unroll
+            for (int ks = ks0; ks < ks1; ++ks)
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+#pragma unroll
+                    for (int g = 0; g < GPW; ++g) acc[c][g] = MF::mac(ta[c][ks], bv[c][g][ks], acc[c][g]);
+        };
+        // the first half of the operands is read before any product; the second half is
+        // read while the first half's products run
+        constexpr int KH = KS / 2;
+        load_b(0, KH);
+        __builtin_amdgcn_sched_barrier(0);
+        load_b(KH, KS);
+        products(0, KH);
+        __builtin_amdgcn_sched_barrier(0);
+        products(KH, KS);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int g = 0; g < GPW; ++g) {
+                const int cell = 16 * g + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int dst = rdst[c][r];
+                    const int ai = dst & 0xffff;
+                    const int o = dst >= (1 << 16) ? NC * OUS + cell * 27 + ai : cell * OUS + ai;
+                    ou_base[o] = acc[c][g][r];
+                }
+            }
+    }
+    if (nlayers >= 2) {
+        __syncthreads();
+        store_layer(cz1 - 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host: tables and launch
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t create(const ProblemDesc& D, void** out)
+{
+    std::vector<double> G;
+    int n_in = 0, n_out = 0;
+    hw_cell_map(D, G, n_in, n_out); // [8 * 91][91], corner 0's rows first
+    if (n_out != NI || n_in != 8 * NI) return hipErrorInvalidValue;
+    CTables<T>* h = new CTables<T>();
+    std::memset(h, 0, sizeof *h);
+    for (int q = 0; q < 8; ++q) {
+        const int qx = q & 1, qy = (q >> 1) & 1, qz = (q >> 2) & 1;
+        // rows: the 8 u outputs of the class, then its v outputs
+        int rows[16], nrow = 0;
+        for (int o = 0; o < 8; ++o)
+            rows[nrow++] = (qx + 2 * (o & 1)) + 4 * (qy + 2 * ((o >> 1) & 1)) + 16 * (qz + 2 * (o >> 2));
+        for (int az = qz; az <= 2; az += 2)
+            for (int ay = qy; ay <= 2; ay += 2)
+                for (int ax = qx; ax <= 2; ax += 2) rows[nrow++] = 64 + ax + 3 * ay + 9 * az;
+        for (int r = 0; r < 16; ++r)
+            h->tr[q][r] = r < nrow ? (rows[r] >= 64 ? 0x1000 | (rows[r] - 64) : rows[r]) : -1;
+        for (int ks = 0; ks < KS; ++ks) {
+            for (int g = 0; g < 4; ++g) {
+                const int l = 4 * ks + g;
+                if (l >= NI) {
+                    h->tb[q][ks][g] = 91; // zero slot of the px = py = 0 sums
+                    continue;
+                }
+                int lx, ly, lz;
+                coef3(l, lx, ly, lz);
+                const int px = (qx + lx) & 1, py = (qy + ly) & 1, pz = (qz + lz) & 1;
+                h->tb[q][ks][g] = ((px + 2 * py) * TL + l) | (pz ? 0x8000 : 0);
+            }
+            for (int lanei = 0; lanei < 64; ++lanei) {
+                const int i = lanei & 15, l = 4 * ks + (lanei >> 4);
+                h->ta[q][ks][lanei] = (i < nrow && l < NI) ? (T)G[(size_t)l * NI + rows[i]] : T(0);
+            }
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(CTables<T>));
+    if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(CTables<T>), hipMemcpyHostToDevice);
+    delete h;
+    if (e != hipSuccess) {
+        if (p) (void)hipFree(p);
+        return e;
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+template <typename T, int CY>
+hipError_t launch(const TiledArgs& a, hipStream_t st)
+{
+    constexpr int NT = 16 * CX * CY;
+    const size_t lds = sizeof(CShared<T, CY>);
+    auto kern = k_cmap3d<T, CY>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int tz = 64;
+    const int tiles = ((a.ext_to[0] + CX - 1) / CX) * ((a.ext_to[1] + CY - 1) / CY);
+    const int chunks = (a.ext_to[2] + tz - 1) / tz;
+    hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz,
+                       static_cast<const CTables<T>*>(a.tables));
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t hw_cmap3d_tables_create(const ProblemDesc& D, bool fp64, void** out)
+{
+    *out = nullptr;
+    if (D.d != 3 || D.m != 3 || (D.variant != HWV_DISS_FULL && D.variant != HWV_DISS_SIMPLE))
+        return hipErrorInvalidValue;
+    return fp64 ? create<double>(D, out) : create<float>(D, out);
+}
+
+hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
+{
+    if (!a.tables) return hipErrorInvalidValue;
+    for (int i = 0; i < 3; ++i)
+        if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
+    // FP32: 4 x 8-cell columns (512 threads, one class per wave); FP64: 4 x 4 (the
+    // butterfly sums of two layers of 32 cells would not fit in LDS)
+    return fp64 ? launch<double, 4>(a, st) : launch<float, 8>(a, st);
+}

@@ -413,6 +413,43 @@ def test_tiled_3d_m3_matches_oracle(n, bc, prec):
     s.close()
 
 
+COMPOSED_CASES = [(n, bc, W.DISS_FULL, 0) for n, bc in TILED_CASES] + [
+    ([5, 6, 4], [W.PERIODIC, W.DIRICHLET, W.PERIODIC], W.DISS_SIMPLE, 0),
+    ([6, 4, 5], [W.NEUMANN, W.PERIODIC, W.DIRICHLET], W.DISS_SIMPLE, 0),
+    ([5, 5, 4], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 7),
+    ([4, 5, 6], [W.DIRICHLET, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 8),
+]
+
+
+@pytest.mark.parametrize("n,bc,meth,stages", COMPOSED_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-bc{''.join(map(str, c[1]))}-meth{c[2]}-st{c[3]}"
+                              for c in COMPOSED_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_composed_3d_m3_matches_oracle(n, bc, meth, stages, prec):
+    """The composed-map 3-D m = 3 kernel (ragged tiles, every wall type, both half-step
+    directions, anisotropic h, both variants, truncated series) against the oracle."""
+    B = _B()
+    _log(f"[composed] n={n} bc={bc} meth={meth} st={stages} {prec}")
+    spec = W.make_spec(3, 3, n, 0.0, [1.0, 0.8, 0.9], 1.2, cfl=0.85, bc=bc, method=meth,
+                       taylor_stages=stages)
+    u, w = _state(spec, 37 + sum(n))
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(spec, precision=precision, kernel=B.HW_KERNEL_COMPOSED)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    n_half = 4
+    s.half_steps(n_half)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
+    if prec == "fp64":
+        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
+    else:
+        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(3, n_half)
+    _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
+    assert err <= tol
+    s.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_tiled_equals_generic(prec):
     """Same problem through both kernels: FP64 agree to round-off, FP32 to the

@@ -41,7 +41,7 @@ def test_validation_codes():
     p.dt = 1.01 * min(good.h(0), good.h(1)) / good.c
     assert _err(p) == B.HW_ECFL
     for field, val in [("d", 0), ("d", 4), ("m", 0), ("m", 7), ("method", 5), ("precision", 9),
-                       ("kernel", 5), ("taylor_stages", -1)]:
+                       ("kernel", 6), ("taylor_stages", -1)]:
         p = B.make_problem(good)
         setattr(p, field, val)
         assert _err(p) == B.HW_EINVAL, field
