@@ -35,7 +35,7 @@ FLOPS_PER_CELL = 48272
 BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 
 
-# HBM traffic of one launch of the dominant kernel (FP32 tiled half step on this
+# HBM traffic of one launch of the dominant kernel (the FP32 tiled half step on this
 # workload), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by the ratio of true to counted bytes of a plain copy of
 # known size measured in the same pass (the --copy-calibration leg).  The record is
@@ -89,7 +89,9 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="timed steps of the FP64 form (default: same as --steps)")
-    ap.add_argument("--kernel", choices=["auto", "generic", "tiled"], default="auto")
+    ap.add_argument("--kernel", choices=["auto", "composed", "tiled", "generic"], default="auto")
+    ap.add_argument("--no-composed", action="store_true",
+                    help="skip the composed-map FP32 form reported beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-operand form")
@@ -202,7 +204,7 @@ def main():
     if args.copy_calibration:
         log("[bench] copy calibration")
         copy_calibration(torch)
-    kernel = {"auto": B.HW_KERNEL_AUTO, "generic": B.HW_KERNEL_GENERIC,
+    kernel = {"auto": B.HW_KERNEL_AUTO, "composed": B.HW_KERNEL_COMPOSED, "generic": B.HW_KERNEL_GENERIC,
               "tiled": B.HW_KERNEL_TILED}[args.kernel]
     n = args.n
     log(f"[bench] building {n}^3 m=3 pulse data on the GPU")
@@ -235,6 +237,19 @@ def main():
             err64, rel64, _ = l2_errors(torch, W, w, s64, (K64 + Wm) * spec.dt)
     s64.close()
 
+    # the composed-map kernel in FP32 (the FP64 form's kernel), reported beside: faster
+    # than the tiled one, with more rounding error
+    comp32 = None
+    if not args.no_composed and args.kernel == "auto":
+        log(f"[bench] composed-map fp32 kernel: warmup {Wm}, timed {K} steps")
+        sc, elc, evc = run_form(torch, B, W, w, B.HW_FP32, B.HW_KERNEL_COMPOSED, K, Wm)
+        comp32 = {"value": cells_per_step * K / elc, "unit": "cell-updates/s", "steps": K,
+                  "ms_per_step": elc / K * 1e3, "kernel_avg_ms": evc / (2 * K)}
+        if not args.no_error:
+            errc, relc, _ = l2_errors(torch, W, w, sc, t_final)
+            comp32.update({"l2_abs": errc, "l2_rel": relc})
+        sc.close()
+
     # BF16-operand form (FP32 storage and accumulation), reported beside the others
     bf16 = None
     if not args.no_bf16:
@@ -255,14 +270,14 @@ def main():
     launches = 2 * K
     avg_ms = ev32 / launches
     cells_per_launch = spec.nodes(W.PRIMAL)
-    tiled = args.kernel != "generic"
+    recorded = args.kernel in ("auto", "tiled")  # the FP32 kernel the traffic record belongs to
     flops_launch = FLOPS_PER_CELL * cells_per_launch
     bytes_launch = BYTES_PER_CELL["fp32"] * cells_per_launch
     ach_tflops = flops_launch / (avg_ms * 1e-3) / 1e12
     ach_gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "alu", "achieved": round(ach_tflops, 2),
             "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
-            "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": traffic_bytes() if (tiled and n == 256) else None,
+            "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": traffic_bytes() if (recorded and n == 256) else None,
             "kernel_avg_ms": round(avg_ms, 4), "hbm_algorithmic_gbs": round(ach_gbs, 1),
             "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
 
@@ -285,6 +300,7 @@ def main():
         "fp64_form": {"value": rate64, "unit": "cell-updates/s", "steps": K64,
                       "ms_per_step": el64 / K64 * 1e3, "speedup_fp32_over_fp64": rate32 / rate64,
                       "kernel_avg_ms": ev64 / (2 * K64)},
+        "composed_fp32_form": comp32,
         "bf16_form": bf16,
         "roofline": roof,
         "cpu_baseline": cpu,

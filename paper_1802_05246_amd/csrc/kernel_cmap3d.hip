@@ -14,7 +14,8 @@
 // (<= 16) x 91 product with the class's column of selected sums, applied to 16 cells at a
 // time on the matrix cores.
 //
-// A workgroup owns a column of 4 x CY cells (CY = 8 in FP32, 4 in FP64) and walks it
+// A workgroup (1024 threads in FP32, 512 in FP64) owns a column of 4 x CY cells (CY = 8
+// in FP32, 4 in FP64) and walks it
 // upwards in z, one node layer of the input grid at a time.  Per layer:
 //   1. the layer's 5 x (CY+1) nodes, loaded into registers during the previous layer, are
 //      stashed in LDS (ghost nodes outside non-periodic walls mirrored with the odd /
@@ -25,7 +26,7 @@
 //   3. the class products: S_p[l] = T_{pxy}(lower layer)[l] +- T_{pxy}(upper layer)[l]
 //      read as the B operand, the class block of the composed map as the A operand
 //      (registers), one 16x16x4 product chain of 23 steps per class and group of 16
-//      cells (FP32: one class and two groups per wave, FP64: two classes, one group);
+//      cells, one chain per wave;
 //      the outputs are staged in LDS for the coalesced stores of step 1.
 #include <hip/hip_runtime.h>
 
@@ -44,6 +45,7 @@ constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded 
 constexpr int TL = 92;                        // stride of one butterfly sum over l
 constexpr int TSZ = 8 * TL + 2;               // cell stride of the butterfly sums [pxy][l][layer]
 constexpr int OUS = 68;                       // cell stride of the staged u outputs
+
 
 template <typename T>
 struct Mf;
@@ -126,16 +128,18 @@ __host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
     }
 }
 
-template <typename T, int CY>
-__global__ void __launch_bounds__(16 * CX * CY) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
+template <typename T, int CY, int NT>
+__global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
 {
     using MF = Mf<T>;
     using SH = CShared<T, CY>;
-    constexpr int NC = SH::NC, NNODE = SH::NNODE, NT = 16 * NC, NW = NT / 64;
-    constexpr int CPW = 8 / NW;   // parity classes per wave
-    constexpr int GPW = NC / 16;  // groups of 16 cells per wave
+    constexpr int NC = SH::NC, NNODE = SH::NNODE, NW = NT / 64;
+    // the 8 classes x NC/16 cell groups of a layer's products over the waves: a wave
+    // keeps CPW classes (A operands in registers) and applies each to GPW groups
+    constexpr int CPW = NW >= 8 ? 1 : 8 / NW;
+    constexpr int GPW = NW >= 8 ? (NC / 16) / (NW / 8) : NC / 16;
     constexpr int NLOAD = (NNODE * NI + NT - 1) / NT;
-    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+    static_assert(NW == 4 || (NW % 8 == 0 && (NC / 16) % (NW / 8) == 0), "waves must tile the products");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SH& sh = *reinterpret_cast<SH*>(smem_raw);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -153,12 +157,13 @@ __global__ void __launch_bounds__(16 * CX * CY) k_cmap3d(TiledArgs a, int tz, co
         sh.tsum[(r >> 2) * TSZ + ((r & 3) * TL + 91) * 2 + b] = T(0);
     }
 
+    auto grp_of = [&](int g) { return NW >= 8 ? wave / 8 + (NW / 8) * g : g; };
     // the wave's classes: A operands, B offsets, output targets (registers)
     T ta[CPW][KS];
     int tb[CPW][KS], rdst[CPW][4];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-        const int q = (wave % 8) + NW * c;
+        const int q = NW >= 8 ? wave % 8 : wave + NW * c;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             ta[c][ks] = tabs->ta[q][ks][lane];
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(16 * CX * CY) k_cmap3d(TiledArgs a, int tz, co
 #pragma unroll
                     for (int ks = ks0; ks < ks1; ++ks) {
                         const int info = tb[c][ks];
-                        const int o = (16 * g + (lane & 15)) * TSZ + 2 * (info & 0x7fff);
+                        const int o = (16 * grp_of(g) + (lane & 15)) * TSZ + 2 * (info & 0x7fff);
                         const T2 v = *reinterpret_cast<const T2*>(sh.tsum + o);
                         const T lo = lo_odd ? v.y : v.x, hi = lo_odd ? v.x : v.y;
                         bv[c][g][ks] = (info & 0x8000) ? lo - hi : lo + hi;
@@ -312,7 +317,7 @@ __global__ void __launch_bounds__(16 * CX * CY) k_cmap3d(TiledArgs a, int tz, co
         for (int c = 0; c < CPW; ++c)
 #pragma unroll
             for (int g = 0; g < GPW; ++g) {
-                const int cell = 16 * g + (lane & 15);
+                const int cell = 16 * grp_of(g) + (lane & 15);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int dst = rdst[c][r];
@@ -381,12 +386,11 @@ hipError_t create(const ProblemDesc& D, void** out)
     return hipSuccess;
 }
 
-template <typename T, int CY>
+template <typename T, int CY, int NT>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
-    constexpr int NT = 16 * CX * CY;
     const size_t lds = sizeof(CShared<T, CY>);
-    auto kern = k_cmap3d<T, CY>;
+    auto kern = k_cmap3d<T, CY, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int tz = 64;
@@ -412,7 +416,8 @@ hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
     if (!a.tables) return hipErrorInvalidValue;
     for (int i = 0; i < 3; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
-    // FP32: 4 x 8-cell columns (512 threads, one class per wave); FP64: 4 x 4 (the
-    // butterfly sums of two layers of 32 cells would not fit in LDS)
-    return fp64 ? launch<double, 4>(a, st) : launch<float, 8>(a, st);
+    // FP32: 4 x 8-cell columns, 1024 threads (one class and one group of 16 cells per
+    // wave, four waves per SIMD); FP64: 4 x 4 (the butterfly sums of two layers of 32
+    // cells would not fit in LDS), 512 threads (two waves per SIMD)
+    return fp64 ? launch<double, 4, 512>(a, st) : launch<float, 8, 1024>(a, st);
 }

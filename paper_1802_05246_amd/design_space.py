@@ -1,5 +1,6 @@
 """Rates of the kernel forms on the 3-D dissipative m = 3 workload (256^3 periodic cube,
-8 Gaussian pulses, c dt / h = 0.9): the fused tiled MFMA kernel (exact series), the
+8 Gaussian pulses, c dt / h = 0.9): the composed-map MFMA kernel (exact and cut series),
+the fused tiled MFMA kernel (exact series), the
 fused generic kernel with the exact series and with the series cut after stage 2m+1
 or 2m+2 (the paper's GPU kernels ran 2m+2 stages, Sec. 6.1), and the two-kernel form
 (interpolants written to memory by one kernel and read back by a second, the paper's
@@ -18,7 +19,9 @@ import time
 from . import binding as B
 from . import workloads as W
 
-FORMS = [("tiled fused, exact series", B.HW_KERNEL_TILED, 0),
+FORMS = [("composed map on the matrix cores, exact series", B.HW_KERNEL_COMPOSED, 0),
+         ("composed map, series cut after stage 2m+2", B.HW_KERNEL_COMPOSED, 8),
+         ("tiled fused, exact series", B.HW_KERNEL_TILED, 0),
          ("generic fused, exact series", B.HW_KERNEL_GENERIC, 0),
          ("generic fused, series cut after stage 2m+1", B.HW_KERNEL_GENERIC, 7),
          ("generic fused, series cut after stage 2m+2", B.HW_KERNEL_GENERIC, 8),
