@@ -21,12 +21,13 @@
 //      stashed in LDS (ghost nodes outside non-periodic walls mirrored with the odd /
 //      even signs of Sec. 3.1.3); the cell layer finished in the previous pass is stored
 //      and the loads of the next node layer are issued;
-//   2. x/y butterflies: per cell and input l, the four sums over the cell's corners of
-//      this layer, T_{pxy}[l] (kept for the next layer as well);
-//   3. the class products: S_p[l] = T_{pxy}(lower layer)[l] +- T_{pxy}(upper layer)[l]
-//      read as the B operand, the class block of the composed map as the A operand
-//      (registers), one 16x16x4 product chain of 23 steps per class and group of 16
-//      cells, one chain per wave;
+//   2. butterflies: per cell and input l, the four sums over the cell's corners of this
+//      layer, T_{pxy}[l], combined with those of the layer below (kept in registers
+//      since the previous pass) into the eight sums S_p[l] = T_{pxy}(lower)[l] +-
+//      T_{pxy}(upper)[l], written to LDS;
+//   3. the class products: the selected sums S_p[l] read as the B operand, the class
+//      block of the composed map as the A operand (registers), one 16x16x4 product
+//      chain of 23 steps per class and group of 16 cells, one chain per wave;
 //      the outputs are staged in LDS for the coalesced stores of step 1.
 #include <hip/hip_runtime.h>
 
@@ -43,7 +44,12 @@ constexpr int NI = 91;                        // inputs per node: u 64 + v 27
 constexpr int NDP = 93;                       // LDS node stride (odd: spreads the banks)
 constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded to 92)
 constexpr int TL = 92;                        // stride of one butterfly sum over l
-constexpr int TSZ = 8 * TL + 2;               // cell stride of the butterfly sums [pxy][l][layer]
+// cell stride of the butterfly sums [p][l]: with 16 cells of a product group at this
+// stride and the 4 inputs of a K-step (l = 4 ks + 0..3) in the four residues mod 4,
+// the operand reads of a wave touch every LDS bank once (FP32: stride 4 x odd; FP64,
+// two banks per value, once per half wave: stride 2 x odd)
+template <typename T>
+constexpr int tsz() { return sizeof(T) == 4 ? 740 : 738; }
 constexpr int OUS = 68;                       // cell stride of the staged u outputs
 
 
@@ -65,8 +71,8 @@ struct Mf<double> {
 // Tables per problem (lambda and tau are inside the composed map):
 //   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, input k = 4 ks + lane / 16)
 //   tb[8][KS][4]   per (class, K-step, lane / 16): offset of the selected butterfly sum in a
-//                  cell's block (pxy * TL + l), bit 15 set when the upper layer enters with
-//                  a minus sign (p_z = 1); input 91 (padding) reads a zero slot
+//                  cell's block, p * TL + l with p = p_x + 2 p_y + 4 p_z; input 91
+//                  (padding) reads slot 91 of p = 0, which holds zero
 //   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
 template <typename T>
 struct CTables {
@@ -75,13 +81,11 @@ struct CTables {
     int tr[8][16];
 };
 
-// column of CX x CY cells: NC cells per layer, 16 NC threads
-// the butterfly sums of the two node layers of a cell layer sit side by side (layer
-// parity fastest), so that one 2-element read gives both
+// column of CX x CY cells: NC cells per layer
 template <typename T, int CY>
 struct CShared {
     static constexpr int NC = CX * CY, NNODE = NXL * (CY + 1);
-    alignas(16) T tsum[NC * TSZ];
+    alignas(16) T tsum[NC * tsz<T>()];
     alignas(16) T out[NC * (OUS + 27)];
     T nd[NNODE * NDP];
 };
@@ -151,11 +155,10 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
     const T* __restrict__ gu = (const T*)a.u_in;
     const T* __restrict__ gv = (const T*)a.v_in;
 
-    // padding input 91 of every cell block reads zero in both layers
-    for (int i = tid; i < 2 * NC * 4; i += NT) {
-        const int b = i / (NC * 4), r = i % (NC * 4);
-        sh.tsum[(r >> 2) * TSZ + ((r & 3) * TL + 91) * 2 + b] = T(0);
-    }
+    constexpr int TSZ = tsz<T>();
+    // slot 91 of every node (the padding input) holds zero, so the butterflies write
+    // zero sums for it; the stash never writes it
+    for (int i = tid; i < NNODE; i += NT) sh.nd[i * NDP + 91] = T(0);
 
     auto grp_of = [&](int g) { return NW >= 8 ? wave / 8 + (NW / 8) * g : g; };
     // the wave's classes: A operands, B offsets, output targets (registers)
@@ -249,6 +252,8 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
         }
     };
 
+    constexpr int NBF = (NC * TL + NT - 1) / NT; // butterfly slots per thread
+    T prev[NBF][4];                              // T_pxy of the lower node layer
     fetch(cz0 + off);
     for (int step = 0; step < nlayers; ++step) {
         stash();
@@ -256,26 +261,35 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
         if (step >= 2) store_layer(cz0 + step - 2);
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
-        // ---- 2. x/y butterflies of this layer: T_p[l], p = px + 2 py ----
-        T* tcur = sh.tsum + (step & 1);
-        for (int t = tid; t < NC * NI; t += NT) {
-            const int cell = t % NC, l = t / NC;
+        // ---- 2. butterflies: T_pxy[l] of this layer (pxy = px + 2 py), combined with
+        //      the lower layer's into S_p[l]; a wave covers 16 cells x 4 inputs, and a
+        //      thread keeps the same (cell, l) slots in every pass ----
+#pragma unroll
+        for (int k = 0; k < NBF; ++k) {
+            const int t = tid + k * NT;
+            if (t >= NC * TL) break;
+            const int hi = t >> 6;
+            const int cell = (t & 15) + 16 * (hi % (NC / 16)), l = 4 * (hi / (NC / 16)) + ((t >> 4) & 3);
             const int n00 = (cell % CX) + NXL * (cell / CX);
             const T x00 = sh.nd[n00 * NDP + l], x10 = sh.nd[(n00 + 1) * NDP + l];
             const T x01 = sh.nd[(n00 + NXL) * NDP + l], x11 = sh.nd[(n00 + NXL + 1) * NDP + l];
             const T p = x00 + x10, q = x00 - x10, r = x01 + x11, s = x01 - x11;
-            T* dst = tcur + cell * TSZ + 2 * l;
-            dst[0] = p + r;
-            dst[2 * TL] = q + s;
-            dst[4 * TL] = p - r;
-            dst[6 * TL] = q - s;
+            const T cur[4] = {p + r, q + s, p - r, q - s};
+            if (step > 0) {
+                T* dst = sh.tsum + cell * TSZ + l;
+#pragma unroll
+                for (int pxy = 0; pxy < 4; ++pxy) {
+                    dst[pxy * TL] = prev[k][pxy] + cur[pxy];
+                    dst[(4 + pxy) * TL] = prev[k][pxy] - cur[pxy];
+                }
+            }
+#pragma unroll
+            for (int pxy = 0; pxy < 4; ++pxy) prev[k][pxy] = cur[pxy];
         }
         __syncthreads();
         if (step == 0) continue; // the first layer only primes the sums
 
         // ---- 3. class products for the cell layer between the two node layers ----
-        typedef T T2 __attribute__((ext_vector_type(2)));
-        const bool lo_odd = ((step - 1) & 1) != 0; // layer parity of the lower node layer
         T bv[CPW][GPW][KS];
         auto load_b = [&](int ks0, int ks1) {
 #pragma unroll
@@ -283,13 +297,8 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
 #pragma unroll
                 for (int g = 0; g < GPW; ++g)
 #pragma unroll
-                    for (int ks = ks0; ks < ks1; ++ks) {
-                        const int info = tb[c][ks];
-                        const int o = (16 * grp_of(g) + (lane & 15)) * TSZ + 2 * (info & 0x7fff);
-                        const T2 v = *reinterpret_cast<const T2*>(sh.tsum + o);
-                        const T lo = lo_odd ? v.y : v.x, hi = lo_odd ? v.x : v.y;
-                        bv[c][g][ks] = (info & 0x8000) ? lo - hi : lo + hi;
-                    }
+                    for (int ks = ks0; ks < ks1; ++ks)
+                        bv[c][g][ks] = sh.tsum[(16 * grp_of(g) + (lane & 15)) * TSZ + tb[c][ks]];
         };
         typename MF::vec acc[CPW][GPW];
 #pragma unroll
@@ -360,13 +369,13 @@ hipError_t create(const ProblemDesc& D, void** out)
             for (int g = 0; g < 4; ++g) {
                 const int l = 4 * ks + g;
                 if (l >= NI) {
-                    h->tb[q][ks][g] = 91; // zero slot of the px = py = 0 sums
+                    h->tb[q][ks][g] = 91; // zero slot of the p = 0 sums
                     continue;
                 }
                 int lx, ly, lz;
                 coef3(l, lx, ly, lz);
                 const int px = (qx + lx) & 1, py = (qy + ly) & 1, pz = (qz + lz) & 1;
-                h->tb[q][ks][g] = ((px + 2 * py) * TL + l) | (pz ? 0x8000 : 0);
+                h->tb[q][ks][g] = (px + 2 * py + 4 * pz) * TL + l;
             }
             for (int lanei = 0; lanei < 64; ++lanei) {
                 const int i = lanei & 15, l = 4 * ks + (lanei >> 4);
