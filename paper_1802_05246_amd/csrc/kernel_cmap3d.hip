@@ -69,10 +69,11 @@ struct Mf<double> {
 };
 
 // Tables per problem (lambda and tau are inside the composed map):
-//   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, input k = 4 ks + lane / 16)
+//   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, K position 4 ks + lane / 16,
+//                  which holds input perm[4 ks + lane / 16], see create())
 //   tb[8][KS][4]   per (class, K-step, lane / 16): offset of the selected butterfly sum in a
-//                  cell's block, p * TL + l with p = p_x + 2 p_y + 4 p_z; input 91
-//                  (padding) reads slot 91 of p = 0, which holds zero
+//                  cell's block, p * TL + l with p = p_x + 2 p_y + 4 p_z (l: the input at
+//                  that K position); the padding position reads slot 91 of p = 0 (zero)
 //   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
 template <typename T>
 struct CTables {
@@ -352,6 +353,22 @@ hipError_t create(const ProblemDesc& D, void** out)
     int n_in = 0, n_out = 0;
     hw_cell_map(D, G, n_in, n_out); // [8 * 91][91], corner 0's rows first
     if (n_out != NI || n_in != 8 * NI) return hipErrorInvalidValue;
+    // K order of the inputs (the products accumulate in it, in the element type):
+    // higher-degree coefficients first.  On smooth data those are the smaller terms, so
+    // the running sums stay small until the large low-degree terms enter; in FP32 that
+    // order leaves several times less rounding error than the natural one.  Position
+    // 91 is the padding input.
+    int perm[4 * KS];
+    {
+        int k = 0;
+        for (int dg = 9; dg >= 0; --dg)
+            for (int l = 0; l < NI; ++l) {
+                int lx, ly, lz;
+                coef3(l, lx, ly, lz);
+                if (lx + ly + lz == dg) perm[k++] = l;
+            }
+        while (k < 4 * KS) perm[k++] = -1;
+    }
     CTables<T>* h = new CTables<T>();
     std::memset(h, 0, sizeof *h);
     for (int q = 0; q < 8; ++q) {
@@ -367,8 +384,8 @@ hipError_t create(const ProblemDesc& D, void** out)
             h->tr[q][r] = r < nrow ? (rows[r] >= 64 ? 0x1000 | (rows[r] - 64) : rows[r]) : -1;
         for (int ks = 0; ks < KS; ++ks) {
             for (int g = 0; g < 4; ++g) {
-                const int l = 4 * ks + g;
-                if (l >= NI) {
+                const int l = perm[4 * ks + g];
+                if (l < 0) {
                     h->tb[q][ks][g] = 91; // zero slot of the p = 0 sums
                     continue;
                 }
@@ -378,8 +395,8 @@ hipError_t create(const ProblemDesc& D, void** out)
                 h->tb[q][ks][g] = (px + 2 * py + 4 * pz) * TL + l;
             }
             for (int lanei = 0; lanei < 64; ++lanei) {
-                const int i = lanei & 15, l = 4 * ks + (lanei >> 4);
-                h->ta[q][ks][lanei] = (i < nrow && l < NI) ? (T)G[(size_t)l * NI + rows[i]] : T(0);
+                const int i = lanei & 15, l = perm[4 * ks + (lanei >> 4)];
+                h->ta[q][ks][lanei] = (i < nrow && l >= 0) ? (T)G[(size_t)l * NI + rows[i]] : T(0);
             }
         }
     }
