@@ -35,19 +35,19 @@ FLOPS_PER_CELL = 48272
 BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 
 
-# HBM traffic of one launch of the dominant kernel (the FP32 tiled half step on this
+# HBM traffic of one launch of the dominant kernel (the FP32 composed-map half step on this
 # workload), from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by the ratio of true to counted bytes of a plain copy of
 # known size measured in the same pass (the --copy-calibration leg).  The record is
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "87b5cb6d02f24d306b16841ca3b6933ecb38b4c4cfd5437227f7651ea01e0eae",
-    "fetch_bytes": 8515004927,  # FETCH_SIZE 4157855.7 KiB x 1048576/524305.5 (copy: 1 GiB read)
+    "source_sha256": "48dfa82f212fa56840a48d71e86dd642a90f44a374e79f38550810d005afdf5f",
+    "fetch_bytes": 8519399437,  # FETCH_SIZE 4159982.0 KiB x 1048576/524303.0 (copy: 1 GiB read)
     "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
-    "profile": "profiles/k_tiled3d_m3-diss3d_m3_256cube-hbm_bytes.md",
+    "profile": "profiles/k_cmap3d-diss3d_m3_256cube-hbm_bytes.md",
 }
-TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_tiled3d.hip")
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_cmap3d.hip")
 COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy (1 GiB read + 1 GiB written)
 
 
@@ -90,8 +90,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="timed steps of the FP64 form (default: same as --steps)")
     ap.add_argument("--kernel", choices=["auto", "composed", "tiled", "generic"], default="auto")
-    ap.add_argument("--no-composed", action="store_true",
-                    help="skip the composed-map FP32 form reported beside")
+    ap.add_argument("--no-tiled", action="store_true",
+                    help="skip the tiled-kernel FP32 form reported beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-operand form")
@@ -237,17 +237,17 @@ def main():
             err64, rel64, _ = l2_errors(torch, W, w, s64, (K64 + Wm) * spec.dt)
     s64.close()
 
-    # the composed-map kernel in FP32 (the FP64 form's kernel), reported beside: faster
-    # than the tiled one, with more rounding error
-    comp32 = None
-    if not args.no_composed and args.kernel == "auto":
-        log(f"[bench] composed-map fp32 kernel: warmup {Wm}, timed {K} steps")
-        sc, elc, evc = run_form(torch, B, W, w, B.HW_FP32, B.HW_KERNEL_COMPOSED, K, Wm)
-        comp32 = {"value": cells_per_step * K / elc, "unit": "cell-updates/s", "steps": K,
-                  "ms_per_step": elc / K * 1e3, "kernel_avg_ms": evc / (2 * K)}
+    # the LDS-tiled kernel in FP32 (the BF16 form's kernel), reported beside the default
+    # composed-map kernel
+    tiled32 = None
+    if not args.no_tiled and args.kernel == "auto":
+        log(f"[bench] tiled fp32 kernel: warmup {Wm}, timed {K} steps")
+        sc, elc, evc = run_form(torch, B, W, w, B.HW_FP32, B.HW_KERNEL_TILED, K, Wm)
+        tiled32 = {"value": cells_per_step * K / elc, "unit": "cell-updates/s", "steps": K,
+                   "ms_per_step": elc / K * 1e3, "kernel_avg_ms": evc / (2 * K)}
         if not args.no_error:
             errc, relc, _ = l2_errors(torch, W, w, sc, t_final)
-            comp32.update({"l2_abs": errc, "l2_rel": relc})
+            tiled32.update({"l2_abs": errc, "l2_rel": relc})
         sc.close()
 
     # BF16-operand form (FP32 storage and accumulation), reported beside the others
@@ -270,7 +270,7 @@ def main():
     launches = 2 * K
     avg_ms = ev32 / launches
     cells_per_launch = spec.nodes(W.PRIMAL)
-    recorded = args.kernel in ("auto", "tiled")  # the FP32 kernel the traffic record belongs to
+    recorded = args.kernel in ("auto", "composed")  # the FP32 kernel the traffic record belongs to
     flops_launch = FLOPS_PER_CELL * cells_per_launch
     bytes_launch = BYTES_PER_CELL["fp32"] * cells_per_launch
     ach_tflops = flops_launch / (avg_ms * 1e-3) / 1e12
@@ -300,7 +300,7 @@ def main():
         "fp64_form": {"value": rate64, "unit": "cell-updates/s", "steps": K64,
                       "ms_per_step": el64 / K64 * 1e3, "speedup_fp32_over_fp64": rate32 / rate64,
                       "kernel_avg_ms": ev64 / (2 * K64)},
-        "composed_fp32_form": comp32,
+        "tiled_fp32_form": tiled32,
         "bf16_form": bf16,
         "roofline": roof,
         "cpu_baseline": cpu,

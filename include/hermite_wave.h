@@ -65,9 +65,8 @@ typedef enum {
 } hw_precision;
 
 typedef enum {
-    HW_KERNEL_AUTO = 0,    /* 3-D dissipative m = 3: tiled for the FP32 / BF16 full variant
-                              with the exact series, composed otherwise; d <= 2: dense where
-                              it exists; else generic */
+    HW_KERNEL_AUTO = 0,    /* 3-D dissipative m = 3: composed in FP64 and FP32, tiled for
+                              BF16 operands; d <= 2: dense where it exists; else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
     HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
     HW_KERNEL_SPLIT = 3,   /* two kernels per half step, as in the paper's two-kernel GPU

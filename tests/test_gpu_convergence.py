@@ -61,9 +61,9 @@ def _c4_error(B, n, steps, precision):
     return math.sqrt(h3 * float(((val - ex) ** 2).sum())), t
 
 
-def test_pulses_3d_tiled_rate():
+def test_pulses_3d_rate():
     """The 3-D benchmark problem (8 Gaussian pulses, m = 3, c dt / h = 0.9) through the
-    tiled kernel on 64^3, 128^3 and 256^3 to the same final time, against the exact
+    default 3-D kernel on 64^3, 128^3 and 256^3 to the same final time, against the exact
     radial solution: the error falls at the dissipative order 2m - 1 = 5 (slope fitted over the
     fourfold refinement)."""
     B = _B()
