@@ -14,9 +14,8 @@
 // (<= 16) x 91 product with the class's column of selected sums, applied to 16 cells at a
 // time on the matrix cores.
 //
-// A workgroup (1024 threads in FP32, 512 in FP64) owns a column of 4 x CY cells (CY = 8
-// in FP32, 4 in FP64) and walks it
-// upwards in z, one node layer of the input grid at a time.  Per layer:
+// A workgroup (512 threads) owns a column of 4 x CY cells (CY = 4) and walks it upwards
+// in z, one node layer of the input grid at a time.  Per layer:
 //   1. the layer's 5 x (CY+1) nodes, loaded into registers during the previous layer, are
 //      stashed in LDS (ghost nodes outside non-periodic walls mirrored with the odd /
 //      even signs of Sec. 3.1.3); the cell layer finished in the previous pass is stored
@@ -442,8 +441,10 @@ hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
     if (!a.tables) return hipErrorInvalidValue;
     for (int i = 0; i < 3; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
-    // FP32: 4 x 8-cell columns, 1024 threads (one class and one group of 16 cells per
-    // wave, four waves per SIMD); FP64: 4 x 4 (the butterfly sums of two layers of 32
-    // cells would not fit in LDS), 512 threads (two waves per SIMD)
-    return fp64 ? launch<double, 4, 512>(a, st) : launch<float, 8, 1024>(a, st);
+    // 4 x 4-cell columns, 512 threads: one class and one group of 16 cells per wave.
+    // FP32: 63 KB of LDS and at most 128 registers, so two workgroups share a CU (four
+    // waves per SIMD) and one's products overlap the other's butterflies (5% faster than
+    // one 4 x 8-cell workgroup of 1024 threads); FP64: 125 KB, one workgroup per CU (two
+    // waves per SIMD)
+    return fp64 ? launch<double, 4, 512>(a, st) : launch<float, 4, 512>(a, st);
 }
