@@ -78,6 +78,38 @@ def test_pulses_3d_rate():
     assert abs(rate - 5) < 0.3
 
 
+def test_pulses_3d_fp32_form_within_bar():
+    """The 3-D benchmark run itself (256^3, m = 3, c dt / h = 0.9, 200 steps) in the FP32
+    form: the relative L2 error of the value coefficient at the primal nodes, against the
+    exact radial solution and against the FP64 form, stays within the FP32 bar of this
+    workload, 1e-5 (the FP64 form's own error is 5e-9, so both measure the FP32
+    rounding).  The order in which the composed map accumulates its inputs decides this:
+    ascending input order gave 1.4e-5 here."""
+    B = _B()
+    w = W.c4_3d(n=256, device="cuda")
+    vals = {}
+    for prec in (B.HW_FP64, B.HW_FP32):
+        s = B.Solver(w.spec, precision=prec)
+        s.set_state(w.u0, w.v0)
+        s.advance(200)
+        u, _ = s.get_state()
+        s.close()
+        vals[prec] = u[:, 0].clone()
+        del u
+    pts = torch.as_tensor(w.spec.points(W.PRIMAL), device="cuda")
+    ex = torch.empty_like(vals[B.HW_FP64])
+    chunk = 1 << 21
+    for a in range(0, pts.shape[0], chunk):
+        ex[a:a + chunk] = w.exact(200 * w.spec.dt, points=pts[a:a + chunk], xp=torch)
+    nex = float(torch.linalg.norm(ex))
+    e64 = float(torch.linalg.norm(vals[B.HW_FP64] - ex)) / nex
+    e32 = float(torch.linalg.norm(vals[B.HW_FP32] - ex)) / nex
+    d = float(torch.linalg.norm(vals[B.HW_FP32] - vals[B.HW_FP64]) / torch.linalg.norm(vals[B.HW_FP64]))
+    _log(f"[c4 fp32] error vs exact: fp64 {e64:.3e}, fp32 {e32:.3e}; fp32 vs fp64 {d:.3e}")
+    assert e64 < 1e-7
+    assert e32 <= 1e-5 and d <= 1e-5
+
+
 def _oracle_drift(spec, up, ud, steps, every):
     """Largest relative energy change of the FP64 oracle on the same run, sampled at the
     same half steps as the library run below."""
