@@ -43,10 +43,11 @@ constexpr int NI = 91;                        // inputs per node: u 64 + v 27
 constexpr int NDP = 93;                       // LDS node stride (odd: spreads the banks)
 constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded to 92)
 constexpr int TL = 92;                        // stride of one butterfly sum over l
-// cell stride of the butterfly sums [p][l]: with 16 cells of a product group at this
-// stride and the 4 inputs of a K-step (l = 4 ks + 0..3) in the four residues mod 4,
-// the operand reads of a wave touch every LDS bank once (FP32: stride 4 x odd; FP64,
-// two banks per value, once per half wave: stride 2 x odd)
+// cell stride of the butterfly sums [p][k] (k: the K position of the input in the
+// products): with 16 cells of a product group at this stride and the 4 positions of a
+// K-step (k = 4 ks + 0..3) in the four residues mod 4, the operand reads of a wave touch
+// every LDS bank once (FP32: stride 4 x odd; FP64, two banks per value, once per half
+// wave: stride 2 x odd)
 template <typename T>
 constexpr int tsz() { return sizeof(T) == 4 ? 740 : 738; }
 constexpr int OUS = 68;                       // cell stride of the staged u outputs
@@ -71,14 +72,17 @@ struct Mf<double> {
 //   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, K position 4 ks + lane / 16,
 //                  which holds input perm[4 ks + lane / 16], see create())
 //   tb[8][KS][4]   per (class, K-step, lane / 16): offset of the selected butterfly sum in a
-//                  cell's block, p * TL + l with p = p_x + 2 p_y + 4 p_z (l: the input at
-//                  that K position); the padding position reads slot 91 of p = 0 (zero)
+//                  cell's block, p * TL + k with p = p_x + 2 p_y + 4 p_z of the input at
+//                  K position k = 4 ks + lane / 16; the padding position k = 91 reads the
+//                  zero sums of the zero node slot 91
+//   kl[4 KS]       input at K position k (91 for the padding position)
 //   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
 template <typename T>
 struct CTables {
     T ta[8][KS][64];
     int tb[8][KS][4];
     int tr[8][16];
+    int kl[4 * KS];
 };
 
 // column of CX x CY cells: NC cells per layer
@@ -254,6 +258,12 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
 
     constexpr int NBF = (NC * TL + NT - 1) / NT; // butterfly slots per thread
     T prev[NBF][4];                              // T_pxy of the lower node layer
+    int bl[NBF];                                 // input of each slot
+#pragma unroll
+    for (int k = 0; k < NBF; ++k) {
+        const int t = tid + k * NT;
+        bl[k] = t < NC * TL ? tabs->kl[4 * ((t >> 6) / (NC / 16)) + ((t >> 4) & 3)] : 0;
+    }
     fetch(cz0 + off);
     for (int step = 0; step < nlayers; ++step) {
         stash();
@@ -262,21 +272,23 @@ __global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTable
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
         // ---- 2. butterflies: T_pxy[l] of this layer (pxy = px + 2 py), combined with
-        //      the lower layer's into S_p[l]; a wave covers 16 cells x 4 inputs, and a
-        //      thread keeps the same (cell, l) slots in every pass ----
+        //      the lower layer's into S_p[l], stored at the input's K position kp; a
+        //      wave covers 16 cells x 4 positions, and a thread keeps the same (cell, kp)
+        //      slots in every pass ----
 #pragma unroll
         for (int k = 0; k < NBF; ++k) {
             const int t = tid + k * NT;
             if (t >= NC * TL) break;
             const int hi = t >> 6;
-            const int cell = (t & 15) + 16 * (hi % (NC / 16)), l = 4 * (hi / (NC / 16)) + ((t >> 4) & 3);
+            const int cell = (t & 15) + 16 * (hi % (NC / 16)), kp = 4 * (hi / (NC / 16)) + ((t >> 4) & 3);
+            const int l = bl[k];
             const int n00 = (cell % CX) + NXL * (cell / CX);
             const T x00 = sh.nd[n00 * NDP + l], x10 = sh.nd[(n00 + 1) * NDP + l];
             const T x01 = sh.nd[(n00 + NXL) * NDP + l], x11 = sh.nd[(n00 + NXL + 1) * NDP + l];
             const T p = x00 + x10, q = x00 - x10, r = x01 + x11, s = x01 - x11;
             const T cur[4] = {p + r, q + s, p - r, q - s};
             if (step > 0) {
-                T* dst = sh.tsum + cell * TSZ + l;
+                T* dst = sh.tsum + cell * TSZ + kp;
 #pragma unroll
                 for (int pxy = 0; pxy < 4; ++pxy) {
                     dst[pxy * TL] = prev[k][pxy] + cur[pxy];
@@ -370,6 +382,7 @@ hipError_t create(const ProblemDesc& D, void** out)
     }
     CTables<T>* h = new CTables<T>();
     std::memset(h, 0, sizeof *h);
+    for (int k = 0; k < 4 * KS; ++k) h->kl[k] = perm[k] < 0 ? 91 : perm[k];
     for (int q = 0; q < 8; ++q) {
         const int qx = q & 1, qy = (q >> 1) & 1, qz = (q >> 2) & 1;
         // rows: the 8 u outputs of the class, then its v outputs
@@ -385,13 +398,13 @@ hipError_t create(const ProblemDesc& D, void** out)
             for (int g = 0; g < 4; ++g) {
                 const int l = perm[4 * ks + g];
                 if (l < 0) {
-                    h->tb[q][ks][g] = 91; // zero slot of the p = 0 sums
+                    h->tb[q][ks][g] = 4 * ks + g; // p = 0: the sums of the zero node slot
                     continue;
                 }
                 int lx, ly, lz;
                 coef3(l, lx, ly, lz);
                 const int px = (qx + lx) & 1, py = (qy + ly) & 1, pz = (qz + lz) & 1;
-                h->tb[q][ks][g] = (px + 2 * py + 4 * pz) * TL + l;
+                h->tb[q][ks][g] = (px + 2 * py + 4 * pz) * TL + 4 * ks + g;
             }
             for (int lanei = 0; lanei < 64; ++lanei) {
                 const int i = lanei & 15, l = perm[4 * ks + (lanei >> 4)];
