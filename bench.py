@@ -42,8 +42,8 @@ BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "d24c3613c0b2036604ac24e738f00ce77ff8c5d00c98e4e36168b30b1d5ea83f",
-    "fetch_bytes": 8792013551,  # FETCH_SIZE 4293119.9 KiB x 1048576/524305.6 (copy: 1 GiB read)
+    "source_sha256": "f42f748cf10d867348d1ab6717541227158e032236dcb28fdb6ed74379815047",
+    "fetch_bytes": 8793245137,  # FETCH_SIZE 4293719.2 KiB x 1048576/524305.4 (copy: 1 GiB read)
     "write_bytes": 6174015504,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-hbm_bytes.md",
 }
