@@ -431,8 +431,11 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
     auto kern = k_cmap3d<T, CY, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    const int tz = 64;
+    // z-chunks of 64 cell layers, doubled while at least 2048 workgroups remain (each
+    // chunk re-reads one node layer below it: longer chunks waste less)
     const int tiles = ((a.ext_to[0] + CX - 1) / CX) * ((a.ext_to[1] + CY - 1) / CY);
+    int tz = 64;
+    while (tz < a.ext_to[2] && (int64_t)tiles * ((a.ext_to[2] + 2 * tz - 1) / (2 * tz)) >= 2048) tz *= 2;
     const int chunks = (a.ext_to[2] + tz - 1) / tz;
     hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz,
                        static_cast<const CTables<T>*>(a.tables));
