@@ -359,6 +359,28 @@ def test_full_size_3d_m3_sampled(prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_long_columns_3d_m3_sampled(prec):
+    """128 x 128 x 512 cells, m = 3, periodic in x, Neumann in y, Dirichlet in z, random
+    data: the 3-D kernel walks its columns in z-chunks, lengthened here to 256 cell layers
+    (two chunks per column, each starting one node layer below itself); both half-step
+    directions, sampled (the first and last output nodes sit at the walls)."""
+    B = _B()
+    _log(f"[long columns] 128 x 128 x 512 {prec}")
+    spec = W.make_spec(3, 3, [128, 128, 512], 0.0, [1.0, 1.0, 4.0], 1.0, cfl=0.9,
+                       bc=[W.PERIODIC, W.NEUMANN, W.DIRICHLET])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(91)
+    nodes = spec.nodes(W.PRIMAL)
+    u0 = torch.rand(nodes, 64, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+    v0 = torch.rand(nodes, 27, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    for steps_half in (1, 2):
+        _sampled_check(spec, precision, 48, 11 + steps_half, (u0, v0), steps_half)
+    del u0, v0
+    torch.cuda.empty_cache()
+
+
 def test_full_size_2d_cons_m4_sampled():
     """2048^2, m = 4, Dirichlet, conservative: both grids, wall nodes included."""
     B = _B()
