@@ -136,8 +136,10 @@ __host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
     }
 }
 
+// FP32: two workgroups per CU (at most 128 registers per lane), which the LDS footprint
+// allows; FP64: one
 template <typename T, int CY, int NT>
-__global__ void __launch_bounds__(NT) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
 {
     using MF = Mf<T>;
     using SH = CShared<T, CY>;
