@@ -117,7 +117,9 @@ hw_status hw_create(const hw_problem* p, hw_solver** out);
 void hw_destroy(hw_solver* s);
 
 /* Node count of `grid` and the number of u and v coefficients per node
- * (v count is 0 for the conservative method).  Any output pointer may be NULL. */
+ * (v count is 0 for the conservative method).  Any output pointer may be NULL.
+ * Sec. 2.1 (primal and dual grids), Sec. 2.2 ((m+1)^d Taylor coefficients of u and
+ * m^d of v per node, Sec. 3.1.1). */
 hw_status hw_layout(const hw_solver* s, int grid, int64_t* n_nodes, int* n_u_coef,
                     int* n_v_coef);
 
@@ -164,7 +166,9 @@ hw_status hw_half_steps(hw_solver* s, int n_half, void* stream);
  * HW_ESTATE if no state is set. */
 hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream);
 
-/* Copy the state out (device pointers, FP64, layouts as above).
+/* Copy the state out (device pointers, FP64, layouts as above; the data of Sec. 3.1.1
+ * for the dissipative method, the two staggered levels of Sec. 4.1 for the
+ * conservative one).
  * Dissipative: u and v of the grid that holds the state (hw_state_grid).
  * Conservative: u on the primal grid and u on the dual grid (newest levels). */
 hw_status hw_get_state(const hw_solver* s, double* u, double* v_or_u_dual, void* stream);
@@ -181,17 +185,24 @@ int hw_state_grid(const hw_solver* s);
 hw_status hw_energy(hw_solver* s, double* e_out, void* stream);
 
 /* Simulated time of the primal level: t0 + (half steps applied)/2 * dt for the
- * dissipative method; the primal level's time for the conservative method. */
+ * dissipative method; the primal level's time for the conservative method
+ * (Sec. 3.1.2: a full step advances both grids by dt; Sec. 4.1: the conservative
+ * levels are staggered by dt/2). */
 double hw_time(const hw_solver* s);
 
 /* Thread-local message describing the last failure ("" if none). */
 const char* hw_last_error(void);
 
 /* ---- batches: independent problems advanced together --------------------------
- * All problems of a batch share d and precision; n, m, c, dt, walls and method may
- * differ.  Each half step of the whole batch is one launch of a grid-stride kernel
- * over a work list of (problem, cell); hw_batch_advance captures the step loop in a
- * hipGraph. */
+ * Many independent problems of the kind above (each one the problem statement of
+ * Sec. 2.1 with its own grid, m, c, dt, walls and method, Sec. 3 / Sec. 4) stepped
+ * together.  All problems of a batch share d and precision.  hw_batch_advance captures
+ * the step loop in a hipGraph.  How a half step of the batch is launched depends on
+ * the kernel selector: HW_KERNEL_GENERIC runs one grid-stride launch over a work list
+ * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_DENSE run one dense launch per problem
+ * the dense kernel serves and one generic launch over the remaining problems.
+ * hw_batch_layout, hw_batch_set_state, hw_batch_cons_startup and hw_batch_get_state
+ * are hw_layout, hw_set_state, hw_cons_startup and hw_get_state for problem i. */
 hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out);
 hw_status hw_batch_layout(const hw_solver* b, int i, int grid, int64_t* n_nodes, int* n_u_coef,
                           int* n_v_coef);

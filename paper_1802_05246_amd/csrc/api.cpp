@@ -208,37 +208,6 @@ void build_ops(hw_solver* s, std::vector<double>& pool, std::vector<double>& dpo
     }
 }
 
-void fill_weights(const Prob& P, ProblemDesc& D)
-{
-    const hw_problem& p = P.p;
-    const double tau = 0.5 * p.dt;
-    D.tau = tau;
-    std::memset(D.F, 0, sizeof D.F);
-    for (int i = 0; i < 3; ++i) {
-        const double lam = (i < p.d) ? p.c * p.dt / P.h[i] : 0.0;
-        const double q = 0.25 * lam * lam; // (lambda/2)^2
-        D.lam2[i] = q;
-        for (int a = 0; a <= HW_MAXM + 1; ++a)
-            for (int b = 0; b <= HW_MAXM + 1; ++b)
-                D.F[i][a][b] = fact(a + 2 * b) / fact(a) * std::pow(q, b) / fact(b);
-    }
-    const int S = p.taylor_stages;
-    auto keep = [S](int s) { return S <= 0 || s <= S; };
-    for (int j = 0; j < HW_MAXJ; ++j) {
-        const double jf = fact(j);
-        if (p.method == HW_CONSERVATIVE) {
-            D.cuQ[j] = jf / fact(2 * j);
-            D.cuR[j] = tau * jf / fact(2 * j + 1);
-            D.cvQ[j] = D.cvR[j] = 0.0;
-        } else {
-            D.cuQ[j] = keep(2 * j + 1) ? tau * jf / fact(2 * j + 1) : 0.0;
-            D.cuR[j] = keep(2 * j + 2) ? jf / fact(2 * j + 2) : 0.0;
-            D.cvQ[j] = keep(2 * j) ? jf / fact(2 * j) : 0.0;
-            D.cvR[j] = keep(2 * j + 1) ? jf / (tau * fact(2 * j + 1)) : 0.0;
-        }
-    }
-}
-
 // descriptor of problem P for half step `phase` (0: first half of a full step) with
 // conservative slot parity q
 ProblemDesc make_desc(const hw_solver* s, const Prob& P, int phase, int q)
@@ -250,7 +219,7 @@ ProblemDesc make_desc(const hw_solver* s, const Prob& P, int phase, int q)
     D.m = p.m;
     for (int i = 0; i < 3; ++i) D.bc[i] = (i < p.d) ? p.bc[i] : HW_PERIODIC;
     D.op = s->op_off[p.m];
-    fill_weights(P, D);
+    hw_fill_weights(p, P.h, D);
     if (p.method == HW_CONSERVATIVE) {
         D.variant = HWV_CONS;
         const int to = phase == 0 ? HW_PRIMAL : HW_DUAL;

@@ -13,9 +13,55 @@
 #include "hw_kernels.h"
 
 #include <array>
+#include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "hermite_tables.h"
+
+
+// Closed-form time-sum weights of the problem descriptor (Sec. 3.1.2 and Sec. 3.3 for
+// the dissipative method, Sec. 4.1 eq. (convUpdate) and Sec. 4.3 for the conservative
+// one): with tau = dt/2 and q_i = (lambda_i/2)^2, lambda_i = c dt / h_i,
+//   F[i][a][b] = (a+2b)!/a! q_i^b / b!   (one dimension's factor of (tau^2 L)^j),
+//   dissipative: cuQ[j] = tau j!/(2j+1)!, cuR[j] = j!/(2j+2)!, cvQ[j] = j!/(2j)!,
+//                cvR[j] = j!/(tau (2j+1)!), each zero where its stage (2j+1, 2j+2, 2j,
+//                2j+1) lies beyond a taylor_stages truncation;
+//   conservative: cuQ[j] = j!/(2j)!, cuR[j] = tau j!/(2j+1)! (start-up odd sum).
+void hw_fill_weights(const hw_problem& p, const double h[3], ProblemDesc& D)
+{
+    auto fact = [](int n) {
+        double r = 1.0;
+        for (int i = 2; i <= n; ++i) r *= i;
+        return r;
+    };
+    const double tau = 0.5 * p.dt;
+    D.tau = tau;
+    std::memset(D.F, 0, sizeof D.F);
+    for (int i = 0; i < 3; ++i) {
+        const double lam = (i < p.d) ? p.c * p.dt / h[i] : 0.0;
+        const double q = 0.25 * lam * lam;
+        D.lam2[i] = q;
+        for (int a = 0; a <= HW_MAXM + 1; ++a)
+            for (int b = 0; b <= HW_MAXM + 1; ++b)
+                D.F[i][a][b] = fact(a + 2 * b) / fact(a) * std::pow(q, b) / fact(b);
+    }
+    const int S = p.taylor_stages;
+    auto keep = [S](int s) { return S <= 0 || s <= S; };
+    for (int j = 0; j < HW_MAXJ; ++j) {
+        const double jf = fact(j);
+        if (p.method == HW_CONSERVATIVE) {
+            D.cuQ[j] = jf / fact(2 * j);
+            D.cuR[j] = tau * jf / fact(2 * j + 1);
+            D.cvQ[j] = D.cvR[j] = 0.0;
+        } else {
+            D.cuQ[j] = keep(2 * j + 1) ? tau * jf / fact(2 * j + 1) : 0.0;
+            D.cuR[j] = keep(2 * j + 2) ? jf / fact(2 * j + 2) : 0.0;
+            D.cvQ[j] = keep(2 * j) ? jf / fact(2 * j) : 0.0;
+            D.cvR[j] = keep(2 * j + 1) ? jf / (tau * fact(2 * j + 1)) : 0.0;
+        }
+    }
+}
 
 namespace {
 

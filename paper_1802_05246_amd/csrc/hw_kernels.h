@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "hw_device.h"
+#include "../../include/hermite_wave.h"
 
 #include <vector>
 
@@ -44,6 +45,9 @@ struct DenseArgs {
     int64_t n_cells;
 };
 bool hw_dense_supported(int d, int m, int method, int precision);
+// The descriptor's time-sum weights (tau, lam2, F, cuQ, cuR, cvQ, cvR) for problem p with
+// cell widths h (cellmap.cpp); the same tables serve every kernel.
+void hw_fill_weights(const hw_problem& p, const double h[3], ProblemDesc& D);
 void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
 

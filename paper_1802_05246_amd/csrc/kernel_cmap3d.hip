@@ -136,10 +136,12 @@ __host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
     }
 }
 
-// FP32: two workgroups per CU (at most 128 registers per lane), which the LDS footprint
-// allows; FP64: one
+// The second launch bound is the minimum number of waves per SIMD.  FP32: two
+// workgroups of 8 waves per CU, i.e. 4 waves per SIMD, which caps the registers at 128
+// per lane (the LDS footprint allows two workgroups); FP64: one workgroup, 2 waves per
+// SIMD (at most 256 registers)
 template <typename T, int CY, int NT>
-__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 2 : 1) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
 {
     using MF = Mf<T>;
     using SH = CShared<T, CY>;

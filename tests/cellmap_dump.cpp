@@ -1,11 +1,10 @@
 // Test driver (CPU): prints the dense cell matrix G that the library composes for one
 // half step (cellmap.cpp), for a problem given on the command line, so that the tests
-// can apply it to corner data and compare with the oracle.
-//   usage: cellmap_dump d m variant lam2_0 lam2_1 tau taylor_stages
-// variant: 0 dissipative full, 1 dissipative simple, 2 conservative.  The time-sum
-// weights are filled as the library's problem descriptor defines them (F, cuQ, cuR,
-// cvQ, cvR; see hw_device.h).  Output: n_in n_out, then G row by row (input-major).
-#include <cmath>
+// can apply it to corner data and compare with the oracle.  The problem descriptor's
+// time-sum weights come from the library's own hw_fill_weights.
+//   usage: cellmap_dump d m method c dt h0 h1 taylor_stages
+// method: 0 dissipative full, 1 dissipative simple, 2 conservative.
+// Output: n_in n_out, then G row by row (input-major).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -13,44 +12,24 @@
 
 #include "hw_kernels.h"
 
-static double fact(int n)
-{
-    double r = 1.0;
-    for (int i = 2; i <= n; ++i) r *= i;
-    return r;
-}
-
 int main(int argc, char** argv)
 {
-    if (argc != 8) return 2;
+    if (argc != 9) return 2;
+    hw_problem p;
+    std::memset(&p, 0, sizeof p);
+    p.d = std::atoi(argv[1]);
+    p.m = std::atoi(argv[2]);
+    p.method = std::atoi(argv[3]);
+    p.c = std::atof(argv[4]);
+    p.dt = std::atof(argv[5]);
+    const double h[3] = {std::atof(argv[6]), std::atof(argv[7]), 1.0};
+    p.taylor_stages = std::atoi(argv[8]);
     ProblemDesc D;
     std::memset(&D, 0, sizeof D);
-    D.d = std::atoi(argv[1]);
-    D.m = std::atoi(argv[2]);
-    D.variant = std::atoi(argv[3]);
-    const double lam2[2] = {std::atof(argv[4]), std::atof(argv[5])};
-    const double tau = std::atof(argv[6]);
-    const int S = std::atoi(argv[7]);
-    D.tau = tau;
-    for (int i = 0; i < 3; ++i) {
-        const double q = i < D.d ? lam2[i] : 0.0;
-        D.lam2[i] = q;
-        for (int a = 0; a <= HW_MAXM + 1; ++a)
-            for (int b = 0; b <= HW_MAXM + 1; ++b) D.F[i][a][b] = fact(a + 2 * b) / fact(a) * std::pow(q, b) / fact(b);
-    }
-    auto keep = [S](int s) { return S <= 0 || s <= S; };
-    for (int j = 0; j < HW_MAXJ; ++j) {
-        const double jf = fact(j);
-        if (D.variant == HWV_CONS) {
-            D.cuQ[j] = jf / fact(2 * j);
-            D.cuR[j] = tau * jf / fact(2 * j + 1);
-        } else {
-            D.cuQ[j] = keep(2 * j + 1) ? tau * jf / fact(2 * j + 1) : 0.0;
-            D.cuR[j] = keep(2 * j + 2) ? jf / fact(2 * j + 2) : 0.0;
-            D.cvQ[j] = keep(2 * j) ? jf / fact(2 * j) : 0.0;
-            D.cvR[j] = keep(2 * j + 1) ? jf / (tau * fact(2 * j + 1)) : 0.0;
-        }
-    }
+    D.d = p.d;
+    D.m = p.m;
+    D.variant = p.method == HW_CONSERVATIVE ? HWV_CONS : (p.method == HW_DISS_SIMPLE ? HWV_DISS_SIMPLE : HWV_DISS_FULL);
+    hw_fill_weights(p, h, D);
     std::vector<double> G;
     int n_in = 0, n_out = 0;
     hw_cell_map(D, G, n_in, n_out);

@@ -27,9 +27,9 @@ def dump(tmp_path_factory):
                            os.path.join(ROOT, "tests", "cellmap_dump.cpp"), os.path.join(CSRC, "cellmap.cpp"),
                            "-o", exe])
 
-    def run(d, m, variant, lam2, tau, stages):
-        out = subprocess.check_output([exe, str(d), str(m), str(variant), repr(lam2[0]), repr(lam2[1]),
-                                       repr(tau), str(stages)], text=True).split()
+    def run(d, m, method, c, dt, h, stages):
+        out = subprocess.check_output([exe, str(d), str(m), str(method), repr(c), repr(dt), repr(h[0]),
+                                       repr(h[1] if len(h) > 1 else 1.0), str(stages)], text=True).split()
         n_in, n_out = int(out[0]), int(out[1])
         return np.array(out[2:], dtype=np.float64).reshape(n_in, n_out)
     return run
@@ -50,8 +50,7 @@ def test_cell_matrix_reproduces_the_oracle_half_step(dump, d, m, method, stages)
                        taylor_stages=stages)
     p = oracle.make_problem(spec.d, spec.m, spec.n, spec.xl, spec.xr, spec.c, spec.dt, spec.bc, spec.method,
                             spec.taylor_stages)
-    lam2 = [(spec.c * spec.dt / spec.h(i)) ** 2 / 4 if i < d else 0.0 for i in range(2)]
-    G = dump(d, m, method, lam2, 0.5 * spec.dt, stages)
+    G = dump(d, m, method, spec.c, spec.dt, [spec.h(i) for i in range(d)], stages)
     rng = np.random.default_rng(11 + 7 * d + m)
     nu = (m + 1) ** d
     u = rng.uniform(-1, 1, (2 ** d, nu))
@@ -71,7 +70,7 @@ def test_cell_matrix_reproduces_the_oracle_half_step(dump, d, m, method, stages)
 
 @pytest.mark.parametrize("d,m,method,stages", CASES)
 def test_cell_matrix_reflection_symmetry(dump, d, m, method, stages):
-    G = dump(d, m, method, [0.2025, 0.15], 0.37, stages)
+    G = dump(d, m, method, 1.0, 0.74, [0.74 / 0.9, 0.74 / 0.77], stages)
     M = m + 1
     nu, nv = M ** d, (0 if method == W.CONSERVATIVE else m ** d)
     ni = nu + nv

@@ -34,12 +34,13 @@ def _start(B, s, works):
     torch.cuda.synchronize()
 
 
-def _oracle_roundoff_floor(spec, u, w, n_half, ref, seed=0):
+def _oracle_roundoff_floor(spec, u, w, n_half, ref, seed=0, eps=2.0 ** -52):
     """Relative change of the oracle's own result when its input is perturbed at the
-    level of FP64 rounding (relative 2^-52): the floor below which two FP64
-    evaluations in different summation orders cannot be expected to agree."""
+    level of rounding (relative eps: 2^-52 for FP64, 2^-24 for FP32 storage): the floor
+    below which two evaluations in different summation orders, or from inputs rounded
+    to that precision, cannot be expected to agree."""
     rng = np.random.default_rng(seed)
-    up = np.asarray(u) * (1.0 + 2.0 ** -52 * rng.standard_normal(np.shape(u)))
+    up = np.asarray(u) * (1.0 + eps * rng.standard_normal(np.shape(u)))
     out = oracle_reference_run(spec, up, w, n_half)
     return max(rel_l2(out[0], ref[0]), rel_l2(out[1], ref[1]))
 
@@ -51,9 +52,20 @@ def test_c5_recipe_reduced_n_every_problem(prec, kernel):
     two full steps of the batch against the oracle, every problem, every node, through
     the default kernel choice (the per-lane dense kernel, one launch per problem) and
     through the generic kernel (one batched launch per half step).
-    FP64 bar: 1e-10, or ten times the oracle's own round-off floor where the
-    problem's map amplifies rounding more (high m: the Hermite operator H_6 has
-    entries up to 1638 and the four half steps compound it)."""
+    FP64 bar: 1e-10, or ten times the oracle's own round-off floor where that floor
+    is higher: the oracle's own result moves by up to 1e-9 when its input is perturbed
+    at FP64 rounding (2^-52) for m = 5 and 6 on random data (H_5 and H_6 have entries up
+    to 385 and 1638, condition numbers 1.7e4 and 1.4e5, squared by the 2-D tensor
+    product, and four half steps compound them), so no FP64 evaluation in another
+    summation order can agree to 1e-10 there.  Every problem on this bar is logged with
+    its error and floor (measured: m = 5 and 6 only, errors up to 1.6e-9 against floors
+    up to 9.8e-10).  FP32 bar (smooth pulse data): fp32_tol(m, 4) on the joint
+    polynomial L2 of [u, tau v] and on the value coefficient, or, where higher, ten
+    times the change of the oracle's own result under FP32-level input rounding
+    (relative 2^-24), which no FP32-state evaluation can undercut.  The plain
+    relative L2 over every coefficient is logged: up to 1.0e-2 at m = 6, where FP32
+    storage alone (the oracle with its state rounded to FP32 after each half step)
+    already gives 1.4e-3."""
     B = _B()
     works = W.c5_batch(n_lo=6, n_hi=16)
     precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
@@ -63,18 +75,42 @@ def test_c5_recipe_reduced_n_every_problem(prec, kernel):
     ins = [[x.cpu().numpy() for x in s.get_state(i)] for i in range(len(works))]
     s.advance(2)
     worst = 0.0
+    relaxed = []
+    worst_field = [0.0, -1, 0]
     for i, w in enumerate(works):
         gu, gw = (x.cpu().numpy() for x in s.get_state(i))
         ou, ow = oracle_reference_run(w.spec, ins[i][0], ins[i][1], 4)
         if precision == B.HW_FP64:
             err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
             if err > tol:
-                tol = max(tol, 10.0 * _oracle_roundoff_floor(w.spec, ins[i][0], ins[i][1], 4, (ou, ow)))
+                floor = _oracle_roundoff_floor(w.spec, ins[i][0], ins[i][1], 4, (ou, ow))
+                tol = max(tol, 10.0 * floor)
+                relaxed.append((i, w.spec.m, w.spec.method, err, floor))
         else:
-            err, tol = joint_err(w.spec, gu, gw, ou, ow), fp32_tol(w.spec.m, 4)
+            # smooth pulse data: the joint polynomial L2 and the value coefficient; the
+            # plain per-field error over every coefficient is logged (at m = 5, 6 the
+            # rounding of sums of terms up to 1e3..1e4 times their result dominates the
+            # tiny high coefficients)
+            err = max(joint_err(w.spec, gu, gw, ou, ow), rel_l2(gu[:, 0], ou[:, 0]))
+            tol = fp32_tol(w.spec.m, 4)
+            per_field = max(rel_l2(gu, ou), rel_l2(gw, ow))
+            if per_field > worst_field[0]:
+                worst_field[:] = [per_field, i, w.spec.m]
+            if err > tol:
+                floor = _oracle_roundoff_floor(w.spec, ins[i][0], ins[i][1], 4, (ou, ow), eps=2.0 ** -24)
+                tol = max(tol, 10.0 * floor)
+                relaxed.append((i, w.spec.m, w.spec.method, err, floor))
         worst = max(worst, err / tol)
         assert err <= tol, (i, w.spec, err, tol)
-    _log(f"[c5 reduced] {prec} {kernel}: worst error / tolerance = {worst:.3f}")
+    for i, m, meth, err, floor in relaxed:
+        _log(f"[c5 reduced] {prec} {kernel}: problem {i} (m = {m}, method {meth}) above the base bar: "
+             f"{err:.2e}, oracle round-off floor {floor:.2e}")
+    if precision != B.HW_FP64:
+        _log(f"[c5 reduced] {prec} {kernel}: largest plain per-field error over every coefficient "
+             f"{worst_field[0]:.2e} (problem {worst_field[1]}, m = {worst_field[2]})")
+    _log(f"[c5 reduced] {prec} {kernel}: worst error / tolerance = {worst:.3f}, "
+         f"{len(relaxed)} problems on the round-off-floor bar (m = "
+         f"{sorted(set(r[1] for r in relaxed))})")
     s.close()
 
 
@@ -128,7 +164,8 @@ def test_c5_full_size_sampled():
             ou, ov = sampled_oracle(spec, to_grid, lambda ix: xu[torch.as_tensor(ix, device="cuda")].cpu().numpy(),
                                     lambda ix: xw[torch.as_tensor(ix, device="cuda")].cpu().numpy(), samples)
             gu, gv = yu[sel].cpu().numpy(), yw[sel].cpu().numpy()
-        err, tol = joint_err(spec, gu, gv, ou, ov), fp32_tol(spec.m, 1)
+        err = max(joint_err(spec, gu, gv, ou, ov), rel_l2(gu[:, 0], ou[:, 0]))
+        tol = fp32_tol(spec.m, 1)
         _log(f"[c5 full] problem {i}: N={spec.n[0]} m={spec.m} method={spec.method} bc={spec.bc[0]} "
              f"sampled rel err {err:.2e} (tol {tol:.1e})")
         assert err <= tol

@@ -78,36 +78,90 @@ def test_pulses_3d_rate():
     assert abs(rate - 5) < 0.3
 
 
-def test_pulses_3d_fp32_form_within_bar():
+def _rel_chunked(a, b):
+    """Relative L2 norm of a - b over every entry, relative to b (chunked to bound the
+    temporaries)."""
+    num = den = 0.0
+    step = 1 << 22
+    for k in range(0, a.shape[0], step):
+        num += float(((a[k:k + step] - b[k:k + step]) ** 2).sum())
+        den += float((b[k:k + step] ** 2).sum())
+    return math.sqrt(num / den)
+
+
+def test_pulses_3d_fp32_form_per_field():
     """The 3-D benchmark run itself (256^3, m = 3, c dt / h = 0.9, 200 steps) in the FP32
-    form: the relative L2 error of the value coefficient at the primal nodes, against the
-    exact radial solution and against the FP64 form, stays within the FP32 bar of this
-    workload, 1e-5 (the FP64 form's own error is 5e-9, so both measure the FP32
-    rounding).  The order in which the composed map accumulates its inputs decides this:
-    ascending input order gave 1.4e-5 here."""
+    form against the FP64 form, field by field, plain relative L2 over every coefficient
+    of every node, and the value coefficient against the exact radial solution.
+
+    Bars (FP32 state and FP32 arithmetic, 400 half steps):
+    * value coefficient u_0: 1e-5 against the FP64 form and against the exact solution
+      (the FP64 form's own error is 5e-9, so both measure the FP32 rounding; measured
+      3.6e-7);
+    * all 64 u coefficients: 2e-4 (measured 8.3e-5); all 27 v coefficients: 1e-3
+      (measured 4.0e-4).  These are rounding noise in the high mixed coefficients, whose
+      true values are 1e-6 .. 1e-10 of u_0 on this smooth data: storing the state in FP32
+      alone, with every half step in FP64, already leaves 7.9e-6 (u) and 1.6e-4 (v) after
+      200 steps (test_pulses_3d_fp32_storage_floor), so no FP32-state form reaches 1e-5
+      on every v coefficient of this workload."""
     B = _B()
     w = W.c4_3d(n=256, device="cuda")
-    vals = {}
+    out = {}
     for prec in (B.HW_FP64, B.HW_FP32):
         s = B.Solver(w.spec, precision=prec)
         s.set_state(w.u0, w.v0)
         s.advance(200)
-        u, _ = s.get_state()
+        out[prec] = s.get_state()
         s.close()
-        vals[prec] = u[:, 0].clone()
-        del u
+    u64, v64 = out[B.HW_FP64]
+    u32, v32 = out[B.HW_FP32]
     pts = torch.as_tensor(w.spec.points(W.PRIMAL), device="cuda")
-    ex = torch.empty_like(vals[B.HW_FP64])
+    ex = torch.empty_like(u64[:, 0])
     chunk = 1 << 21
     for a in range(0, pts.shape[0], chunk):
         ex[a:a + chunk] = w.exact(200 * w.spec.dt, points=pts[a:a + chunk], xp=torch)
+    del pts
     nex = float(torch.linalg.norm(ex))
-    e64 = float(torch.linalg.norm(vals[B.HW_FP64] - ex)) / nex
-    e32 = float(torch.linalg.norm(vals[B.HW_FP32] - ex)) / nex
-    d = float(torch.linalg.norm(vals[B.HW_FP32] - vals[B.HW_FP64]) / torch.linalg.norm(vals[B.HW_FP64]))
-    _log(f"[c4 fp32] error vs exact: fp64 {e64:.3e}, fp32 {e32:.3e}; fp32 vs fp64 {d:.3e}")
+    e64 = float(torch.linalg.norm(u64[:, 0] - ex)) / nex
+    e32 = float(torch.linalg.norm(u32[:, 0] - ex)) / nex
+    d0 = _rel_chunked(u32[:, :1], u64[:, :1])
+    du = _rel_chunked(u32, u64)
+    dv = _rel_chunked(v32, v64)
+    _log(f"[c4 fp32] value coefficient vs exact: fp64 {e64:.3e}, fp32 {e32:.3e}; fp32 vs fp64: "
+         f"u_0 {d0:.3e}, all u coefficients {du:.3e}, all v coefficients {dv:.3e}")
     assert e64 < 1e-7
-    assert e32 <= 1e-5 and d <= 1e-5
+    assert e32 <= 1e-5 and d0 <= 1e-5
+    assert du <= 2e-4 and dv <= 1e-3
+
+
+def test_pulses_3d_fp32_storage_floor():
+    """What storing the state in FP32 costs by itself on the 3-D benchmark: the FP64 form
+    with its state rounded to FP32 after every full step (all arithmetic in FP64), 200
+    steps, against the plain FP64 form.  The v field already misses 1e-5 on every
+    coefficient by an order of magnitude (measured 1.6e-4; u 7.9e-6): the rounding of the
+    large low-order u inputs enters v through the second-derivative rows of the Hermite
+    interpolant.  This bounds from below what any FP32-state form can reach there."""
+    B = _B()
+    w = W.c4_3d(n=256, device="cuda")
+    ref = B.Solver(w.spec, precision=B.HW_FP64)
+    ref.set_state(w.u0, w.v0)
+    rnd = B.Solver(w.spec, precision=B.HW_FP64)
+    rnd.set_state(w.u0.to(torch.float32).to(torch.float64), w.v0)
+    del w
+    ref.advance(200)
+    for _ in range(200):
+        rnd.advance(1)
+        u, v = rnd.get_state()
+        rnd.set_state(u.to(torch.float32).to(torch.float64), v.to(torch.float32).to(torch.float64))
+        del u, v
+    u64, v64 = ref.get_state()
+    ur, vr = rnd.get_state()
+    ref.close()
+    rnd.close()
+    du, dv = _rel_chunked(ur, u64), _rel_chunked(vr, v64)
+    _log(f"[c4 fp32 storage only] all u coefficients {du:.3e}, all v coefficients {dv:.3e}")
+    assert dv > 1e-5
+    assert du < 1e-4 and dv < 1e-3
 
 
 def _oracle_drift(spec, up, ud, steps, every):
@@ -170,18 +224,92 @@ def test_conservation_long_run_1d(m, data):
 
 
 def test_conservative_full_size_accuracy():
-    """2048^2, m = 4, Dirichlet, c dt = h (the conservative 2-D workload): 200 steps from
-    the exact time levels stay on the exact standing wave (rate 2m + 2 at lambda = 1,
-    Sec. 5.3, so only rounding is left at this resolution)."""
+    """2048^2, m = 4, Dirichlet, c dt = h (the conservative 2-D workload), the full 2000
+    steps from the exact time levels: both forms stay on the exact standing wave (rate
+    2m + 2 at lambda = 1, Sec. 5.3, so only rounding is left at this resolution): nodal
+    L2 error of the value coefficient 1e-11 (FP64, measured 3.3e-14) and 1e-4 (FP32,
+    measured 9.6e-6).  The FP32 form against the FP64 form: the value coefficient within
+    1e-4; over every coefficient of both grids the difference is the rounding noise of
+    the non-dissipative scheme, which accumulates step by step in the top coefficients
+    (measured 7.9e-2 after 2000 steps; asserted at 0.2 as a regression bound)."""
     B = _B()
     w = W.c3_2d()
+    out = {}
     for prec, name, tol in ((B.HW_FP64, "fp64", 1e-11), (B.HW_FP32, "fp32", 1e-4)):
         s = B.Solver(w.spec, precision=prec)
         s.set_state(w.u0, w.u_half)
-        s.advance(200)
+        s.advance(2000)
         t = s.time()
-        u, _ = s.get_state()
+        out[prec] = s.get_state()
         s.close()
-        err = W.nodal_l2(w.spec, u[:, 0].cpu().numpy(), w.exact(t))
+        err = W.nodal_l2(w.spec, out[prec][0][:, 0].cpu().numpy(), w.exact(t))
         _log(f"[c3 2048^2 m=4] {name}: t {t:.5f} nodal L2 error {err:.3e}")
         assert err <= tol
+    (p32, d32), (p64, d64) = out[B.HW_FP32], out[B.HW_FP64]
+    v0 = _rel_chunked(p32[:, :1], p64[:, :1])
+    dp, dd = _rel_chunked(p32, p64), _rel_chunked(d32, d64)
+    _log(f"[c3 2048^2 m=4] fp32 vs fp64 after 2000 steps: value coefficient {v0:.3e}; every coefficient: "
+         f"primal {dp:.3e}, dual {dd:.3e}")
+    assert v0 <= 1e-4
+    assert dp <= 0.2 and dd <= 0.2
+
+
+def _oracle_energy_drift_2d(spec, up, ud, steps, every):
+    """Largest relative energy change of the FP64 oracle over `steps` full steps of the
+    conservative method from the levels (up at t, ud at t + dt/2), sampled every
+    `every` steps after the first full step (as the library run below)."""
+    import oracle
+    p = oracle.make_problem(spec.d, spec.m, spec.n, spec.xl, spec.xr, spec.c, spec.dt, spec.bc,
+                            spec.method)
+    up = oracle.cons_half(p, W.PRIMAL, ud, up)
+    nd = oracle.cons_half(p, W.DUAL, up, ud)
+    e0 = oracle.cons_energy(p, W.PRIMAL, up, nd, ud)
+    old, ud = ud, nd
+    worst = 0.0
+    for k in range(1, steps + 1):
+        up = oracle.cons_half(p, W.PRIMAL, ud, up)
+        nd = oracle.cons_half(p, W.DUAL, up, ud)
+        old, ud = ud, nd
+        if k % every == 0:
+            worst = max(worst, abs(oracle.cons_energy(p, W.PRIMAL, up, ud, old) - e0) / abs(e0))
+    return worst
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_energy_drift_conservative_2d_both_forms(m):
+    """The conservative 2-D workload's method (Dirichlet, c dt = h, the workload's seeded
+    standing wave) at 32^2 cells, 2000 steps, energy sampled every 100 steps, for m = 2
+    and the workload's m = 4.  In exact arithmetic the energy is constant (Sec. 4.2); in
+    floating point the rounding of each step random-walks in this non-dissipative scheme
+    while the |.|_{m+1} energy weighs the top interpolant coefficients by h^-(2m+1) per
+    dimension, so the energy drifts linearly with the step count, more with m (the
+    paper's Sec. 5.2 observation in 1-D).  The FP64 oracle drifts by 1e-12 (m = 2) and
+    3.4e-3 (m = 4) on these runs.  Bars: FP64 library within ten times the oracle's drift
+    (and 1e-10 at m = 2); the FP32 state with FP64 energy accumulation at m = 2 within
+    1e-4.  At m = 4 the FP32 state's energy is its rounding noise from the first step
+    (E0 7.0e31 against 4.6e22 in FP64): reported, not bounded."""
+    B = _B()
+    w = W.c3_2d(n=32, m=m)
+    spec, up, ud = w.spec, w.u0, w.u_half
+    steps, every = 2000, 100
+    ref = _oracle_energy_drift_2d(spec, up, ud, steps, every)
+    drift, e0s = {}, {}
+    for prec, name in ((B.HW_FP64, "fp64"), (B.HW_FP32, "fp32")):
+        s = B.Solver(spec, precision=prec)
+        s.set_state(up, ud)
+        s.half_steps(2)
+        e0 = s.energy()
+        B.hw_prepare_advance(s.h, every)
+        worst = 0.0
+        for _ in range(steps // every):
+            s.advance(every)
+            worst = max(worst, abs(s.energy() - e0) / abs(e0))
+        s.close()
+        drift[name], e0s[name] = worst, e0
+        _log(f"[energy drift 32^2 m={m} k=({w.meta['k1']},{w.meta['k2']})] {name}: E0 {e0:.6e}, largest "
+             f"relative change over {steps} steps {worst:.3e} (FP64 oracle {ref:.3e})")
+    assert drift["fp64"] <= 10.0 * ref + 1e-12
+    if m == 2:
+        assert drift["fp64"] <= 1e-10
+        assert drift["fp32"] <= 1e-4
+        assert e0s["fp32"] == pytest.approx(e0s["fp64"], rel=1e-3)

@@ -42,6 +42,18 @@ def joint_err(spec, gu, gv, ou, ov):
     return poly_rel_err(spec, gu, ou, gv, ov)
 
 
+def state_err(spec, gu, gv, ou, ov, prec, n_half):
+    """(error, tolerance) of a GPU state against the oracle's, random data.
+    FP64: plain relative L2 over every coefficient of every node, u and v separately,
+    bar 1e-10.  FP32: the same per-field plain relative L2 and the polynomial L2 of the
+    joint [u, tau v], all against fp32_tol(m, n_half)."""
+    eu = rel_l2(gu, ou)
+    ev = rel_l2(gv, ov) if gv is not None and ov is not None else 0.0
+    if prec in ("fp64", 0):
+        return max(eu, ev), 1e-10
+    return max(eu, ev, joint_err(spec, gu, gv, ou, ov)), fp32_tol(spec.m, n_half)
+
+
 def _B():
     from paper_1802_05246_amd import binding as B
     return B
@@ -120,10 +132,7 @@ def test_small_grids_match_oracle(case, prec):
     s.half_steps(n_half)
     gu, gw = (x.cpu().numpy() for x in s.get_state())
     ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
-    if prec == "fp64":
-        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
-    else:
-        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(m, n_half)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, n_half)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
     s.close()
@@ -166,10 +175,7 @@ def test_dense_kernel_matches_oracle(case, prec):
     s.half_steps(n_half)
     gu, gw = (x.cpu().numpy() for x in s.get_state())
     ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
-    if prec == "fp64":
-        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
-    else:
-        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(m, n_half)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, n_half)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
     s.close()
@@ -208,8 +214,13 @@ def test_graph_advance_equals_plain_launches_bitwise(prec):
 
 
 @pytest.mark.parametrize("d,m,bc", [(2, 2, W.PERIODIC), (2, 3, W.DIRICHLET), (1, 4, W.NEUMANN),
-                                    (3, 1, W.PERIODIC)])
-def test_energy_matches_oracle_and_is_conserved(d, m, bc):
+                                    (3, 1, W.PERIODIC), (2, 4, W.DIRICHLET)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_energy_matches_oracle_and_is_conserved(d, m, bc, prec):
+    """hw_energy (FP64 accumulation, in both state precisions) against the oracle's
+    energy of the GPU's own last three levels (1e-12 relative: the same FP64 quantity
+    summed in another order), and conserved over 8 half steps: to 1e-11 with the FP64
+    state; with the FP32 state each half step's rounding moves it (bound 1e-4)."""
     import oracle
     from helpers import oracle_problem
     B = _B()
@@ -221,26 +232,26 @@ def test_energy_matches_oracle_and_is_conserved(d, m, bc):
     if bc != W.PERIODIC:
         from test_oracle_pins import _wall_compatible
         up = _wall_compatible(spec, up)
-    s = B.Solver(spec, precision=B.HW_FP64)
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    s = B.Solver(spec, precision=precision)
     s.cons_startup(up)
     energies = []
     for k in range(8):
+        if k == 7:
+            gp7, gd7 = (x.cpu().numpy() for x in s.get_state())
         s.half_steps(1)
         energies.append(s.energy())
     gp, gd = (x.cpu().numpy() for x in s.get_state())
-    # oracle energy on the GPU's own last three levels
-    p = oracle_problem(spec)
-    s2 = B.Solver(spec, precision=B.HW_FP64)
-    s2.cons_startup(up)
-    s2.half_steps(7)
-    gp7, gd7 = (x.cpu().numpy() for x in s2.get_state())
     # after 8 half steps the dual grid was updated last: A = primal, B = dual
+    p = oracle_problem(spec)
     e_or = oracle.cons_energy(p, oracle.PRIMAL, gp, gd, gd7)
-    assert energies[-1] == pytest.approx(e_or, rel=1e-12)
     e = np.array(energies)
-    assert np.abs(e - e[0]).max() <= 1e-11 * abs(e[0])
+    drift = np.abs(e - e[0]).max() / abs(e[0])
+    _log(f"[energy] d{d} m{m} bc{bc} {prec}: vs oracle {abs(energies[-1] - e_or) / abs(e_or):.2e}, "
+         f"drift over 8 half steps {drift:.2e}")
+    assert energies[-1] == pytest.approx(e_or, rel=1e-12)
+    assert drift <= (1e-11 if prec == "fp64" else 1e-4)
     s.close()
-    s2.close()
 
 
 def test_cons_startup_matches_oracle():
@@ -282,10 +293,7 @@ def test_batch_matches_oracle_per_problem():
         for i, spec in enumerate(specs):
             gu, gw = (x.cpu().numpy() for x in s.get_state(i))
             ou, ow = oracle_reference_run(spec, ins[i][0], ins[i][1], 6)
-            if prec == B.HW_FP64:
-                err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
-            else:
-                err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(spec.m, 6)
+            err, tol = state_err(spec, gu, gw, ou, ow, "fp64" if prec == B.HW_FP64 else "fp32", 6)
             _log(f"[batch] problem {i} prec {prec} rel-L2 {err:.3e}")
             assert err <= tol
         s.close()
@@ -341,7 +349,11 @@ def _sampled_check(spec, precision, n_samples, seed, w_state=None, steps_half=1)
         err = max(rel_l2(gu, ou), rel_l2(gv, ov) if gv is not None else 0.0)
         tol = 1e-10
     else:
-        err, tol = joint_err(spec, gu, gv, ou, ov), fp32_tol(spec.m, 1)
+        # smooth data: the joint polynomial L2 of [u, tau v] and the value coefficient
+        # (the high mixed coefficients and v after the first half step from v = 0 are
+        # tiny, so their plain relative error measures FP32 rounding noise, not parity)
+        err = max(joint_err(spec, gu, gv, ou, ov), rel_l2(gu[:, 0], ou[:, 0]))
+        tol = fp32_tol(spec.m, 1)
     _log(f"    sampled rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
 
@@ -426,10 +438,7 @@ def test_tiled_3d_m3_matches_oracle(n, bc, prec):
     s.half_steps(n_half)
     gu, gw = (x.cpu().numpy() for x in s.get_state())
     ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
-    if prec == "fp64":
-        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
-    else:
-        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(3, n_half)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, n_half)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
     s.close()
@@ -463,10 +472,7 @@ def test_composed_3d_m3_matches_oracle(n, bc, meth, stages, prec):
     s.half_steps(n_half)
     gu, gw = (x.cpu().numpy() for x in s.get_state())
     ou, ow = oracle_reference_run(spec, u_in, w_in, n_half)
-    if prec == "fp64":
-        err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
-    else:
-        err, tol = joint_err(spec, gu, gw, ou, ow), fp32_tol(3, n_half)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, n_half)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
     s.close()
@@ -504,8 +510,9 @@ SPLIT_CASES = [(1, 3, [9], [W.NEUMANN], W.DISS_FULL), (2, 3, [7, 6], [W.PERIODIC
 @pytest.mark.parametrize("case", SPLIT_CASES, ids=lambda c: f"d{c[0]}-m{c[1]}-meth{c[4]}")
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_two_kernel_form_equals_fused_bitwise(case, prec):
-    """The two-kernel form (interpolants through memory in the state precision) does
-    the same arithmetic as the fused generic kernel: identical results."""
+    """The two-kernel form (interpolants through memory in the state precision) against
+    the oracle, to the bar of its precision, and against the fused generic kernel, which
+    does the same arithmetic: identical results."""
     B = _B()
     d, m, n, bc, meth = case
     spec = W.make_spec(d, m, n, 0.0, 1.0, 1.3, cfl=0.9, bc=bc, method=meth)
@@ -515,9 +522,16 @@ def test_two_kernel_form_equals_fused_bitwise(case, prec):
     for kernel in (B.HW_KERNEL_GENERIC, B.HW_KERNEL_SPLIT):
         s = B.Solver(spec, precision=precision, kernel=kernel)
         s.set_state(u, w)
+        if kernel == B.HW_KERNEL_SPLIT:
+            u_in, w_in = (x.cpu().numpy() for x in s.get_state())
         s.advance(3)
         out.append(s.get_state())
         s.close()
+    gu, gw = (x.cpu().numpy() for x in out[1])
+    ou, ow = oracle_reference_run(spec, u_in, w_in, 6)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, 6)
+    _log(f"[split] {_case_id((d, m, n, bc, meth, 0))} {prec}: against the oracle {err:.3e} (tol {tol:.2e})")
+    assert err <= tol
     assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
 
 
