@@ -184,6 +184,19 @@ int hw_state_grid(const hw_solver* s);
  * deterministic order.  Synchronises `stream`.  HW_ESTATE before the first step. */
 hw_status hw_energy(hw_solver* s, double* e_out, void* stream);
 
+/* The same energy without any allocation, for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * writes E to e_out_device (a caller-owned DEVICE double) asynchronously on `stream`;
+ * no host synchronisation, no host-side buffer.  The per-workgroup partial sums of both
+ * passes go to a fixed device array of the library, 2 x 2048 doubles (32 KiB) on each GPU
+ * it runs on, held until the process ends: calls that overlap on one GPU (concurrent
+ * streams or threads) race on it and must be serialised by the caller.  Any grid size is
+ * served (at most 2048 workgroups per pass, grid-stride over cells); HW_EINVAL if a pass
+ * would need more partial sums than the array holds.  The two passes' partials are
+ * summed on the GPU in a fixed order, so the result agrees with hw_energy to rounding
+ * (a different summation order), not bit for bit.  Other errors as hw_energy. */
+hw_status hw_energy_noalloc(hw_solver* s, double* e_out_device, void* stream);
+
 /* Simulated time of the primal level: t0 + (half steps applied)/2 * dt for the
  * dissipative method; the primal level's time for the conservative method
  * (Sec. 3.1.2: a full step advances both grids by dt; Sec. 4.1: the conservative

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 # every entry point declared in include/hermite_wave.h
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
                 "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_get_state", "hw_state_grid", "hw_energy",
+                "hw_energy_noalloc",
                 "hw_time", "hw_last_error", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
                 "hw_batch_get_state"]
@@ -75,6 +76,7 @@ def lib():
             "hw_get_state": ([vp, dp, dp, vp], ctypes.c_int),
             "hw_state_grid": ([vp], ctypes.c_int),
             "hw_energy": ([vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+            "hw_energy_noalloc": ([vp, dp, vp], ctypes.c_int),
             "hw_time": ([vp], ctypes.c_double),
             "hw_last_error": ([], ctypes.c_char_p),
             "hw_batch_create": ([pp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
@@ -213,6 +215,12 @@ def hw_energy(h, stream=None) -> float:
     e = ctypes.c_double()
     _check(lib().hw_energy(h, ctypes.byref(e), _stream(stream)))
     return e.value
+
+
+def hw_energy_noalloc(h, e_out_device, stream=None):
+    """e_out_device: a float64 CUDA tensor with at least one element; the energy is
+    written to its first element asynchronously on the stream."""
+    _check(lib().hw_energy_noalloc(h, _ptr(e_out_device), _stream(stream)))
 
 
 def hw_time(h) -> float:

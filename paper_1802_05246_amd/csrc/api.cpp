@@ -446,7 +446,7 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         hipMalloc((void**)&s->prefix, s->h_prefix.size() * sizeof(int64_t)) != hipSuccess ||
         hipMalloc((void**)&s->startup_desc, sizeof(ProblemDesc)) != hipSuccess ||
         hipMalloc((void**)&s->startup_prefix, 2 * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc((void**)&s->partials, 4096 * sizeof(double)) != hipSuccess)
+        hipMalloc((void**)&s->partials, HW_ENERGY_MAX_GROUPS * sizeof(double)) != hipSuccess)
         return cleanup(fail(HW_ENOMEM, "descriptor allocation failed"));
     if (hipMemcpy(s->descs, s->h_descs.data(), s->h_descs.size() * sizeof(ProblemDesc),
                   hipMemcpyHostToDevice) != hipSuccess ||
@@ -569,6 +569,52 @@ hw_status set_state_impl(hw_solver* s, int i, const double* u, const double* w, 
         HIP_TRY(hw_launch_convert(w, true, P.u[HW_DUAL][0], s->fp64, P.nodes[1] * P.Mu, st));
     else
         HIP_TRY(hw_launch_convert(w, true, P.v[HW_PRIMAL], s->fp64, P.nodes[0] * P.Mv, st));
+    return HW_OK;
+}
+
+// The two passes of the energy (Sec. 4.2 eq. (Vconst)): pass 0 = |p_A|^2 on the grid
+// not updated last, pass 1 = <p_B^new, p_B^old> on the grid updated last; one partial
+// sum per workgroup, at most HW_ENERGY_MAX_GROUPS workgroups (grid-stride over cells).
+hw_status energy_passes(hw_solver* s, const void* out, EnergyDesc E[2], int gsz[2])
+{
+    if (check_solver(s)) return HW_EINVAL;
+    if (!out) return fail(HW_EINVAL, "null output");
+    if (s->probs.size() != 1) return fail(HW_EINVAL, "energy is per single-problem solver");
+    const Prob& P = s->probs[0];
+    if (P.p.method != HW_CONSERVATIVE) return fail(HW_EINVAL, "energy is defined for the conservative method");
+    if (!s->state_set || s->half_steps < 1) return fail(HW_ESTATE, "energy needs at least one half step");
+    const int64_t h = s->half_steps;
+    // last update: primal if h is odd, dual if h is even
+    const int B = (h & 1) ? HW_PRIMAL : HW_DUAL;
+    const int A = 1 - B;
+    const int sp = (int)(((h + 1) / 2) & 1), sd = (int)((h / 2) & 1);
+    const int slotA = (A == HW_PRIMAL) ? sp : sd;
+    const int slotB = (B == HW_PRIMAL) ? sp : sd;
+    const void* fa = P.u[A][slotA];
+    const void* fb_new = P.u[B][slotB];
+    const void* fb_old = P.u[B][1 - slotB];
+    const int m = P.p.m;
+    double hfac = 1.0;
+    for (int i = 0; i < P.p.d; ++i) hfac *= std::pow(P.h[i], 1.0 - 2.0 * (m + 1));
+    for (int t = 0; t < 2; ++t) {
+        std::memset(&E[t], 0, sizeof E[t]);
+        E[t].d = P.p.d;
+        E[t].m = m;
+        const int data_grid = t == 0 ? A : B;
+        E[t].center_grid = 1 - data_grid;
+        for (int i = 0; i < 3; ++i) {
+            E[t].bc[i] = (i < P.p.d) ? P.p.bc[i] : HW_PERIODIC;
+            E[t].ext_from[i] = P.ext[data_grid][i];
+            E[t].ext_to[i] = P.ext[E[t].center_grid][i];
+        }
+        E[t].n_cells = (int)P.nodes[E[t].center_grid];
+        E[t].f = t == 0 ? fa : fb_new;
+        E[t].g = t == 0 ? fa : fb_old;
+        E[t].hfac = hfac;
+        E[t].hi_off = s->hi_off[m];
+        E[t].gram_off = s->gram_off[m];
+        gsz[t] = E[t].n_cells < HW_ENERGY_MAX_GROUPS ? E[t].n_cells : HW_ENERGY_MAX_GROUPS;
+    }
     return HW_OK;
 }
 
@@ -822,53 +868,19 @@ double hw_time(const hw_solver* s)
 
 hw_status hw_energy(hw_solver* s, double* e_out, void* stream)
 {
-    if (check_solver(s)) return HW_EINVAL;
-    if (!e_out) return fail(HW_EINVAL, "null output");
-    if (s->probs.size() != 1) return fail(HW_EINVAL, "energy is per single-problem solver");
-    const Prob& P = s->probs[0];
-    if (P.p.method != HW_CONSERVATIVE) return fail(HW_EINVAL, "energy is defined for the conservative method");
-    if (!s->state_set || s->half_steps < 1) return fail(HW_ESTATE, "energy needs at least one half step");
+    EnergyDesc E[2];
+    int gsz[2];
+    hw_status r = energy_passes(s, e_out, E, gsz);
+    if (r != HW_OK) return r;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t h = s->half_steps;
-    // last update: primal if h is odd, dual if h is even
-    const int B = (h & 1) ? HW_PRIMAL : HW_DUAL;
-    const int A = 1 - B;
-    const int sp = (int)(((h + 1) / 2) & 1), sd = (int)((h / 2) & 1);
-    const int slotA = (A == HW_PRIMAL) ? sp : sd;
-    const int slotB = (B == HW_PRIMAL) ? sp : sd;
-    const void* fa = P.u[A][slotA];
-    const void* fb_new = P.u[B][slotB];
-    const void* fb_old = P.u[B][1 - slotB];
-    const int m = P.p.m;
-    double hfac = 1.0;
-    for (int i = 0; i < P.p.d; ++i) hfac *= std::pow(P.h[i], 1.0 - 2.0 * (m + 1));
-    const int grid = 2048;
     double total[2];
     for (int t = 0; t < 2; ++t) {
-        EnergyDesc E;
-        std::memset(&E, 0, sizeof E);
-        E.d = P.p.d;
-        E.m = m;
-        const int data_grid = t == 0 ? A : B;
-        E.center_grid = 1 - data_grid;
-        for (int i = 0; i < 3; ++i) {
-            E.bc[i] = (i < P.p.d) ? P.p.bc[i] : HW_PERIODIC;
-            E.ext_from[i] = P.ext[data_grid][i];
-            E.ext_to[i] = P.ext[E.center_grid][i];
-        }
-        E.n_cells = (int)P.nodes[E.center_grid];
-        E.f = t == 0 ? fa : fb_new;
-        E.g = t == 0 ? fa : fb_old;
-        E.hfac = hfac;
-        E.hi_off = s->hi_off[m];
-        E.gram_off = s->gram_off[m];
-        const int gsz = E.n_cells < grid ? E.n_cells : grid;
-        HIP_TRY(hw_launch_energy(P.p.d, s->fp64, E, s->dops, s->partials, gsz, st));
-        std::vector<double> part(gsz);
-        HIP_TRY(hipMemcpyAsync(part.data(), s->partials, gsz * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hw_launch_energy(s->d, s->fp64, E[t], s->dops, s->partials, gsz[t], st));
+        std::vector<double> part(gsz[t]);
+        HIP_TRY(hipMemcpyAsync(part.data(), s->partials, gsz[t] * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         double sum = 0.0, comp = 0.0;
-        for (int k = 0; k < gsz; ++k) {
+        for (int k = 0; k < gsz[t]; ++k) {
             const double y = part[k] - comp;
             const double tt = sum + y;
             comp = (tt - sum) - y;
@@ -877,6 +889,21 @@ hw_status hw_energy(hw_solver* s, double* e_out, void* stream)
         total[t] = sum;
     }
     *e_out = 2.0 * (total[0] - total[1]);
+    return HW_OK;
+}
+
+hw_status hw_energy_noalloc(hw_solver* s, double* e_out_device, void* stream)
+{
+    EnergyDesc E[2];
+    int gsz[2];
+    hw_status r = energy_passes(s, e_out_device, E, gsz);
+    if (r != HW_OK) return r;
+    for (int t = 0; t < 2; ++t)
+        if (gsz[t] > HW_ENERGY_MAX_GROUPS)
+            return fail(HW_EINVAL, "energy pass %d needs %d partial sums, the static scratch holds %d", t,
+                        gsz[t], HW_ENERGY_MAX_GROUPS);
+    HIP_TRY(hw_launch_energy_noalloc(s->d, s->fp64, E[0], gsz[0], E[1], gsz[1], s->dops, e_out_device,
+                                     (hipStream_t)stream));
     return HW_OK;
 }
 

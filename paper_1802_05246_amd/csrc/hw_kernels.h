@@ -19,6 +19,14 @@ hipError_t hw_launch_energy(int d, bool fp64, const EnergyDesc& E, const double*
                             double* partials, int grid, hipStream_t st);
 hipError_t hw_launch_convert(const void* src, bool src64, void* dst, bool dst64, int64_t n,
                              hipStream_t st);
+// Energy without allocation: both passes' partial sums go to a file-scope device array
+// of 2 x HW_ENERGY_MAX_GROUPS doubles (one per GPU); a final one-workgroup kernel writes
+// E = 2 (pass 0 - pass 1) to e_out (device).  Calls that overlap on one GPU race on the
+// array.  hipErrorInvalidValue for a grid outside 1..HW_ENERGY_MAX_GROUPS.
+constexpr int HW_ENERGY_MAX_GROUPS = 2048;
+constexpr int HW_MAX_DEVICES = 64;
+hipError_t hw_launch_energy_noalloc(int d, bool fp64, const EnergyDesc& E0, int grid0, const EnergyDesc& E1,
+                                    int grid1, const double* dops, double* e_out, hipStream_t st);
 
 // LDS-tiled MFMA kernel for the 3-D dissipative full method with m = 3 (periodic or
 // not).  Returns hipErrorInvalidValue when the problem is outside its scope.

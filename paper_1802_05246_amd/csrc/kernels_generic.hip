@@ -20,6 +20,8 @@
 // (tau^2 L)^j a/(2j)! - u_old with a = I_{m..m} u, the Pascal-matrix formula of
 // Sec. 4.3 with the factor (c dt/(2h))^2i.
 
+#include <mutex>
+
 #include "hw_device.h"
 #include "hw_kernels.h"
 
@@ -558,6 +560,36 @@ k_energy(EnergyDesc E, const double* __restrict__ dops, double* __restrict__ par
     }
 }
 
+// Sum of the per-workgroup energy partials of both passes in one fixed order (lane k
+// adds partials k, k + 64, ...; then lane 0 adds the 64 lane sums in order), written as
+// E = 2 (sum of pass 0 - sum of pass 1) to one device word.
+__global__ void __launch_bounds__(GW)
+k_energy_finish(const double* __restrict__ partials, int n0, int stride1, int n1, double* __restrict__ e_out)
+{
+    __shared__ double red[2][GW];
+    const int lane = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = lane; i < n0; i += GW) s0 += partials[i];
+    for (int i = lane; i < n1; i += GW) s1 += partials[stride1 + i];
+    red[0][lane] = s0;
+    red[1][lane] = s1;
+    __syncthreads();
+    if (lane == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int i = 0; i < GW; ++i) {
+            t0 += red[0][i];
+            t1 += red[1][i];
+        }
+        e_out[0] = 2.0 * (t0 - t1);
+    }
+}
+
+// Partial sums of the allocation-free energy call: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes its name to a kernel:
+// the name is a host-side stand-in; the device address comes from hipGetSymbolAddress
+// (once per device, below).
+static __device__ __align__(256) double scratch[2 * HW_ENERGY_MAX_GROUPS];
+
 template <typename Tin, typename Tout>
 __global__ void k_convert(const Tin* __restrict__ src, Tout* __restrict__ dst, int64_t n)
 {
@@ -658,6 +690,42 @@ hipError_t hw_launch_energy(int d, bool fp64, const EnergyDesc& E, const double*
     if (d == 1) return launch_en<float, 1>(E, dops, partials, grid, st);
     if (d == 2) return launch_en<float, 2>(E, dops, partials, grid, st);
     return launch_en<float, 3>(E, dops, partials, grid, st);
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+static hipError_t scratch_address(double** out)
+{
+    static std::mutex mu;
+    static double* addr[HW_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= HW_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t hw_launch_energy_noalloc(int d, bool fp64, const EnergyDesc& E0, int grid0, const EnergyDesc& E1,
+                                    int grid1, const double* dops, double* e_out, hipStream_t st)
+{
+    if (grid0 < 1 || grid1 < 1 || grid0 > HW_ENERGY_MAX_GROUPS || grid1 > HW_ENERGY_MAX_GROUPS)
+        return hipErrorInvalidValue;
+    double* part = nullptr;
+    hipError_t e = scratch_address(&part);
+    if (e != hipSuccess) return e;
+    e = hw_launch_energy(d, fp64, E0, dops, part, grid0, st);
+    if (e != hipSuccess) return e;
+    e = hw_launch_energy(d, fp64, E1, dops, part + HW_ENERGY_MAX_GROUPS, grid1, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(GW), 0, st, part, grid0, HW_ENERGY_MAX_GROUPS, grid1, e_out);
+    return hipGetLastError();
 }
 
 hipError_t hw_launch_convert(const void* src, bool src64, void* dst, bool dst64, int64_t n,
