@@ -78,6 +78,10 @@ def lib():
         L.hwo_diss_half_forced.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp, dp, ip,
                                            ctypes.c_int64, ctypes.c_int]
         L.hwo_cons_half.argtypes = [pp, ctypes.c_int, dp, dp, dp, ip, ctypes.c_int64, ctypes.c_int]
+        L.hwo_diss_half_ext.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp, dp, dp, dp, ip,
+                                        ctypes.c_int64, ctypes.c_int]
+        L.hwo_cons_half_ext.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int, dp, dp, ip,
+                                        ctypes.c_int64, ctypes.c_int]
         L.hwo_cons_startup.argtypes = [pp, dp, dp, dp, ctypes.c_int]
         L.hwo_cons_energy.argtypes = [pp, ctypes.c_int, dp, dp, dp, ctypes.c_int]
         L.hwo_cons_energy.restype = ctypes.c_double
@@ -118,12 +122,42 @@ def _sel(sel):
     return s, s.size
 
 
-def diss_half(p: Problem, to_grid: int, u, v, sel=None, nthreads=0, forcing=None):
+def wall_faces(p: Problem):
+    """The faces of the wall records, in their order: (dim, side, tangential extents)
+    for every non-periodic dimension (side -1 = low wall, +1 = high wall).  The
+    tangential extents are those of the input (dual) grid of a half step onto the
+    primal grid, with one ghost position added at each end of a non-periodic
+    dimension (index 0 = beyond the low wall, n + 1 = beyond the high wall)."""
+    faces = []
+    for i in range(p.d):
+        if p.bc[i] == PERIODIC:
+            continue
+        ext = [p.n[t] + (0 if p.bc[t] == PERIODIC else 2) for t in range(p.d) if t != i]
+        faces.append((i, -1, ext))
+        faces.append((i, 1, ext))
+    return faces
+
+
+def wall_points(p: Problem) -> int:
+    return int(sum(int(np.prod(e)) if e else 1 for _, _, e in wall_faces(p)))
+
+
+def _walls(p, walls, M):
+    w = np.ascontiguousarray(walls, dtype=np.float64)
+    if w.shape != (wall_points(p), M ** p.d):
+        raise ValueError(f"wall records must have shape {(wall_points(p), M ** p.d)}, got {w.shape}")
+    return w
+
+
+def diss_half(p: Problem, to_grid: int, u, v, sel=None, nthreads=0, forcing=None, walls=None):
     """One dissipative half step onto `to_grid` (Sec. 3.1.2, Sec. 3.3).  With `sel`
     only those output nodes are computed (rows in the order given).  `forcing`, if
     given, has shape (nodes of to_grid, R, (2m)^d): the scaled space-time Taylor
     coefficients h^k/k! d^k d^r/dt^r f of the forcing at every output node and the
-    start of the half step, r < R (Sec. 3.1.2 eq. (recursion_diss_1d_2))."""
+    start of the half step, r < R (Sec. 3.1.2 eq. (recursion_diss_1d_2)).  `walls`, if
+    given, is (wall_u, wall_v): the inhomogeneous / time-dependent wall data of
+    Sec. 3.1.3, records of shape (wall_points, (m+1)^d) and (wall_points, m^d) (layout in
+    hermite_oracle.c), used when to_grid is the primal grid."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     v = np.ascontiguousarray(v, dtype=np.float64)
     s, ns = _sel(sel)
@@ -131,31 +165,44 @@ def diss_half(p: Problem, to_grid: int, u, v, sel=None, nthreads=0, forcing=None
     uo = np.zeros((cnt, (p.m + 1) ** p.d))
     vo = np.zeros((cnt, p.m ** p.d))
     selp = None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    if forcing is None:
-        rc = lib().hwo_diss_half(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(uo), _dp(vo),
-                                 selp, ns, nthreads)
-    else:
+    f, nf = None, 0
+    if forcing is not None:
         f = np.ascontiguousarray(forcing, dtype=np.float64)
         if f.ndim != 3 or f.shape[0] != nodes(p, to_grid) or f.shape[2] != (2 * p.m) ** p.d:
             raise ValueError(f"forcing must have shape (nodes, R, (2m)^d), got {f.shape}")
-        rc = lib().hwo_diss_half_forced(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(f), f.shape[1],
-                                        _dp(uo), _dp(vo), selp, ns, nthreads)
+        nf = f.shape[1]
+    wu = wv = None
+    if walls is not None:
+        wu, wv = _walls(p, walls[0], p.m + 1), _walls(p, walls[1], p.m)
+    rc = lib().hwo_diss_half_ext(ctypes.byref(p), to_grid, _dp(u), _dp(v), _dp(f), nf, _dp(wu), _dp(wv),
+                                 _dp(uo), _dp(vo), selp, ns, nthreads)
     if rc:
         raise ValueError(f"diss_half failed ({rc})")
     return uo, vo
 
 
-def cons_half(p: Problem, to_grid: int, u_from, u_old, sel=None, nthreads=0):
+def cons_half(p: Problem, to_grid: int, u_from, u_old, sel=None, nthreads=0, forcing=None, walls=None):
     """One conservative half step (Sec. 4.1 eq. (convUpdate), Sec. 4.3): new data on
-    `to_grid` from the other grid's data at the middle time and the old data."""
+    `to_grid` from the other grid's data at the middle time and the old data.
+    `forcing`: shape (nodes of to_grid, R, (2m+2)^d), the scaled Taylor coefficients
+    h^k/k! d^k d^q/dt^q f at every output node and the middle time (eq. (wavequ));
+    `walls`: wall records of shape (wall_points, (m+1)^d) (Sec. 3.1.3), used when
+    to_grid is the primal grid."""
     u_from = np.ascontiguousarray(u_from, dtype=np.float64)
     u_old = np.ascontiguousarray(u_old, dtype=np.float64)
     s, ns = _sel(sel)
     cnt = ns if s is not None else nodes(p, to_grid)
     un = np.zeros((cnt, (p.m + 1) ** p.d))
-    rc = lib().hwo_cons_half(ctypes.byref(p), to_grid, _dp(u_from), _dp(u_old), _dp(un),
-                             None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                             ns, nthreads)
+    f, nf = None, 0
+    if forcing is not None:
+        f = np.ascontiguousarray(forcing, dtype=np.float64)
+        if f.ndim != 3 or f.shape[0] != nodes(p, to_grid) or f.shape[2] != (2 * p.m + 2) ** p.d:
+            raise ValueError(f"forcing must have shape (nodes, R, (2m+2)^d), got {f.shape}")
+        nf = f.shape[1]
+    wu = _walls(p, walls, p.m + 1) if walls is not None else None
+    selp = None if s is None else s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    rc = lib().hwo_cons_half_ext(ctypes.byref(p), to_grid, _dp(u_from), _dp(u_old), _dp(f), nf, _dp(wu),
+                                 _dp(un), selp, ns, nthreads)
     if rc:
         raise ValueError(f"cons_half failed ({rc})")
     return un

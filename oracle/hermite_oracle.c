@@ -135,6 +135,9 @@ static double hdim(const hwo_problem *p, int i) { return (p->xr[i] - p->xl[i]) /
 typedef struct {
     int64_t node[1 << MAXD];       /* input node of corner sigma                */
     int ghost[1 << MAXD][MAXD];    /* 1 if corner sigma is a ghost in that dim  */
+    int side[1 << MAXD][MAXD];     /* ghost side: -1 beyond the low wall, +1 beyond */
+                                   /* the high wall, 0 inside                     */
+    int64_t idx[1 << MAXD][MAXD];  /* input node index per dim (mirrored)        */
 } corners_t;
 
 static void find_corners(const hwo_problem *p, int to_grid, const int64_t out_idx[MAXD],
@@ -148,7 +151,7 @@ static void find_corners(const hwo_problem *p, int to_grid, const int64_t out_id
             const int s = (sig >> i) & 1;
             const int64_t ext = grid_extent(p, from_grid, i);
             int64_t j;
-            int gh = 0;
+            int gh = 0, side = 0;
             if (to_grid == HWO_DUAL) {
                 j = out_idx[i] + s; /* primal i (s=0) and i+1 (s=1) */
                 if (p->bc[i] == HWO_PERIODIC) j %= ext;
@@ -159,12 +162,16 @@ static void find_corners(const hwo_problem *p, int to_grid, const int64_t out_id
                 } else if (j < 0) {
                     j = 0; /* ghost at -1/2 mirrors dual node 1/2 */
                     gh = 1;
+                    side = -1;
                 } else if (j >= ext) {
                     j = ext - 1; /* ghost at n+1/2 mirrors dual node n-1/2 */
                     gh = 1;
+                    side = 1;
                 }
             }
             cr->ghost[sig][i] = gh;
+            cr->side[sig][i] = side;
+            cr->idx[sig][i] = j;
             node += j * stride;
             stride *= ext;
         }
@@ -185,6 +192,109 @@ static double ghost_sign(const hwo_problem *p, const corners_t *cr, int sig, con
 }
 
 /* ------------------------------------------------------------------------- */
+/* Inhomogeneous and time-dependent wall data (Sec. 3.1.3).  The ghost           */
+/* polynomial is fixed by requiring the interpolant centred at the wall node to  */
+/* match the interior data on one side and the boundary condition on the wall:   */
+/* its even normal part (Dirichlet: u = g and, through the PDE, its even normal  */
+/* derivatives) or odd normal part (Neumann) is prescribed, the rest comes from  */
+/* the interior.  With W that prescribed part (even / odd in the normal          */
+/* variable), the interpolant is p = R(q) + W where q is the interior polynomial */
+/* and R its homogeneous odd / even reflection; matching p at the interior       */
+/* corner gives the ghost data                                                   */
+/*     ghost = R(interior) + 2 W(ghost position),                                */
+/* which is the homogeneous mirror of Sec. 3.1.3 when W = 0.  At a corner ghost   */
+/* in several dimensions the walls are applied one dimension after another in    */
+/* increasing order, each to the result of the previous one.                     */
+/*                                                                               */
+/* Wall records (one per wall point, Mrec^d values with Mrec = m+1 for u and m   */
+/* for v, coefficient index x fastest): in the normal dimension the index j      */
+/* stands for the normal degree k = 2j (Dirichlet) or 2j+1 (Neumann); each entry */
+/* is the scaled Taylor coefficient h^k/k! d^k_normal h^l/l! d^l_tangential of   */
+/* the solution at the wall point, at the time of the half step's input data.    */
+/* Faces: for every non-periodic dimension i in increasing order, the low wall   */
+/* then the high wall.  Wall points of face i: the input (dual) grid's node       */
+/* positions in every other dimension t, extended by one ghost position at each  */
+/* end when t is non-periodic (index 0 = -1/2 beyond the low wall, n_t+1 = beyond */
+/* the high wall; periodic t: the n_t dual nodes), x fastest.                    */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const double *data; /* all faces' records, or NULL (homogeneous walls) */
+    int Mrec;           /* coefficients per dimension of a record          */
+} walls_t;
+
+static int64_t face_points(const hwo_problem *p, int i)
+{
+    int64_t n = 1;
+    for (int t = 0; t < p->d; ++t) {
+        if (t == i) continue;
+        n *= (p->bc[t] == HWO_PERIODIC) ? p->n[t] : p->n[t] + 2;
+    }
+    return n;
+}
+
+static double refl_sign(int bc, int l)
+{
+    const int odd = l & 1;
+    if (bc == HWO_DIRICHLET) return odd ? 1.0 : -1.0; /* (-1)^(l+1) */
+    return odd ? -1.0 : 1.0;                           /* (-1)^l     */
+}
+
+static double wall_term(const hwo_problem *p, const corners_t *cr, int sig, const int *l,
+                        const walls_t *w)
+{
+    const int d = p->d;
+    const int rec = pw(w->Mrec, d);
+    double total = 0.0;
+    for (int r = 0; r < d; ++r) {
+        if (!cr->side[sig][r]) continue;
+        /* reflections of the dimensions applied after r */
+        double sgn = 1.0;
+        for (int g = r + 1; g < d; ++g)
+            if (cr->side[sig][g]) sgn *= refl_sign(p->bc[g], l[g]);
+        /* face offset: faces of earlier non-periodic dimensions, then this side */
+        int64_t off = 0;
+        for (int i = 0; i < r; ++i)
+            if (p->bc[i] != HWO_PERIODIC) off += 2 * face_points(p, i);
+        if (cr->side[sig][r] > 0) off += face_points(p, r);
+        /* wall point: dims before r already reflected (ghost position if ghost), */
+        /* dims after r still at the mirrored interior node                       */
+        int64_t pt = 0, stride = 1;
+        for (int t = 0; t < d; ++t) {
+            if (t == r) continue;
+            int64_t pos, ext;
+            if (p->bc[t] == HWO_PERIODIC) {
+                ext = p->n[t];
+                pos = cr->idx[sig][t];
+            } else {
+                ext = p->n[t] + 2;
+                if (t < r && cr->side[sig][t] < 0) pos = 0;
+                else if (t < r && cr->side[sig][t] > 0) pos = p->n[t] + 1;
+                else pos = cr->idx[sig][t] + 1;
+            }
+            pt += pos * stride;
+            stride *= ext;
+        }
+        const double *rw = w->data + (off + pt) * (int64_t)rec;
+        /* W at the ghost position, a distance h/2 beyond the wall: Taylor shift of */
+        /* the normal expansion by delta = -1/2 (low) or +1/2 (high)                */
+        const double delta = cr->side[sig][r] < 0 ? -0.5 : 0.5;
+        double sum = 0.0;
+        for (int j = 0; j < w->Mrec; ++j) {
+            const int k = (p->bc[r] == HWO_DIRICHLET) ? 2 * j : 2 * j + 1;
+            if (k < l[r]) continue;
+            int c = 0, cs = 1;
+            for (int t = 0; t < d; ++t) {
+                c += (t == r ? j : l[t]) * cs;
+                cs *= w->Mrec;
+            }
+            sum += binom(k, l[r]) * pow(delta, k - l[r]) * rw[c];
+        }
+        total += sgn * 2.0 * sum;
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Tensor-product interpolant I_{md_1..md_d} (Sec. 2.2, eqs. (Hermn2),        */
 /* (Hermcon2) and their mixed-degree variants).  corner data: coefficient       */
 /* arrays with M_data entries per dimension; only l_i <= md_i is used.          */
@@ -202,8 +312,8 @@ static void load_tables(int m, tables_t *t)
 }
 
 static void tensor_interp(const hwo_problem *p, const tables_t *tb, const corners_t *cr,
-                          const double *data, int M_data, const int md[MAXD], double *a,
-                          double *work)
+                          const double *data, int M_data, const int md[MAXD], const walls_t *w,
+                          double *a, double *work)
 {
     const int d = p->d;
     int ext[MAXD] = {1, 1, 1};
@@ -225,6 +335,11 @@ static void tensor_interp(const hwo_problem *p, const tables_t *tb, const corner
             cstride *= M_data;
         }
         a[idx] = ghost_sign(p, cr, sig, l) * data[cr->node[sig] * (int64_t)pw(M_data, d) + coef];
+        if (w && w->data) {
+            int any = 0;
+            for (int i = 0; i < d; ++i) any |= cr->side[sig][i];
+            if (any) a[idx] += wall_term(p, cr, sig, l, w);
+        }
     }
     /* dimension-by-dimension application of H_{md_i} */
     int stride = 1;
@@ -315,7 +430,8 @@ static void scratch_alloc(scratch_t *s, int d, int m)
 /* (recursion_diss_1d_2) of Sec. 3.1.2 applied in every dimension.                        */
 static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t *cr,
                       const double *u_in, const double *v_in, const double *fcell, int n_orders,
-                      double *u_out, double *v_out, scratch_t *s)
+                      const walls_t *wu, const walls_t *wv, double *u_out, double *v_out,
+                      scratch_t *s)
 {
     const int d = p->d, m = p->m, M = m + 1, Mv = m, P = 2 * m + 2;
     const int T = pw(P, d);
@@ -324,14 +440,14 @@ static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t 
 
     /* U_0 = I_{m..m} u (degree 2m+1 per dimension) */
     for (int i = 0; i < d; ++i) md[i] = m;
-    tensor_interp(p, tb, cr, u_in, M, md, s->tmp, s->work);
+    tensor_interp(p, tb, cr, u_in, M, md, wu, s->tmp, s->work);
     memcpy(s->p0, s->tmp, sizeof(double) * T);
     /* V_0 = I_{m-1..m-1} v (degree 2m-1 per dimension), zero padded */
     for (int i = 0; i < d; ++i) {
         md[i] = m - 1;
         ext[i] = 2 * m;
     }
-    tensor_interp(p, tb, cr, v_in, Mv, md, s->tmp, s->work);
+    tensor_interp(p, tb, cr, v_in, Mv, md, wv, s->tmp, s->work);
     embed(d, ext, s->tmp, P, s->q0);
 
     memcpy(s->U, s->p0, sizeof(double) * T);
@@ -363,7 +479,7 @@ static void diss_cell(const hwo_problem *p, const tables_t *tb, const corners_t 
                     md[j] = (j == i) ? m : m - 1;
                     ext[j] = 2 * md[j] + 2;
                 }
-                tensor_interp(p, tb, cr, u_in, M, md, s->tmp, s->work);
+                tensor_interp(p, tb, cr, u_in, M, md, wu, s->tmp, s->work);
                 embed(d, ext, s->tmp, P, s->ci);
                 const double h = hdim(p, i);
                 int stride = 1;
@@ -468,14 +584,24 @@ static int nthreads_or_default(int nthreads)
 int hwo_diss_half(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
                   double *u_out, double *v_out, const int64_t *sel, int64_t nsel, int nthreads)
 {
-    return hwo_diss_half_forced(p, to_grid, u_in, v_in, NULL, 0, u_out, v_out, sel, nsel, nthreads);
+    return hwo_diss_half_ext(p, to_grid, u_in, v_in, NULL, 0, NULL, NULL, u_out, v_out, sel, nsel,
+                             nthreads);
 }
 
 int hwo_diss_half_forced(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
                          const double *f_coef, int n_orders, double *u_out, double *v_out,
                          const int64_t *sel, int64_t nsel, int nthreads)
 {
+    return hwo_diss_half_ext(p, to_grid, u_in, v_in, f_coef, n_orders, NULL, NULL, u_out, v_out, sel,
+                             nsel, nthreads);
+}
+
+int hwo_diss_half_ext(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
+                      const double *f_coef, int n_orders, const double *wall_u, const double *wall_v,
+                      double *u_out, double *v_out, const int64_t *sel, int64_t nsel, int nthreads)
+{
     if (n_orders < 0 || (n_orders > 0 && !f_coef)) return -1;
+    if ((wall_u == NULL) != (wall_v == NULL)) return -1;
     if (check_problem(p) || p->m < 1 || (p->method != HWO_DISS_FULL && p->method != HWO_DISS_SIMPLE))
         return -1;
     const int d = p->d, M = p->m + 1, Mv = p->m;
@@ -497,7 +623,9 @@ int hwo_diss_half_forced(const hwo_problem *p, int to_grid, const double *u_in, 
             find_corners(p, to_grid, idx, &cr);
             const double *fcell =
                 n_orders > 0 ? f_coef + node * (int64_t)n_orders * pw(2 * p->m, d) : NULL;
-            diss_cell(p, tb, &cr, u_in, v_in, fcell, n_orders, u_out + q * Mu_tot,
+            const walls_t wu = {to_grid == HWO_PRIMAL ? wall_u : NULL, M};
+            const walls_t wv = {to_grid == HWO_PRIMAL ? wall_v : NULL, Mv};
+            diss_cell(p, tb, &cr, u_in, v_in, fcell, n_orders, &wu, &wv, u_out + q * Mu_tot,
                       v_out + q * Mv_tot, &s);
         }
         free(s.p0);
@@ -534,10 +662,45 @@ static void cons_even_odd_sum(const hwo_problem *p, const double *a, double tau,
     }
 }
 
+/* With a forcing term (u_tt = c^2 Lap u + f, eq. (wavequ)) the even time derivatives */
+/* in eq. (update) obey d^2r u/dt^2r = c^2 Lap d^(2r-2) u/dt^(2r-2) + d^(2r-2) f/dt^(2r-2), */
+/* so D_0 = a, D_r = c^2 Lap D_(r-1) + phi_(2r-2) and the sum is                       */
+/* sum_r (dt/2)^(2r)/(2r)! D_r.  phi_q: the q-th time derivative of f at the cell      */
+/* centre and the middle time, (2m+2)^d scaled Taylor coefficients.                    */
+static void cons_forced_sum(const hwo_problem *p, const double *a, double tau, const double *fcell,
+                            int n_orders, double *acc, double *cur, double *tmp)
+{
+    const int d = p->d, P = 2 * p->m + 2, T = pw(P, d);
+    const double c2 = p->c * p->c;
+    memcpy(cur, a, sizeof(double) * T);
+    memcpy(acc, a, sizeof(double) * T);
+    double coef = 1.0;
+    for (int r = 1; r <= d * (P / 2) + 1 + n_orders; ++r) {
+        scaled_laplacian(p, P, cur, tmp);
+        int nonzero = 0;
+        for (int k = 0; k < T; ++k) cur[k] = c2 * tmp[k];
+        const int q = 2 * r - 2;
+        if (q < n_orders)
+            for (int k = 0; k < T; ++k) cur[k] += fcell[(int64_t)q * T + k];
+        for (int k = 0; k < T; ++k) nonzero |= cur[k] != 0.0;
+        if (!nonzero && q + 2 >= n_orders) break;
+        coef = coef * tau * tau / ((double)(2 * r) * (double)(2 * r - 1));
+        for (int k = 0; k < T; ++k) acc[k] += coef * cur[k];
+    }
+}
+
 int hwo_cons_half(const hwo_problem *p, int to_grid, const double *u_from, const double *u_old,
                   double *u_new, const int64_t *sel, int64_t nsel, int nthreads)
 {
+    return hwo_cons_half_ext(p, to_grid, u_from, u_old, NULL, 0, NULL, u_new, sel, nsel, nthreads);
+}
+
+int hwo_cons_half_ext(const hwo_problem *p, int to_grid, const double *u_from, const double *u_old,
+                      const double *f_coef, int n_orders, const double *wall_u, double *u_new,
+                      const int64_t *sel, int64_t nsel, int nthreads)
+{
     if (check_problem(p) || p->method != HWO_CONSERVATIVE) return -1;
+    if (n_orders < 0 || (n_orders > 0 && !f_coef)) return -1;
     const int d = p->d, m = p->m, M = m + 1, P = 2 * m + 2;
     const int Mu_tot = pw(M, d), T = pw(P, d);
     const int64_t count = sel ? nsel : hwo_nodes(p, to_grid);
@@ -557,8 +720,13 @@ int hwo_cons_half(const hwo_problem *p, int to_grid, const double *u_from, const
             corners_t cr;
             out_index(p, to_grid, node, idx);
             find_corners(p, to_grid, idx, &cr);
-            tensor_interp(p, tb, &cr, u_from, M, md, a, work);
-            cons_even_odd_sum(p, a, 0.5 * p->dt, 0, acc, cur, tmp);
+            const walls_t wu = {to_grid == HWO_PRIMAL ? wall_u : NULL, M};
+            tensor_interp(p, tb, &cr, u_from, M, md, &wu, a, work);
+            if (n_orders > 0)
+                cons_forced_sum(p, a, 0.5 * p->dt, f_coef + node * (int64_t)n_orders * T, n_orders, acc,
+                                cur, tmp);
+            else
+                cons_even_odd_sum(p, a, 0.5 * p->dt, 0, acc, cur, tmp);
             for (int c = 0; c < Mu_tot; ++c) {
                 int rem = c, off = 0, st = 1;
                 for (int i = 0; i < d; ++i) {
@@ -601,10 +769,10 @@ int hwo_cons_startup(const hwo_problem *p, const double *u0, const double *v0, d
             corners_t cr;
             out_index(p, HWO_DUAL, node, idx);
             find_corners(p, HWO_DUAL, idx, &cr);
-            tensor_interp(p, tb, &cr, u0, M, md, a, work);
+            tensor_interp(p, tb, &cr, u0, M, md, NULL, a, work);
             cons_even_odd_sum(p, a, 0.5 * p->dt, 0, acc, cur, tmp);
             if (v0) {
-                tensor_interp(p, tb, &cr, v0, M, md, a, work);
+                tensor_interp(p, tb, &cr, v0, M, md, NULL, a, work);
                 cons_even_odd_sum(p, a, 0.5 * p->dt, 1, acc2, cur, tmp);
                 for (int k = 0; k < T; ++k) acc[k] += acc2[k];
             }
@@ -680,8 +848,8 @@ static double seminorm_pair(const hwo_problem *p, int center_grid, const double 
             corners_t cr;
             out_index(p, center_grid, node, idx);
             find_corners(p, center_grid, idx, &cr);
-            tensor_interp(p, tb, &cr, f, M, md, fa, work);
-            tensor_interp(p, tb, &cr, g, M, md, ga, work);
+            tensor_interp(p, tb, &cr, f, M, md, NULL, fa, work);
+            tensor_interp(p, tb, &cr, g, M, md, NULL, ga, work);
             double w = hfac;
             for (int i = 0; i < d; ++i)
                 if (p->bc[i] != HWO_PERIODIC && center_grid == HWO_PRIMAL &&

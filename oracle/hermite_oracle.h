@@ -33,6 +33,17 @@ int hwo_diss_half_forced(const hwo_problem *p, int to_grid, const double *u_in, 
                          const int64_t *sel, int64_t nsel, int nthreads);
 int hwo_cons_half(const hwo_problem *p, int to_grid, const double *u_from, const double *u_old,
                   double *u_new, const int64_t *sel, int64_t nsel, int nthreads);
+/* Half steps with forcing and inhomogeneous / time-dependent wall data (Sec. 3.1.3).    */
+/* wall_u, wall_v: NULL (homogeneous walls) or the wall records of every face (layout in  */
+/* hermite_oracle.c), used on half steps onto the primal grid.  Conservative forcing:     */
+/* n_orders blocks of (2m+2)^d values per output node, phi[q][k] = h^k/k! d^k d^q/dt^q f  */
+/* at the node and the time of the input level.                                          */
+int hwo_diss_half_ext(const hwo_problem *p, int to_grid, const double *u_in, const double *v_in,
+                      const double *f_coef, int n_orders, const double *wall_u, const double *wall_v,
+                      double *u_out, double *v_out, const int64_t *sel, int64_t nsel, int nthreads);
+int hwo_cons_half_ext(const hwo_problem *p, int to_grid, const double *u_from, const double *u_old,
+                      const double *f_coef, int n_orders, const double *wall_u, double *u_new,
+                      const int64_t *sel, int64_t nsel, int nthreads);
 int hwo_cons_startup(const hwo_problem *p, const double *u0, const double *v0, double *u_half,
                      int nthreads);
 double hwo_cons_energy(const hwo_problem *p, int grid_a, const double *u_a, const double *u_b_new,
