@@ -7,8 +7,8 @@
  * Problem statement (Sec. 2.1, Sec. 3, Sec. 4):
  *   domain prod_i [xl_i, xr_i], n_i cells, h_i = (xr_i - xl_i)/n_i;
  *   constant speed c, time step dt with c dt <= min_i h_i (Sec. 1);
- *   walls per dimension: periodic, homogeneous Dirichlet or homogeneous Neumann
- *   (Sec. 3.1.3: ghost polynomials by odd / even extension);
+ *   walls per dimension: periodic, Dirichlet or Neumann (Sec. 3.1.3: ghost polynomials
+ *   by odd / even extension; homogeneous, or with wall data through hw_half_step_ext);
  *   nodal degree m: (m+1)^d coefficients of u per node, m^d of v (dissipative).
  *
  * Grids (Sec. 2.1).  Primal nodes x_i = xl + i h, dual nodes x_{i+1/2}.  Periodic
@@ -149,21 +149,58 @@ hw_status hw_prepare_advance(hw_solver* s, int n_full_steps);
 /* Advance n half steps with plain kernel launches (no graph). */
 hw_status hw_half_steps(hw_solver* s, int n_half, void* stream);
 
-/* One half step of a single dissipative problem with a forcing term,
- * u_tt = c^2 Lap u + f (Sec. 3.1.2 eq. (recursion_diss_1d_2): stage s of the Taylor
- * series in time receives dt^s/s! times the (s-1)-th time derivative of f; here in
- * closed form, exact for f polynomial in time up to the orders given).
- * f_coef: device pointer (FP64, caller-owned, read during the call's kernel on `stream`)
- *   to [n_out][n_orders][(2m)^d] values phi[r][k] = h^k/k! d^k/dx^k d^r/dt^r f (k a
- *   multi-index, k_x fastest, 0 <= k_i < 2m) at every node of the grid this half step
- *   writes (the grid opposite hw_state_grid; node order as in hw_layout) and at the
- *   time at the start of the half step.  f of degree <= 2m-1 per dimension is
- *   represented exactly.
- * n_orders: 0..16 (0 = no forcing; f_coef may then be NULL).
- * Runs the generic kernel (plain launch, no graph); a taylor_stages truncation drops
- * the forcing terms of later stages as well.  HW_EINVAL for batches, the
- * conservative method, n_orders out of range or a NULL f_coef with n_orders > 0;
+/* One half step of a single problem with a forcing term and / or inhomogeneous,
+ * time-dependent wall data (plain launches, no graph).
+ *
+ * Forcing, u_tt = c^2 Lap u + f.  Dissipative method: Sec. 3.1.2 eq.
+ * (recursion_diss_1d_2), stage s of the Taylor series in time receives dt^s/s! times the
+ * (s-1)-th time derivative of f.  Conservative method: eq. (wavequ) with f in the even
+ * Taylor sum of eq. (update), d^2r u/dt^2r = c^2 Lap d^(2r-2) u/dt^(2r-2) +
+ * d^(2r-2) f/dt^(2r-2).  Both in closed form, exact for f polynomial in time up to the
+ * orders given.  f_coef: device pointer (FP64, caller-owned, read during the call's
+ * kernels on `stream`) to [n_out][n_orders][K^d] values phi[r][k] = h^k/k! d^k/dx^k
+ * d^r/dt^r f (k a multi-index, k_x fastest, 0 <= k_i < K) at every node of the grid this
+ * half step writes (the grid opposite hw_state_grid for the dissipative method; node
+ * order as in hw_layout), with K = 2m at the time at the start of the half step
+ * (dissipative) and K = 2m+2 at the middle time, the time of the other grid's level
+ * (conservative; only the even orders r enter).  n_orders: 0..16 (0 = no forcing; f_coef
+ * may then be NULL).  A taylor_stages truncation drops the forcing terms of later stages
+ * as well.  With forcing the whole half step runs in the generic kernel.
+ *
+ * Wall data (Sec. 3.1.3).  On a half step that writes the primal grid the cells at a
+ * non-periodic wall have ghost corners.  With wall_u (and, dissipative, wall_v) NULL they
+ * are the homogeneous odd (Dirichlet) / even (Neumann) mirror images of the interior
+ * nodes.  Otherwise the ghost data are R(interior) + 2 W(ghost): R the homogeneous mirror,
+ * W the solution's prescribed-parity part about the wall (Dirichlet: its even normal part,
+ * whose constant term is the wall value g(t) and whose higher even terms follow from g
+ * through the PDE, e.g. u_xx = (g_tt - c^2 Lap_tangential g)/c^2; Neumann: its odd normal
+ * part), taken at the ghost node half a cell beyond the wall; at corners the walls are
+ * applied dimension by dimension in increasing order.  The records (FP64 device arrays,
+ * caller-owned) give W at wall points:
+ *   faces: for every non-periodic dimension i in increasing order, the low wall
+ *     (x_i = xl_i) then the high wall (x_i = xr_i);
+ *   wall points of face i: the positions of the input grid's nodes (the dual grid,
+ *     hw_layout) in the other dimensions t, extended by one ghost position at each end
+ *     when t is non-periodic (index 0 = half a cell below xl_t, n_t + 1 = half a cell above
+ *     xr_t; periodic t: the n_t dual nodes), x fastest;
+ *   one record per wall point: M^d values (M = m+1 for wall_u, m for wall_v), coefficient
+ *     index l_x fastest; in dimension i the index j stands for the normal degree k = 2j
+ *     (Dirichlet) or 2j+1 (Neumann); each entry is h_i^k/k! d_i^k prod_{t != i}
+ *     h_t^l_t/l_t! d_t^l_t of the solution (u, resp. v = u_t) at the wall point and at the
+ *     time of the half step's input data.
+ * The records are read only on half steps that write the primal grid (else ignored) and
+ * only at the wall points some ghost corner needs.  Without forcing the problem's own
+ * kernel runs the half step with homogeneous walls and a second launch adds the wall
+ * data's contribution to the cells at the walls (the half step is linear in the ghost
+ * data).
+ *
+ * HW_EINVAL for batches, n_orders out of range, a NULL f_coef with n_orders > 0, a
+ * dissipative call with only one of wall_u / wall_v, or a conservative one with wall_v;
  * HW_ESTATE if no state is set. */
+hw_status hw_half_step_ext(hw_solver* s, const double* f_coef, int n_orders, const double* wall_u,
+                           const double* wall_v, void* stream);
+
+/* hw_half_step_ext with homogeneous walls. */
 hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream);
 
 /* Copy the state out (device pointers, FP64, layouts as above; the data of Sec. 3.1.1

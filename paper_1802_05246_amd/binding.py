@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 
 # every entry point declared in include/hermite_wave.h
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
-                "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_get_state", "hw_state_grid", "hw_energy",
+                "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_half_step_ext", "hw_get_state", "hw_state_grid", "hw_energy",
                 "hw_energy_noalloc",
                 "hw_time", "hw_last_error", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
@@ -73,6 +73,7 @@ def lib():
             "hw_half_steps": ([vp, ctypes.c_int, vp], ctypes.c_int),
             "hw_prepare_advance": ([vp, ctypes.c_int], ctypes.c_int),
             "hw_half_step_forced": ([vp, dp, ctypes.c_int, vp], ctypes.c_int),
+            "hw_half_step_ext": ([vp, dp, ctypes.c_int, dp, dp, vp], ctypes.c_int),
             "hw_get_state": ([vp, dp, dp, vp], ctypes.c_int),
             "hw_state_grid": ([vp], ctypes.c_int),
             "hw_energy": ([vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
@@ -199,6 +200,10 @@ def hw_half_step_forced(h, f_coef, n_orders, stream=None):
     _check(lib().hw_half_step_forced(h, _ptr(f_coef), n_orders, _stream(stream)))
 
 
+def hw_half_step_ext(h, f_coef, n_orders, wall_u, wall_v, stream=None):
+    _check(lib().hw_half_step_ext(h, _ptr(f_coef), n_orders, _ptr(wall_u), _ptr(wall_v), _stream(stream)))
+
+
 def hw_get_state(h, u, w, stream=None):
     _check(lib().hw_get_state(h, _ptr(u), _ptr(w), _stream(stream)))
 
@@ -292,6 +297,15 @@ class Solver:
             return
         f = self._dev(f_coef)
         hw_half_step_forced(self.h, f, int(f.shape[1]))
+        self.torch.cuda.current_stream().synchronize()
+
+    def half_step_ext(self, f_coef=None, wall_u=None, wall_v=None):
+        """One half step with forcing coefficients of shape (n_out, R, K^d) and / or wall
+        records (see hw_half_step_ext); None: no forcing / homogeneous walls."""
+        f = None if f_coef is None else self._dev(f_coef)
+        wu = None if wall_u is None else self._dev(wall_u)
+        wv = None if wall_v is None else self._dev(wall_v)
+        hw_half_step_ext(self.h, f, 0 if f is None else int(f.shape[1]), wu, wv)
         self.torch.cuda.current_stream().synchronize()
 
     def state_grid(self):

@@ -90,7 +90,10 @@ struct hw_solver {
     size_t lds = 0;
     int grid = 0;
     double* partials = nullptr;
-    double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single dissipative problem)
+    double* forcing_w = nullptr;  // [2][HW_MAXF][HW_MAXJ] (single problems)
+    int64_t* wall_cells = nullptr; // primal nodes whose cell has a ghost corner (single problems)
+    int64_t* wall_prefix = nullptr; // {0, n_wall_cells}
+    int64_t n_wall_cells = 0;
     void* tiled_tables = nullptr; // weights of the tiled kernel for this problem's lam2 and tau
     std::vector<char> dense;      // per problem: served by the per-lane dense kernel (d <= 2)
     std::vector<const void*> dense_G;  // per problem: its cell matrix in the state precision
@@ -479,7 +482,7 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         if (hipMemcpy(s->split_descs, sd, sizeof sd, hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(HW_EHIP, "descriptor upload failed"));
     }
-    if (count == 1 && p0.method != HW_CONSERVATIVE) {
+    if (count == 1) {
         // forcing weights: u: tau^(r+2) j!/(2j+r+2)!, v: tau^(r+1) j!/(2j+r+1)!, zero for
         // terms beyond a stage truncation (the term enters stage 2j+r+2 / 2j+r+1)
         std::vector<double> fw((size_t)2 * HW_MAXF * HW_MAXJ, 0.0);
@@ -498,6 +501,33 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         if (hipMemcpy(s->forcing_w, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice) !=
             hipSuccess)
             return cleanup(fail(HW_EHIP, "forcing table upload failed"));
+    }
+    if (count == 1) {
+        // primal nodes on a non-periodic wall: the cells of half steps onto the primal grid
+        // that have ghost corners (the work list of the wall-data correction)
+        const Prob& P = s->probs[0];
+        std::vector<int64_t> wc;
+        for (int64_t node = 0; node < P.nodes[HW_PRIMAL]; ++node) {
+            int64_t r = node;
+            bool wall = false;
+            for (int i = 0; i < p0.d; ++i) {
+                const int e = P.ext[HW_PRIMAL][i];
+                const int64_t oi = r % e;
+                r /= e;
+                if (p0.bc[i] != HW_PERIODIC && (oi == 0 || oi == e - 1)) wall = true;
+            }
+            if (wall) wc.push_back(node);
+        }
+        s->n_wall_cells = (int64_t)wc.size();
+        if (!wc.empty()) {
+            const int64_t pre[2] = {0, s->n_wall_cells};
+            if (hipMalloc((void**)&s->wall_cells, wc.size() * sizeof(int64_t)) != hipSuccess ||
+                hipMalloc((void**)&s->wall_prefix, sizeof pre) != hipSuccess)
+                return cleanup(fail(HW_ENOMEM, "wall cell list allocation failed"));
+            if (hipMemcpy(s->wall_cells, wc.data(), wc.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(s->wall_prefix, pre, sizeof pre, hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(HW_EHIP, "wall cell list upload failed"));
+        }
     }
     if (!s->dense.empty()) {
         // cell matrices (problems with identical maps share one), and the generic kernel's
@@ -651,6 +681,8 @@ void hw_destroy(hw_solver* s)
     if (s->prefix) (void)hipFree(s->prefix);
     if (s->partials) (void)hipFree(s->partials);
     if (s->forcing_w) (void)hipFree(s->forcing_w);
+    if (s->wall_cells) (void)hipFree(s->wall_cells);
+    if (s->wall_prefix) (void)hipFree(s->wall_prefix);
     if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
     if (s->cmap_tables) (void)hipFree(s->cmap_tables);
     for (void* g : s->dense_alloc) (void)hipFree(g);
@@ -744,24 +776,62 @@ hw_status hw_half_steps(hw_solver* s, int n, void* stream)
     return HW_OK;
 }
 
-hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream)
+hw_status hw_half_step_ext(hw_solver* s, const double* f_coef, int n_orders, const double* wall_u,
+                           const double* wall_v, void* stream)
 {
     if (check_solver(s)) return HW_EINVAL;
-    if (s->probs.size() != 1 || s->probs[0].p.method == HW_CONSERVATIVE || !s->forcing_w)
-        return fail(HW_EINVAL, "forcing applies to a single dissipative problem");
+    if (s->probs.size() != 1 || !s->forcing_w)
+        return fail(HW_EINVAL, "forcing and wall data apply to single problems");
+    const Prob& P = s->probs[0];
+    const bool cons = P.p.method == HW_CONSERVATIVE;
     if (n_orders < 0 || n_orders > HW_MAXF)
         return fail(HW_EINVAL, "n_orders must be in 0..%d", HW_MAXF);
     if (n_orders > 0 && !f_coef) return fail(HW_EINVAL, "null forcing coefficients");
-    if (s->precision == HW_BF16) return fail(HW_EUNSUPPORTED, "no forced steps with BF16 operands");
+    if (cons ? (wall_v != nullptr) : ((wall_u == nullptr) != (wall_v == nullptr)))
+        return fail(HW_EINVAL, cons ? "the conservative method has no v wall data"
+                                    : "dissipative wall data need both the u and the v records");
     if (!s->state_set) return fail(HW_ESTATE, "state not set");
     hipStream_t st = (hipStream_t)stream;
     const int phase = (int)(s->half_steps & 1);
-    ForcingArgs fa{n_orders > 0 ? f_coef : nullptr, n_orders, s->forcing_w};
-    // the generic kernel carries the forcing terms (the tiled kernel does not)
-    HIP_TRY(hw_launch_generic(s->d, s->fp64, s->descs + (size_t)(phase * 2) * 1, s->prefix + (size_t)phase * 2, 1,
-                              s->total_cells[phase], s->ops, s->lds, s->grid, st, &fa));
+    const int q = (int)((s->half_steps >> 1) & 1);
+    const ProblemDesc* desc = s->descs + (size_t)(phase * 2 + q);
+    const bool to_primal = s->h_descs[(size_t)(phase * 2 + q)].to_grid == HW_PRIMAL;
+    const bool walls = wall_u != nullptr && to_primal && s->n_wall_cells > 0;
+    if (n_orders > 0) {
+        // the generic kernel carries the forcing terms (and the wall data with them)
+        ForcingArgs fa;
+        fa.coef = f_coef;
+        fa.orders = n_orders;
+        fa.w = s->forcing_w;
+        if (walls) {
+            fa.wall_u = wall_u;
+            fa.wall_v = wall_v;
+        }
+        HIP_TRY(hw_launch_generic(s->d, s->fp64, desc, s->prefix + (size_t)phase * 2, 1,
+                                  s->total_cells[phase], s->ops, s->lds, s->grid, st, &fa));
+    } else {
+        // the problem's own kernel with homogeneous walls, then the walls' contribution
+        // added to the wall cells (the half step is linear in the ghost data)
+        hw_status r = launch_half(s, phase, q, st);
+        if (r != HW_OK) return r;
+        if (walls) {
+            ForcingArgs fa;
+            fa.wall_u = wall_u;
+            fa.wall_v = wall_v;
+            fa.cells = s->wall_cells;
+            fa.correction = 1;
+            const int grid = (int)std::min<int64_t>(s->n_wall_cells, (int64_t)s->grid);
+            HIP_TRY(hw_launch_generic(s->d, s->fp64, desc, s->wall_prefix, 1, s->n_wall_cells, s->ops,
+                                      s->lds, grid, st, &fa));
+        }
+    }
     s->half_steps++;
     return HW_OK;
+}
+
+hw_status hw_half_step_forced(hw_solver* s, const double* f_coef, int n_orders, void* stream)
+{
+    return hw_half_step_ext(s, f_coef, n_orders, nullptr, nullptr, stream);
 }
 
 static hw_status graph_for(hw_solver* s, int n, hipGraphExec_t* out)

@@ -50,16 +50,28 @@ struct ProblemDesc {
     void* work;
 };
 
-// Forcing of one dissipative half step (u_tt = c^2 Lap u + f): for every output node,
-// `orders` blocks of (2m)^d scaled space-time Taylor coefficients
-// h^k/k! d^k/dx^k d^r/dt^r f at the node and the start of the half step (FP64).
-// w[0][r][j] = tau^(r+2) j!/(2j+r+2)! (u), w[1][r][j] = tau^(r+1) j!/(2j+r+1)! (v),
-// zero beyond a stage truncation.
+// Forcing and inhomogeneous wall data of one half step of the generic kernel.
+// Forcing (u_tt = c^2 Lap u + f): for every output node, `orders` blocks of scaled
+// space-time Taylor coefficients h^k/k! d^k/dx^k d^r/dt^r f at the node (FP64), (2m)^d per
+// block for the dissipative method (at the start of the half step), (2m+2)^d for the
+// conservative one (at the middle time).  w[0][r][j] = tau^(r+2) j!/(2j+r+2)! (u),
+// w[1][r][j] = tau^(r+1) j!/(2j+r+1)! (v), zero beyond a stage truncation; the
+// conservative update adds twice the u weights of the even orders.
+// Walls (half steps onto the primal grid): the wall records of every face (FP64, the
+// layout of hw_half_step_ext), u with (m+1)^d and v with m^d values per record; a ghost
+// corner gets R(interior) + 2 W(ghost).  correction != 0: the interior data count as zero
+// and the outputs are accumulated (+=), so the launch adds the walls' contribution to a
+// half step computed with homogeneous walls; `cells` (or null) lists the output nodes
+// of the work list.
 #define HW_MAXF 16
 struct ForcingArgs {
-    const double* coef; // null: no forcing
-    int orders;
-    const double* w;    // [2][HW_MAXF][HW_MAXJ]
+    const double* coef = nullptr; // null: no forcing
+    int orders = 0;
+    const double* w = nullptr;    // [2][HW_MAXF][HW_MAXJ]
+    const double* wall_u = nullptr;
+    const double* wall_v = nullptr;
+    const int64_t* cells = nullptr;
+    int correction = 0;
 };
 
 // Energy (conservative): sum over the cells centred at the nodes of `center_grid`

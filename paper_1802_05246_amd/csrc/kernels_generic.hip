@@ -141,34 +141,114 @@ __device__ inline Geom geom_of(const ProblemDesc& P)
     return G;
 }
 
+// Wall points of the face normal to dimension i: the input grid's nodes in the other
+// dimensions, one ghost position added at each end of a non-periodic one.
+template <int D>
+__device__ int64_t face_points(const Geom& P, int i)
+{
+    int64_t n = 1;
+    for (int t = 0; t < D; ++t)
+        if (t != i) n *= (P.bc[t] == 0) ? P.ext_from[t] : P.ext_from[t] + 2;
+    return n;
+}
+
+// Inhomogeneous wall data of ghost corner s at coefficient l (Sec. 3.1.3): the sum over
+// its ghost dimensions r (applied in increasing order) of 2 W_r at the ghost position,
+// times the reflection signs of the ghost dimensions applied after r.  W_r at the ghost
+// is the record's normal expansion (degrees 2j Dirichlet, 2j+1 Neumann, about the wall)
+// shifted by half a cell outwards.  The record is read at the wall point whose
+// tangential positions are the corner's after the dimensions before r were reflected.
+template <int D>
+__device__ double wall_term(const Geom& P, const Corners& cr, const int* s, const int* l, int Md,
+                            const double* __restrict__ rec)
+{
+    const int rs = ipow(Md, D);
+    double total = 0.0;
+    for (int r = 0; r < D; ++r) {
+        if (!cr.ghost[r][s[r]]) continue;
+        double sgn = 1.0;
+        for (int g = r + 1; g < D; ++g)
+            if (cr.ghost[g][s[g]]) {
+                const bool odd = (l[g] & 1);
+                if ((P.bc[g] == 1) ? !odd : odd) sgn = -sgn;
+            }
+        int64_t off = 0;
+        for (int i = 0; i < r; ++i)
+            if (P.bc[i] != 0) off += 2 * face_points<D>(P, i);
+        if (s[r] == 1) off += face_points<D>(P, r);
+        int64_t pt = 0, stride = 1;
+        for (int t = 0; t < D; ++t) {
+            if (t == r) continue;
+            int pos, ext;
+            if (P.bc[t] == 0) {
+                ext = P.ext_from[t];
+                pos = cr.node[t][s[t]];
+            } else {
+                ext = P.ext_from[t] + 2;
+                if (t < r && cr.ghost[t][s[t]]) pos = s[t] == 0 ? 0 : P.ext_from[t] + 1;
+                else pos = cr.node[t][s[t]] + 1;
+            }
+            pt += pos * stride;
+            stride *= ext;
+        }
+        const double* rw = rec + (off + pt) * rs;
+        const double delta = s[r] == 0 ? -0.5 : 0.5;
+        double sum = 0.0;
+        for (int j = 0; j < Md; ++j) {
+            const int k = (P.bc[r] == 1) ? 2 * j : 2 * j + 1;
+            if (k < l[r]) continue;
+            int c = 0, cs = 1;
+            for (int t = 0; t < D; ++t) {
+                c += (t == r ? j : l[t]) * cs;
+                cs *= Md;
+            }
+            // binomial(k, l_r) delta^(k - l_r)
+            double b = 1.0;
+            for (int q = 0; q < l[r]; ++q) b = b * (k - q) / (q + 1);
+            for (int q = 0; q < k - l[r]; ++q) b *= delta;
+            sum += b * rw[c];
+        }
+        total += sgn * 2.0 * sum;
+    }
+    return total;
+}
+
 // Gather corner data into the mixed layout j_i = s_i*Md + l_i (extent 2*Md per dim).
 // Mirrored corners: coefficient l along the wall normal times (-1)^(l+1) for
-// Dirichlet, (-1)^l for Neumann.
+// Dirichlet, (-1)^l for Neumann, plus the wall data's term when `walls` is given;
+// with `zero_base` the node data count as zero (only the wall terms are gathered).
 template <typename T, int D>
 __device__ void gather(const Geom& P, const Corners& cr, const T* __restrict__ data, int Md,
-                       T* X, int lane)
+                       T* X, int lane, const double* walls = nullptr, bool zero_base = false)
 {
     const int K = 2 * Md;
     const int total = ipow(K, D);
     const int ncoef = ipow(Md, D);
     for (int e = lane; e < total; e += GW) {
         int rem = e, node = 0, nstride = 1, coef = 0, cstride = 1;
+        int sv[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
+        bool any_ghost = false;
         T sign = T(1);
         for (int i = 0; i < D; ++i) {
             const int jd = rem % K;
             rem /= K;
             const int s = jd / Md, l = jd % Md;
+            sv[i] = s;
+            lv[i] = l;
             node += cr.node[i][s] * nstride;
             nstride *= P.ext_from[i];
             coef += l * cstride;
             cstride *= Md;
             if (cr.ghost[i][s]) {
+                any_ghost = true;
                 const bool odd = (l & 1);
                 const bool neg = (P.bc[i] == 1) ? !odd : odd;
                 if (neg) sign = -sign;
             }
         }
-        X[e] = sign * data[(int64_t)node * ncoef + coef];
+        T x = zero_base ? T(0) : sign * data[(int64_t)node * ncoef + coef];
+        if (walls && any_ghost) x += T(wall_term<D>(P, cr, sv, lv, Md, walls));
+        X[e] = x;
     }
 }
 
@@ -225,8 +305,9 @@ __device__ void diss_cell(const ProblemDesc& P, const T* lops, const WTab& WT, i
     Corners cr;
     const Geom G = geom_of<D>(P);
     find_corners<D>(G, cell, cr);
-    gather<T, D>(G, cr, (const T*)P.u_in, M, Xu, lane);
-    gather<T, D>(G, cr, (const T*)P.v_in, m, Xv, lane);
+    const bool walls = P.to_grid == 0 && FA.wall_u != nullptr;
+    gather<T, D>(G, cr, (const T*)P.u_in, M, Xu, lane, walls ? FA.wall_u : nullptr, FA.correction != 0);
+    gather<T, D>(G, cr, (const T*)P.v_in, m, Xv, lane, walls ? FA.wall_v : nullptr, FA.correction != 0);
     __syncthreads();
 
     const T* full = lops;
@@ -334,8 +415,8 @@ __device__ void diss_cell(const ProblemDesc& P, const T* lops, const WTab& WT, i
                     const int idx = (a[0] + 2 * b0) + E * ((a[1] + 2 * b1) + E * (a[2] + 2 * b2));
                     acc += T(g * cq[j]) * Q[idx] + T(g * crr[j]) * Rr[idx];
                 }
-        if (is_u) uo[c] = acc;
-        else vo[c] = acc;
+        T* dst = is_u ? uo + c : vo + c;
+        *dst = FA.correction ? *dst + acc : acc;
     }
     if (FA.coef == nullptr) return;
 
@@ -379,7 +460,7 @@ __device__ void diss_cell(const ProblemDesc& P, const T* lops, const WTab& WT, i
 
 template <typename T, int D>
 __device__ void cons_cell(const ProblemDesc& P, const T* lops, const WTab& WT, int64_t cell, T* sm,
-                          int lane)
+                          int lane, const ForcingArgs& FA)
 {
     const int m = P.m, M = m + 1, Pn = 2 * m + 2, K = Pn;
     const int KD = ipow(K, D);
@@ -394,7 +475,8 @@ __device__ void cons_cell(const ProblemDesc& P, const T* lops, const WTab& WT, i
     Corners cr;
     const Geom G = geom_of<D>(P);
     find_corners<D>(G, cell, cr);
-    gather<T, D>(G, cr, (const T*)P.u_in, M, Xu, lane);
+    const bool walls = P.to_grid == 0 && FA.wall_u != nullptr && P.variant == HWV_CONS;
+    gather<T, D>(G, cr, (const T*)P.u_in, M, Xu, lane, walls ? FA.wall_u : nullptr, FA.correction != 0);
     if (startup) gather<T, D>(G, cr, (const T*)P.v_in, M, Xv, lane);
     __syncthreads();
     const T* full = lops;
@@ -426,8 +508,42 @@ __device__ void cons_cell(const ProblemDesc& P, const T* lops, const WTab& WT, i
                     acc += T(g * WT.cuQ[j]) * A[idx];
                     if (startup) acc += T(g * WT.cuR[j]) * B[idx];
                 }
-        if (P.variant == HWV_CONS) uo[c] = T(2) * acc - uold[cell * Mu_tot + c];
+        if (FA.correction) uo[c] += T(2) * acc;
+        else if (P.variant == HWV_CONS) uo[c] = T(2) * acc - uold[cell * Mu_tot + c];
         else uo[c] = acc;
+    }
+    if (FA.coef == nullptr || P.variant != HWV_CONS) return;
+
+    // forcing (eq. (wavequ)): u_new += 2 sum_k sum_j tau^(2k+2)/(2j+2k+2)! [L^j f_2k],
+    // the even time derivatives f_2k of f at the middle time, extent 2m+2 per dimension;
+    // every lane adds to the outputs it wrote above
+    const int PD = ipow(Pn, D);
+    const double* fc = FA.coef + cell * (int64_t)FA.orders * PD;
+    for (int r = 0; r < FA.orders; r += 2) {
+        __syncthreads();
+        for (int e = lane; e < PD; e += GW) bufA[e] = T(fc[(int64_t)r * PD + e]);
+        __syncthreads();
+        const double* w = FA.w + r * HW_MAXJ;
+        for (int c = lane; c < Mu_tot; c += GW) {
+            int a[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
+            int rem = c;
+            for (int i = 0; i < D; ++i) {
+                a[i] = rem % M;
+                rem /= M;
+                bmax[i] = (Pn - 1 - a[i]) / 2;
+            }
+            T acc = T(0);
+            for (int b2 = 0; b2 <= bmax[2]; ++b2)
+                for (int b1 = 0; b1 <= bmax[1]; ++b1)
+                    for (int b0 = 0; b0 <= bmax[0]; ++b0) {
+                        double g = WT.f(0, a[0], b0);
+                        if (D > 1) g *= WT.f(1, a[1], b1);
+                        if (D > 2) g *= WT.f(2, a[2], b2);
+                        const int idx = (a[0] + 2 * b0) + Pn * ((a[1] + 2 * b1) + Pn * (a[2] + 2 * b2));
+                        acc += T(2.0 * g * w[b0 + b1 + b2]) * bufA[idx];
+                    }
+            uo[c] += acc;
+        }
     }
 }
 
@@ -471,9 +587,10 @@ k_half_step(const ProblemDesc* __restrict__ descs, const int64_t* __restrict__ p
             __syncthreads();
             cur = lo;
         }
-        const int64_t cell = g - prefix[lo];
+        int64_t cell = g - prefix[lo];
+        if (FA.cells) cell = FA.cells[cell];
         if (P.variant <= HWV_DISS_SIMPLE) diss_cell<T, D>(P, lops, WT, cell, sm, lane, FA);
-        else cons_cell<T, D>(P, lops, WT, cell, sm, lane);
+        else cons_cell<T, D>(P, lops, WT, cell, sm, lane, FA);
         __syncthreads();
     }
 }
@@ -652,7 +769,7 @@ hipError_t hw_launch_generic(int d, bool fp64, const ProblemDesc* descs, const i
                              int nprob, int64_t total, const void* ops, size_t lds, int grid,
                              hipStream_t st, const ForcingArgs* forcing)
 {
-    ForcingArgs fa{nullptr, 0, nullptr};
+    ForcingArgs fa;
     if (forcing) fa = *forcing;
     if (fp64) {
         if (d == 1) return launch_hs<double, 1>(descs, prefix, nprob, total, ops, lds, grid, st, fa);

@@ -99,9 +99,21 @@ def test_forced_entry_point_errors():
     s.half_step_forced(None)  # zero orders: a plain half step
     assert B.hw_state_grid(s.h) == B.HW_DUAL
     s.close()
-    cons = W.make_spec(2, 2, [4, 4], 0.0, 1.0, 1.0, cfl=0.9, method=W.CONSERVATIVE)
+    # the conservative method takes forcing (and u wall data) too, but no v wall data
+    cons = W.make_spec(2, 2, [4, 4], 0.0, 1.0, 1.0, cfl=0.9, bc=W.DIRICHLET, method=W.CONSERVATIVE)
     sc = B.Solver(cons, precision=B.HW_FP64)
     with pytest.raises(B.HwError) as e:
         B.hw_half_step_forced(sc.h, None, 0)
+    assert e.value.status == B.HW_ESTATE
+    sc.cons_startup(W.random_state(cons, 2)[0])
+    w = torch.zeros((40, 9), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.HwError) as e:
+        B.hw_half_step_ext(sc.h, None, 0, w, w)
     assert e.value.status == B.HW_EINVAL
     sc.close()
+    # batches take neither
+    sb = B.Solver(problems=[spec, spec], precision=B.HW_FP64)
+    with pytest.raises(B.HwError) as e:
+        B.hw_half_step_ext(sb.h, None, 0, None, None)
+    assert e.value.status == B.HW_EINVAL
+    sb.close()
