@@ -33,6 +33,17 @@ PEAKS_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
 # without sharing between neighbouring cells; bytes = read one node + write one node
 FLOPS_PER_CELL = 48272
 BYTES_PER_CELL = {"fp32": 2 * 91 * 4, "fp64": 2 * 91 * 8}
+# work the composed-map kernel executes per cell-update: 184 products of 16x16x4 (1024
+# multiply-adds) per 16 cells, i.e. 11 776 multiply-adds on the matrix cores (padded class
+# rows included), plus 1 460 vector additions of the corner butterflies
+EXECUTED_FLOPS_PER_CELL = 2 * 11776 + 1460
+# matrix-core busy fraction of the same kernel from its counters (SQ_BUSY_CYCLES /
+# SQ_VALU_MFMA_BUSY_CYCLES pass), tied to the source it was measured on like the traffic
+MFMA_BUSY_RECORD = {
+    "source_sha256": "992983c2c86334c1f287a1834acc0e4093603eeba236fb88a58bc3631c8dff86",
+    "busy_frac": 0.41,
+    "profile": "profiles/k_cmap3d-diss3d_m3_256cube-sq_counters.md",
+}
 
 
 # HBM traffic of one launch of the dominant kernel (the FP32 composed-map half step on this
@@ -61,6 +72,13 @@ def traffic_bytes():
     if not rec or rec.get("source_sha256") != source_digest():
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def mfma_busy():
+    rec = MFMA_BUSY_RECORD
+    if not rec or rec.get("source_sha256") != source_digest():
+        return None
+    return rec["busy_frac"]
 
 
 def copy_calibration(torch):
@@ -97,6 +115,11 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-operand form")
     ap.add_argument("--cpu-layers", type=int, default=40,
                     help="z-layers of the grid in the oracle's timed sample")
+    ap.add_argument("--cpu-layers-1t", type=int, default=3,
+                    help="z-layers of the oracle's single-thread sample")
+    ap.add_argument("--accuracy-steps", type=int, default=200,
+                    help="steps of the untimed accuracy leg (the workload's length); 0: skip")
+    ap.add_argument("--no-probes", action="store_true", help="skip the measured-peak probes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the plain copy used to scale HBM byte counters")
     return ap.parse_args()
@@ -152,7 +175,29 @@ def l2_errors(torch, W, w, s, t_final):
     return err, err / ref, val
 
 
-def cpu_baseline(W, layers, n):
+def physical_cores():
+    """(physical cores, logical CPUs) of the host, from /proc/cpuinfo."""
+    logical = os.cpu_count() or 1
+    try:
+        pairs = set()
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("physical id"):
+                    phys = line.split(":")[1].strip()
+                elif line.startswith("core id"):
+                    core = line.split(":")[1].strip()
+                elif not line.strip() and phys is not None and core is not None:
+                    pairs.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            pairs.add((phys, core))
+        return (len(pairs) or logical), logical
+    except OSError:
+        return logical, logical
+
+
+def cpu_baseline(W, layers, n, threads=None):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload: the
     first `layers` z-layers of cells of the n^3 grid, one primal -> dual half step."""
     import oracle
@@ -172,7 +217,8 @@ def cpu_baseline(W, layers, n):
         terms.append(term)
     u = W.separable_nodal(box, W.PRIMAL, 4, terms)
     v = np.zeros((box.nodes(W.PRIMAL), 27))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if threads is None:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     p = oracle.make_problem(3, 3, box.n, box.xl, box.xr, 1.0, dt, box.bc, W.DISS_FULL)
     t0 = time.perf_counter()
     uo, _ = oracle.diss_half(p, oracle.DUAL, u, v, nthreads=threads)
@@ -186,6 +232,42 @@ def cpu_baseline(W, layers, n):
     return {"value": cells / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{cells} cells ({layers} z-layers of the {n}^3 grid), one primal->dual "
                       f"half step, FP64, {el:.1f} s, CPU: {model}"}
+
+
+def rel_chunked(torch, a, b):
+    """relative L2 norm of a - b over every entry (chunked)"""
+    num = den = 0.0
+    step = 1 << 22
+    for k in range(0, a.shape[0], step):
+        num += float(((a[k:k + step] - b[k:k + step]) ** 2).sum())
+        den += float((b[k:k + step] ** 2).sum())
+    return math.sqrt(num / den)
+
+
+def accuracy_leg(torch, B, W, w, steps, kernel):
+    """The workload's own length, untimed: FP32 and FP64 forms advanced `steps` steps from
+    the initial data; the value coefficient against the exact radial solution (nodal L2),
+    and the FP32 state against the FP64 state over every coefficient, u and v apart."""
+    out = {}
+    states = {}
+    for prec, name in ((B.HW_FP64, "fp64"), (B.HW_FP32, "fp32")):
+        s = B.Solver(w.spec, precision=prec, kernel=kernel)
+        s.set_state(w.u0, w.v0)
+        s.advance(steps)
+        err, rel, _ = l2_errors(torch, W, w, s, steps * w.spec.dt)
+        out[f"{name}_value_rel"] = rel
+        out[f"{name}_value_abs"] = err
+        states[name] = s.get_state()
+        s.close()
+    (u32, v32), (u64, v64) = states["fp32"], states["fp64"]
+    out["fp32_vs_fp64_value_rel"] = rel_chunked(torch, u32[:, :1], u64[:, :1])
+    out["fp32_vs_fp64_all_u_coefficients_rel"] = rel_chunked(torch, u32, u64)
+    out["fp32_vs_fp64_all_v_coefficients_rel"] = rel_chunked(torch, v32, v64)
+    out["steps"] = steps
+    out["t_final"] = steps * w.spec.dt
+    del states, u32, v32, u64, v64
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -263,8 +345,20 @@ def main():
             if K64 == K:
                 bf16["vs_fp64_rel"] = float(torch.linalg.norm(val16 - val64) / torch.linalg.norm(val64))
         s16.close()
+    accuracy = None
+    if not args.no_error and args.accuracy_steps > 0:
+        log(f"[bench] accuracy leg: {args.accuracy_steps} steps of the FP32 and FP64 forms (untimed)")
+        accuracy = accuracy_leg(torch, B, W, w, args.accuracy_steps, kernel)
     del w
     torch.cuda.empty_cache()
+    probes = None
+    if not args.no_probes:
+        log("[bench] peak probes: STREAM triad, matrix-core FP32 / FP64")
+        probes = {"hbm_triad_gbs": B.hw_probe_stream_triad(1 << 28),
+                  "mfma_fp32_tflops": B.hw_probe_mfma(B.HW_FP32),
+                  "mfma_fp64_tflops": B.hw_probe_mfma(B.HW_FP64),
+                  "note": "attainable peaks measured on this GPU (triad over three 2 GiB FP64 arrays; "
+                          "independent 16x16x4 matrix-core products)"}
 
     # roofline of the dominant kernel (the half-step kernel of the FP32 form)
     launches = 2 * K
@@ -275,16 +369,36 @@ def main():
     bytes_launch = BYTES_PER_CELL["fp32"] * cells_per_launch
     ach_tflops = flops_launch / (avg_ms * 1e-3) / 1e12
     ach_gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+    exe_tflops = EXECUTED_FLOPS_PER_CELL * cells_per_launch / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(ach_tflops, 2),
             "peak": PEAKS_TFLOPS["fp32"], "unit": "TFLOP/s",
             "frac": round(ach_tflops / PEAKS_TFLOPS["fp32"], 4), "traffic": traffic_bytes() if (recorded and n == 256) else None,
+            "achieved_counts": "algorithmic flops (48 272 per cell-update, the factored method of the "
+                               "paper counted per cell): an algorithm-equivalent rate",
+            "executed_tflops": round(exe_tflops, 2),
+            "executed_frac": round(exe_tflops / PEAKS_TFLOPS["fp32"], 4),
+            "executed_counts": f"{EXECUTED_FLOPS_PER_CELL} flops per cell-update executed by the composed-map "
+                               "kernel (matrix-core multiply-adds incl. padding, butterfly additions)",
+            "mfma_busy_frac": mfma_busy() if (recorded and n == 256) else None,
             "kernel_avg_ms": round(avg_ms, 4), "hbm_algorithmic_gbs": round(ach_gbs, 1),
             "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 4)}
+    if probes:
+        roof["measured_peaks"] = probes
+        roof["frac_of_measured_fp32_mfma"] = round(ach_tflops / probes["mfma_fp32_tflops"], 4)
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {args.cpu_layers} z-layers")
         cpu = cpu_baseline(W, args.cpu_layers, n)
+        phys, logical = physical_cores()
+        cpu["physical_cores"] = phys
+        cpu["logical_cpus"] = logical
+        cpu["omp_num_threads_env"] = os.environ.get("OMP_NUM_THREADS")
+        if args.cpu_layers_1t > 0:
+            log(f"[bench] cpu baseline, one thread: oracle on {args.cpu_layers_1t} z-layers")
+            one = cpu_baseline(W, args.cpu_layers_1t, n, threads=1)
+            cpu["value_1thread"] = one["value"]
+            cpu["sample_1thread"] = one["sample"]
 
     out = {
         "metric": METRIC, "value": rate32, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
@@ -302,6 +416,7 @@ def main():
                       "kernel_avg_ms": ev64 / (2 * K64)},
         "tiled_fp32_form": tiled32,
         "bf16_form": bf16,
+        "accuracy_at_workload_length": accuracy,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -66,7 +66,8 @@ typedef enum {
 
 typedef enum {
     HW_KERNEL_AUTO = 0,    /* 3-D dissipative m = 3: composed in FP64 and FP32, tiled for
-                              BF16 operands; d <= 2: dense where it exists; else generic */
+                              BF16 operands; 2-D batches: batched; single problems with
+                              d <= 2: dense where it exists; else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
     HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
     HW_KERNEL_SPLIT = 3,   /* two kernels per half step, as in the paper's two-kernel GPU
@@ -82,11 +83,18 @@ typedef enum {
                               d = 2 conservative m <= 5, FP64 or FP32 (HW_EUNSUPPORTED
                               otherwise; with HW_KERNEL_AUTO the other problems of a batch
                               share one generic launch) */
-    HW_KERNEL_COMPOSED = 5 /* 3-D dissipative (full or simple variant, any truncation), m = 3,
+    HW_KERNEL_COMPOSED = 5, /* 3-D dissipative (full or simple variant, any truncation), m = 3,
                               FP64 or FP32, single problems: each cell's half step as its
                               composed matrix, corners combined by the reflection symmetry
                               of the Hermite operators, applied per output parity class to 16
                               cells at a time on the matrix cores (HW_EUNSUPPORTED otherwise) */
+    HW_KERNEL_BATCH = 6    /* 2-D, FP64 or FP32, any m and method, batches or single problems:
+                              the problems grouped by (m, method); per group and half step one
+                              persistent launch of the dense kernel walks a work list of tiles
+                              of every problem of the group (at most one launch per group,
+                              all of them in the captured graph); tile shapes chosen by the
+                              autotuner (HW_EUNSUPPORTED otherwise; the default for 2-D
+                              batches) */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;
@@ -243,14 +251,37 @@ double hw_time(const hw_solver* s);
 /* Thread-local message describing the last failure ("" if none). */
 const char* hw_last_error(void);
 
+/* The autotuner's choices so far in this process, one line per key (kernel, d, m,
+ * method, precision, size class -> chosen launch shape, its time).  Launch shapes are
+ * timed on the problem itself when a solver is created (HW_AUTOTUNE=0 in the environment
+ * turns this off; HW_TUNE_CACHE=<file> keeps the choices across processes).  The text is
+ * thread-local and valid until the next call from the same thread.  This is about the
+ * implementation's launch configuration, not the method of the paper. */
+const char* hw_tuning_report(void);
+
+/* ---- peak probes -------------------------------------------------------------------
+ * Measured attainable peaks of the current GPU, against which the rooflines are set (the
+ * paper times a DAXPY on its GPU for its attainable bandwidth, Sec. 6).  Both allocate
+ * their own buffers, run on a private stream and synchronise it.
+ * hw_probe_stream_triad: a = b + s c over three FP64 arrays of n elements (n even, >= 1024;
+ *   choose them far larger than the caches), 10 timed passes after 2 untimed;
+ *   *gbs_out = 24 n bytes per pass / time, in GB/s.
+ * hw_probe_mfma: 2048 workgroups of 4 waves, each wave 4096 rounds of 8 independent
+ *   16x16x4 matrix-core products (2048 flops each) in HW_FP32 or HW_FP64, no memory
+ *   traffic; *tflops_out in TFLOP/s. */
+hw_status hw_probe_stream_triad(int64_t n, double* gbs_out);
+hw_status hw_probe_mfma(int precision, double* tflops_out);
+
 /* ---- batches: independent problems advanced together --------------------------
  * Many independent problems of the kind above (each one the problem statement of
  * Sec. 2.1 with its own grid, m, c, dt, walls and method, Sec. 3 / Sec. 4) stepped
  * together.  All problems of a batch share d and precision.  hw_batch_advance captures
  * the step loop in a hipGraph.  How a half step of the batch is launched depends on
  * the kernel selector: HW_KERNEL_GENERIC runs one grid-stride launch over a work list
- * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_DENSE run one dense launch per problem
- * the dense kernel serves and one generic launch over the remaining problems.
+ * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_BATCH for 2-D batches run one persistent
+ * dense launch per (m, method) group over the tiles of all its problems; HW_KERNEL_DENSE
+ * runs one dense launch per problem the dense kernel serves and one generic launch over
+ * the remaining problems.
  * hw_batch_layout, hw_batch_set_state, hw_batch_cons_startup and hw_batch_get_state
  * are hw_layout, hw_set_state, hw_cons_startup and hw_get_state for problem i. */
 hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out);

@@ -18,6 +18,7 @@ HW_DISS_FULL, HW_DISS_SIMPLE, HW_CONSERVATIVE = 0, 1, 2
 HW_PERIODIC, HW_DIRICHLET, HW_NEUMANN = 0, 1, 2
 HW_FP64, HW_FP32, HW_BF16 = 0, 1, 2
 HW_KERNEL_AUTO, HW_KERNEL_GENERIC, HW_KERNEL_TILED, HW_KERNEL_SPLIT, HW_KERNEL_DENSE, HW_KERNEL_COMPOSED = 0, 1, 2, 3, 4, 5
+HW_KERNEL_BATCH = 6
 HW_PRIMAL, HW_DUAL = 0, 1
 
 STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
@@ -27,7 +28,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
                 "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_half_step_ext", "hw_get_state", "hw_state_grid", "hw_energy",
                 "hw_energy_noalloc",
-                "hw_time", "hw_last_error", "hw_batch_create", "hw_batch_layout",
+                "hw_time", "hw_last_error", "hw_tuning_report", "hw_probe_stream_triad", "hw_probe_mfma", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
                 "hw_batch_get_state"]
 
@@ -80,6 +81,9 @@ def lib():
             "hw_energy_noalloc": ([vp, dp, vp], ctypes.c_int),
             "hw_time": ([vp], ctypes.c_double),
             "hw_last_error": ([], ctypes.c_char_p),
+            "hw_tuning_report": ([], ctypes.c_char_p),
+            "hw_probe_stream_triad": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "hw_probe_mfma": ([ctypes.c_int, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "hw_batch_create": ([pp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
             "hw_batch_layout": ([vp, ctypes.c_int, ctypes.c_int, i64p, ip, ip], ctypes.c_int),
             "hw_batch_set_state": ([vp, ctypes.c_int, dp, dp, vp], ctypes.c_int),
@@ -93,6 +97,22 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+def hw_probe_stream_triad(n: int) -> float:
+    g = ctypes.c_double()
+    _check(lib().hw_probe_stream_triad(int(n), ctypes.byref(g)))
+    return g.value
+
+
+def hw_probe_mfma(precision: int) -> float:
+    t = ctypes.c_double()
+    _check(lib().hw_probe_mfma(int(precision), ctypes.byref(t)))
+    return t.value
+
+
+def hw_tuning_report() -> str:
+    return lib().hw_tuning_report().decode()
 
 
 def last_error() -> str:

@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhermite_wave.so")
-SOURCES = ["api.cpp", "cellmap.cpp", "kernels_generic.hip", "kernel_tiled3d.hip", "kernel_dense.hip", "kernel_cmap3d.hip"]
+SOURCES = ["api.cpp", "cellmap.cpp", "tune.cpp", "kernels_generic.hip", "kernel_tiled3d.hip", "kernel_dense.hip",
+           "kernel_cmap3d.hip", "probes.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # keep the compiler from forming packed FP32 (v_pk_*_f32) instructions

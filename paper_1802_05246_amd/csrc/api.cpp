@@ -72,6 +72,19 @@ struct hw_solver {
     int precision = HW_FP64;
     bool use_tiled = false;
     bool use_cmap = false;        // composed-map MFMA kernel (3-D dissipative, m = 3)
+    bool use_batch2d = false;     // batched 2-D path: one persistent launch per (m, method) class
+    struct BatchClass {
+        int m = 0;
+        bool cons = false;
+        std::vector<int> probs;            // problems of the class
+        DenseArgs* args = nullptr;         // device [phase 0..1][slot parity 0..1][class member]
+        int4* tiles[2] = {nullptr, nullptr}; // work list per phase: {member, x0, y0, 0}
+        int ntiles[2] = {0, 0};
+        int grid = 0;
+        int tx = 64;
+    };
+    std::vector<BatchClass> bclasses;
+    std::vector<int> dense_tx;    // per problem: tile width of the dense kernel (autotuned)
     void* cmap_tables = nullptr;
     bool state_set = false;
     int64_t half_steps = 0;
@@ -123,7 +136,7 @@ hw_status validate(const hw_problem* p)
         return fail(HW_EINVAL, "m = %d outside %d..%d for this method", p->m, mlo, HW_MAXM);
     if (p->precision < HW_FP64 || p->precision > HW_BF16)
         return fail(HW_EINVAL, "unknown precision %d", p->precision);
-    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_COMPOSED)
+    if (p->kernel < HW_KERNEL_AUTO || p->kernel > HW_KERNEL_BATCH)
         return fail(HW_EINVAL, "unknown kernel selector %d", p->kernel);
     if (!(p->c > 0.0) || !(p->dt > 0.0) || !std::isfinite(p->c) || !std::isfinite(p->dt))
         return fail(HW_EINVAL, "c and dt must be positive and finite");
@@ -262,9 +275,19 @@ hw_status check_solver(const hw_solver* s)
     return HW_OK;
 }
 
+DenseArgs dense_args(const hw_solver* s, int k, int i);
+
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
 {
     const int np = (int)s->probs.size();
+    if (s->use_batch2d) {
+        for (const auto& C : s->bclasses) {
+            const size_t n = C.probs.size();
+            HIP_TRY(hw_launch_dense_list(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.grid,
+                                         C.m, C.cons, s->fp64, st));
+        }
+        return HW_OK;
+    }
     if (s->use_tiled || s->use_cmap) {
         const Prob& P = s->probs[0];
         const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np];
@@ -291,20 +314,7 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         for (int i = 0; i < np; ++i) {
             if (!s->dense[i]) continue;
             const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np + i];
-            DenseArgs a;
-            for (int k = 0; k < 3; ++k) {
-                a.ext_from[k] = D.ext_from[k];
-                a.ext_to[k] = D.ext_to[k];
-                a.bc[k] = D.bc[k];
-            }
-            a.to_grid = D.to_grid;
-            a.u_in = D.u_in;
-            a.v_in = D.v_in;
-            a.u_old = D.u_old;
-            a.u_out = D.u_out;
-            a.v_out = D.v_out;
-            a.G = s->dense_G[i];
-            a.n_cells = D.n_out;
+            const DenseArgs a = dense_args(s, phase * 2 + q, i);
             HIP_TRY(hw_launch_dense(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
         }
         if (!s->any_generic) return HW_OK;
@@ -323,6 +333,163 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
     }
     HIP_TRY(hw_launch_generic(s->d, s->fp64, descs, prefix, np, s->total_cells[phase], s->ops, s->lds,
                               s->grid, st));
+    return HW_OK;
+}
+
+// Dense-kernel arguments of problem i for half step k = phase * 2 + slot parity.
+DenseArgs dense_args(const hw_solver* s, int k, int i)
+{
+    const int np = (int)s->probs.size();
+    const ProblemDesc& D = s->h_descs[(size_t)k * np + i];
+    DenseArgs a;
+    for (int t = 0; t < 3; ++t) {
+        a.ext_from[t] = D.ext_from[t];
+        a.ext_to[t] = D.ext_to[t];
+        a.bc[t] = D.bc[t];
+    }
+    a.to_grid = D.to_grid;
+    a.u_in = D.u_in;
+    a.v_in = D.v_in;
+    a.u_old = D.u_old;
+    a.u_out = D.u_out;
+    a.v_out = D.v_out;
+    a.G = s->dense_G[i];
+    a.n_cells = D.n_out;
+    a.tile_x = s->dense_tx.empty() ? 64 : s->dense_tx[i];
+    return a;
+}
+
+// Tiles of tx x (256 / tx) cells covering the grid written in `phase` by the members of
+// a class (member j is problem probs[j]).
+void class_tiles(const hw_solver* s, int phase, const std::vector<int>& probs, int tx, std::vector<int4>& tiles)
+{
+    const int np = (int)s->probs.size();
+    tiles.clear();
+    for (int j = 0; j < (int)probs.size(); ++j) {
+        const ProblemDesc& D = s->h_descs[(size_t)(phase * 2) * np + probs[j]];
+        const int h = 256 / tx;
+        for (int y = 0; y < D.ext_to[1]; y += h)
+            for (int x = 0; x < D.ext_to[0]; x += tx) tiles.push_back(make_int4(j, x, y, 0));
+    }
+}
+
+// Time `launch` (one warm-up call, three timed) on a private stream; microseconds per call.
+template <typename F>
+double time_launches(F launch)
+{
+    hipStream_t ts = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double us = -1.0;
+    if (hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+        bool ok = launch(ts) == hipSuccess && hipEventRecord(e0, ts) == hipSuccess;
+        for (int r = 0; ok && r < 3; ++r) ok = launch(ts) == hipSuccess;
+        ok = ok && hipEventRecord(e1, ts) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) us = 1e3 * ms / 3.0;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ts) (void)hipStreamDestroy(ts);
+    return us;
+}
+
+// zero every state buffer of problem i (before timing launches on it)
+void zero_state(hw_solver* s, int i)
+{
+    const Prob& P = s->probs[i];
+    for (int g = 0; g < 2; ++g) {
+        for (int sl = 0; sl < 2; ++sl)
+            if (P.u[g][sl]) (void)hipMemset(P.u[g][sl], 0, (size_t)P.nodes[g] * P.Mu * s->elem);
+        if (P.v[g]) (void)hipMemset(P.v[g], 0, (size_t)P.nodes[g] * P.Mv * s->elem);
+    }
+}
+
+const std::vector<int> kTileCandidates = {16, 32, 64, 128};
+
+// Tile width of the single-problem dense kernel for 2-D problem i (autotuned).
+void tune_dense_single(hw_solver* s, int i)
+{
+    const Prob& P = s->probs[i];
+    if (P.p.d != 2 || !hw_tune_enabled()) return;
+    zero_state(s, i);
+    const bool cons = P.p.method == HW_CONSERVATIVE;
+    auto time_us = [&](int cand) {
+        DenseArgs a = dense_args(s, 0, i);
+        a.tile_x = cand;
+        return time_launches([&](hipStream_t ts) { return hw_launch_dense(a, 2, P.p.m, cons, s->fp64, ts); });
+    };
+    s->dense_tx[i] = hw_tune_choose("dense", 2, P.p.m, P.p.method, s->fp64, hw_tune_size_class(P.nodes[1]),
+                                    kTileCandidates, time_us);
+}
+
+// The batched 2-D path: the problems grouped by (m, method); per class the dense
+// kernel's descriptors of every member for the four (phase, slot parity) combinations,
+// a tile width timed by the autotuner on the class's largest member, and the work lists.
+hw_status setup_batch_classes(hw_solver* s)
+{
+    const int np = (int)s->probs.size();
+    std::map<std::pair<int, int>, int> cls_of;
+    for (int i = 0; i < np; ++i) {
+        const auto key = std::make_pair(s->probs[i].p.m, s->probs[i].p.method == HW_CONSERVATIVE ? 1 : 0);
+        auto it = cls_of.find(key);
+        if (it == cls_of.end()) {
+            it = cls_of.emplace(key, (int)s->bclasses.size()).first;
+            s->bclasses.emplace_back();
+            s->bclasses.back().m = key.first;
+            s->bclasses.back().cons = key.second != 0;
+        }
+        s->bclasses[it->second].probs.push_back(i);
+    }
+    for (auto& C : s->bclasses) {
+        const int n = (int)C.probs.size();
+        std::vector<DenseArgs> ha((size_t)4 * n);
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < n; ++j) ha[(size_t)k * n + j] = dense_args(s, k, C.probs[j]);
+        if (hipMalloc((void**)&C.args, ha.size() * sizeof(DenseArgs)) != hipSuccess)
+            return fail(HW_ENOMEM, "batch descriptor allocation failed");
+        auto upload_args = [&](int tx) {
+            for (auto& a : ha) a.tile_x = tx;
+            return hipMemcpy(C.args, ha.data(), ha.size() * sizeof(DenseArgs), hipMemcpyHostToDevice);
+        };
+        if (hw_tune_enabled()) {
+            int rep = 0;  // member with the most cells
+            for (int j = 1; j < n; ++j)
+                if (s->probs[C.probs[j]].nodes[1] > s->probs[C.probs[rep]].nodes[1]) rep = j;
+            zero_state(s, C.probs[rep]);
+            int4* dt = nullptr;
+            auto time_us = [&](int cand) -> double {
+                std::vector<int4> tl;
+                class_tiles(s, 0, std::vector<int>{C.probs[rep]}, cand, tl);
+                for (auto& t : tl) t.x = rep;  // the list names the member's own descriptor
+                if (upload_args(cand) != hipSuccess) return -1.0;
+                if (dt) (void)hipFree(dt);
+                dt = nullptr;
+                if (hipMalloc((void**)&dt, tl.size() * sizeof(int4)) != hipSuccess ||
+                    hipMemcpy(dt, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+                    return -1.0;
+                const int grid = (int)std::min<size_t>(tl.size(), 2048);
+                return time_launches([&](hipStream_t ts) {
+                    return hw_launch_dense_list(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64, ts);
+                });
+            };
+            C.tx = hw_tune_choose("dense_list", 2, C.m, C.cons ? HW_CONSERVATIVE : HW_DISS_FULL, s->fp64,
+                                  hw_tune_size_class(s->probs[C.probs[rep]].nodes[1]), kTileCandidates, time_us);
+            if (dt) (void)hipFree(dt);
+        }
+        if (upload_args(C.tx) != hipSuccess) return fail(HW_EHIP, "batch descriptor upload failed");
+        for (int ph = 0; ph < 2; ++ph) {
+            std::vector<int4> tl;
+            class_tiles(s, ph, C.probs, C.tx, tl);
+            C.ntiles[ph] = (int)tl.size();
+            if (hipMalloc((void**)&C.tiles[ph], std::max<size_t>(tl.size(), 1) * sizeof(int4)) != hipSuccess)
+                return fail(HW_ENOMEM, "batch work list allocation failed");
+            if (!tl.empty() &&
+                hipMemcpy(C.tiles[ph], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+                return fail(HW_EHIP, "batch work list upload failed");
+        }
+        C.grid = (int)std::min(std::max(C.ntiles[0], C.ntiles[1]), 2048);
+    }
     return HW_OK;
 }
 
@@ -355,6 +522,8 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             if (!hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision))
                 return fail(HW_EUNSUPPORTED, "no dense kernel for d=%d m=%d method=%d precision=%d (problem %d)",
                             ps[i].d, ps[i].m, ps[i].method, ps[i].precision, i);
+    if (p0.kernel == HW_KERNEL_BATCH && (p0.d != 2 || p0.precision == HW_BF16))
+        return fail(HW_EUNSUPPORTED, "the batched kernel serves 2-D problems in FP64 or FP32");
     if (p0.kernel == HW_KERNEL_SPLIT && (count != 1 || p0.method == HW_CONSERVATIVE))
         return fail(HW_EUNSUPPORTED, "the two-kernel form serves single dissipative problems");
     if (p0.precision == HW_BF16 &&
@@ -378,12 +547,21 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     s->use_cmap = cmap_ok && (p0.kernel == HW_KERNEL_COMPOSED || p0.kernel == HW_KERNEL_AUTO);
     s->use_tiled = tiled_ok && p0.kernel != HW_KERNEL_GENERIC && p0.kernel != HW_KERNEL_DENSE && !s->split &&
                    !s->use_cmap && p0.taylor_stages == 0;
-    if (!s->use_tiled && !s->use_cmap && !s->split && (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE)) {
+    // batches of 2-D problems: one persistent launch per half step over all of them
+    s->use_batch2d = p0.d == 2 && p0.precision != HW_BF16 &&
+                     (p0.kernel == HW_KERNEL_BATCH || (p0.kernel == HW_KERNEL_AUTO && count > 1));
+    if (s->use_batch2d) {
+        // every problem of a batched 2-D solver has its cell matrix (conservative m = 6
+        // included: the list kernel serves it)
+        s->dense.assign(count, 1);
+    } else if (!s->use_tiled && !s->use_cmap && !s->split &&
+               (p0.kernel == HW_KERNEL_AUTO || p0.kernel == HW_KERNEL_DENSE)) {
         s->dense.assign(count, 0);
         for (int i = 0; i < count; ++i)
             s->dense[i] = hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision) ? 1 : 0;
         if (std::find(s->dense.begin(), s->dense.end(), 1) == s->dense.end()) s->dense.clear();
     }
+    s->dense_tx.assign(count, 64);
     s->probs.resize(count);
     auto cleanup = [&](hw_status st) {
         hw_destroy(s);
@@ -576,6 +754,14 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         if (hipMemcpy(s->gen_prefix, gp.data(), gp.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(HW_EHIP, "descriptor upload failed"));
     }
+    if (s->use_batch2d) {
+        hw_status r = setup_batch_classes(s);
+        if (r != HW_OK) return cleanup(r);
+        s->dense.clear();  // the classes' launches replace the per-problem dense launches
+    } else {
+        for (int i = 0; i < count; ++i)
+            if (!s->dense.empty() && s->dense[i]) tune_dense_single(s, i);
+    }
     if (s->use_cmap && hw_cmap3d_tables_create(s->h_descs[0], s->fp64, &s->cmap_tables) != hipSuccess)
         return cleanup(fail(HW_EHIP, "composed-map table setup failed"));
     if (s->use_tiled) {
@@ -654,6 +840,13 @@ extern "C" {
 
 const char* hw_last_error(void) { return g_err.c_str(); }
 
+const char* hw_tuning_report(void)
+{
+    thread_local std::string text;
+    text = hw_tune_report_text();
+    return text.c_str();
+}
+
 hw_status hw_create(const hw_problem* p, hw_solver** out) { return create_impl(p, 1, out); }
 
 hw_status hw_batch_create(const hw_problem* ps, int count, hw_solver** out)
@@ -686,6 +879,11 @@ void hw_destroy(hw_solver* s)
     if (s->tiled_tables) hw_tiled_tables_destroy(s->tiled_tables);
     if (s->cmap_tables) (void)hipFree(s->cmap_tables);
     for (void* g : s->dense_alloc) (void)hipFree(g);
+    for (auto& C : s->bclasses) {
+        if (C.args) (void)hipFree(C.args);
+        for (int ph = 0; ph < 2; ++ph)
+            if (C.tiles[ph]) (void)hipFree(C.tiles[ph]);
+    }
     if (s->gen_prefix) (void)hipFree(s->gen_prefix);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
@@ -975,6 +1173,77 @@ hw_status hw_energy_noalloc(hw_solver* s, double* e_out_device, void* stream)
     HIP_TRY(hw_launch_energy_noalloc(s->d, s->fp64, E[0], gsz[0], E[1], gsz[1], s->dops, e_out_device,
                                      (hipStream_t)stream));
     return HW_OK;
+}
+
+hw_status hw_probe_stream_triad(int64_t n, double* gbs_out)
+{
+    if (!gbs_out || n < 1024 || (n & 1)) return fail(HW_EINVAL, "need an even n >= 1024 and an output pointer");
+    double *a = nullptr, *b = nullptr, *c = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hw_status r = HW_OK;
+    const size_t bytes = (size_t)n * sizeof(double);
+    if (hipMalloc((void**)&a, bytes) != hipSuccess || hipMalloc((void**)&b, bytes) != hipSuccess ||
+        hipMalloc((void**)&c, bytes) != hipSuccess) {
+        r = fail(HW_ENOMEM, "triad arrays allocation failed");
+    } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        r = fail(HW_EHIP, "triad stream setup failed");
+    } else {
+        const int reps = 10;
+        bool ok = hipMemsetAsync(b, 0, bytes, st) == hipSuccess && hipMemsetAsync(c, 0, bytes, st) == hipSuccess;
+        for (int k = 0; ok && k < 2; ++k) ok = hw_probe_triad_launch(a, b, c, n, st) == hipSuccess;
+        ok = ok && hipEventRecord(e0, st) == hipSuccess;
+        for (int k = 0; ok && k < reps; ++k) ok = hw_probe_triad_launch(a, b, c, n, st) == hipSuccess;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f)
+            *gbs_out = 24.0 * (double)n * reps / (ms * 1e-3) / 1e9;
+        else
+            r = fail(HW_EHIP, "triad probe failed");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (c) (void)hipFree(c);
+    return r;
+}
+
+hw_status hw_probe_mfma(int precision, double* tflops_out)
+{
+    if (!tflops_out || (precision != HW_FP64 && precision != HW_FP32))
+        return fail(HW_EINVAL, "precision must be HW_FP64 or HW_FP32, output non-null");
+    const bool fp64 = precision == HW_FP64;
+    const int groups = 256 * 8, iters = 4096, chains = 8;
+    void* sink = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hw_status r = HW_OK;
+    if (hipMalloc(&sink, (size_t)groups * 256 * 8) != hipSuccess) {
+        r = fail(HW_ENOMEM, "probe sink allocation failed");
+    } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        r = fail(HW_EHIP, "probe stream setup failed");
+    } else {
+        bool ok = hw_probe_mfma_launch(fp64, sink, groups, iters, st) == hipSuccess;
+        ok = ok && hipEventRecord(e0, st) == hipSuccess;
+        ok = ok && hw_probe_mfma_launch(fp64, sink, groups, iters, st) == hipSuccess;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
+            const double flops = (double)groups * 4 * iters * chains * 2048.0;
+            *tflops_out = flops / (ms * 1e-3) / 1e12;
+        } else {
+            r = fail(HW_EHIP, "MFMA probe failed");
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (sink) (void)hipFree(sink);
+    return r;
 }
 
 } // extern "C"

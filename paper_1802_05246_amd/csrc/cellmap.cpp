@@ -12,6 +12,7 @@
 // truncation of the series).
 #include "hw_kernels.h"
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>

@@ -7,6 +7,8 @@
 #include "hw_device.h"
 #include "../../include/hermite_wave.h"
 
+#include <functional>
+#include <string>
 #include <vector>
 
 size_t hw_generic_lds_bytes(int d, int m, int variant, int elem_size);
@@ -51,13 +53,20 @@ struct DenseArgs {
     void* v_out;       // dissipative
     const void* G;     // rows of corner 0 of the cell matrix: [n_in / 2^d][n_out], input-major
     int64_t n_cells;
+    int tile_x = 64;   // 2-D: cells along x of a workgroup's tile of 256 (a divisor of 256)
 };
 bool hw_dense_supported(int d, int m, int method, int precision);
+
+
 // The descriptor's time-sum weights (tau, lam2, F, cuQ, cuR, cvQ, cvR) for problem p with
 // cell widths h (cellmap.cpp); the same tables serve every kernel.
 void hw_fill_weights(const hw_problem& p, const double h[3], ProblemDesc& D);
 void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
+// Persistent launch over the tiles of many 2-D problems of one (m, method): probs[i] are
+// their descriptors, tiles {problem i, x0, y0, 0} of tile_x x (256 / tile_x) cells.
+hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
+                                bool fp64, hipStream_t st);
 
 // Composed-map MFMA kernel for the 3-D dissipative method, m = 3 (kernel_cmap3d.hip):
 // the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are
@@ -72,3 +81,16 @@ bool hw_tiled_supported(int d, int m, int method, int precision);
 hipError_t hw_tiled_tables_create(int precision, const double lam2[3], double tau, void** out);
 void hw_tiled_tables_destroy(void* tables);
 hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st);
+
+// Autotuner (tune.cpp): the candidate with the smallest time_us(candidate) for a key,
+// timed once per process (or read from the HW_TUNE_CACHE file) and cached.
+bool hw_tune_enabled();
+int hw_tune_size_class(int64_t cells);
+int hw_tune_choose(const char* kernel, int d, int m, int method, bool fp64, int size_class,
+                   const std::vector<int>& candidates, const std::function<double(int)>& time_us);
+std::string hw_tune_report_text();
+
+// Peak probes (probes.hip): STREAM triad over FP64 arrays of n elements; independent MFMA
+// chains over `groups` workgroups of 256 threads, `iters` rounds of 8 products per wave.
+hipError_t hw_probe_triad_launch(double* a, const double* b, const double* c, int64_t n, hipStream_t st);
+hipError_t hw_probe_mfma_launch(bool fp64, void* sink, int groups, int iters, hipStream_t st);

@@ -24,24 +24,14 @@ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 __device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
 
 template <typename T, int D, int MU, bool CONS>
-__global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
+__device__ void dense_cell(const DenseArgs& a, int64_t cell)
 {
     constexpr int MV = CONS ? 0 : MU - 1;
     constexpr int NU = cpow(MU, D), NV = CONS ? 0 : cpow(MV, D);
     constexpr int NO = CONS ? NU : NU + NV;
-    // 1-D: consecutive cells per workgroup; 2-D: a tile of 64 x 4 cells, so that the
-    // rows of corner nodes a workgroup reads are shared by its own cells
-    int64_t cell;
-    if constexpr (D == 1) {
-        cell = (int64_t)blockIdx.x * DENSE_BLOCK + threadIdx.x;
-        if (cell >= a.n_cells) return;
-    } else {
-        const int tiles_x = (a.ext_to[0] + 63) / 64;
-        const int x = (blockIdx.x % tiles_x) * 64 + (threadIdx.x & 63);
-        const int y = (blockIdx.x / tiles_x) * (DENSE_BLOCK / 64) + (threadIdx.x >> 6);
-        if (x >= a.ext_to[0] || y >= a.ext_to[1]) return;
-        cell = x + (int64_t)a.ext_to[0] * y;
-    }
+    // the old level is read before the products (its latency overlaps them) unless the
+    // registers it would hold are needed more by the accumulators (conservative m = 6)
+    constexpr bool EARLY_OLD = CONS && NU <= 36;
 
     // corners: input node per dimension and side, and whether it is a ghost image
     int node[2][2];
@@ -86,8 +76,8 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
     const T* __restrict__ uin = static_cast<const T*>(a.u_in);
     const T* __restrict__ vin = static_cast<const T*>(a.v_in);
     // conservative: the old level is read first, so that its latency overlaps the products
-    T uold[CONS ? NU : 1];
-    if constexpr (CONS) {
+    T uold[EARLY_OLD ? NU : 1];
+    if constexpr (EARLY_OLD) {
 #pragma unroll
         for (int o = 0; o < NU; ++o) uold[o] = static_cast<const T*>(a.u_old)[cell * NU + o];
     }
@@ -166,9 +156,13 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
     if constexpr (!CONS) block(vin, std::integral_constant<int, MV>{}, NU);
 
     T* __restrict__ uo = static_cast<T*>(a.u_out) + cell * NU;
-    if constexpr (CONS) {
+    if constexpr (EARLY_OLD) {
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - uold[o];
+    } else if constexpr (CONS) {
+        const T* __restrict__ old = static_cast<const T*>(a.u_old) + cell * NU;
+#pragma unroll
+        for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - old[o];
     } else {
         T* __restrict__ vo = static_cast<T*>(a.v_out) + cell * NV;
 #pragma unroll
@@ -178,14 +172,99 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
     }
 }
 
+// one problem: 1-D consecutive cells per workgroup; 2-D tiles of TX x (256 / TX) cells
+// (TX = a.tile_x), so that the rows of corner nodes a workgroup reads are shared by its
+// own cells
+template <typename T, int D, int MU, bool CONS>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
+{
+    int64_t cell;
+    if constexpr (D == 1) {
+        cell = (int64_t)blockIdx.x * DENSE_BLOCK + threadIdx.x;
+        if (cell >= a.n_cells) return;
+    } else {
+        const int tx = a.tile_x;
+        const int tiles_x = (a.ext_to[0] + tx - 1) / tx;
+        const int x = (blockIdx.x % tiles_x) * tx + (int)threadIdx.x % tx;
+        const int y = (blockIdx.x / tiles_x) * (DENSE_BLOCK / tx) + (int)threadIdx.x / tx;
+        if (x >= a.ext_to[0] || y >= a.ext_to[1]) return;
+        cell = x + (int64_t)a.ext_to[0] * y;
+    }
+    dense_cell<T, D, MU, CONS>(a, cell);
+}
+
+// many 2-D problems of one (m, method): a persistent grid walks a work list of tiles
+// (problem, x0, y0) of TX x (256 / TX) cells (TX = that problem's tile_x).  Workgroup b
+// runs on XCD b mod 8 and takes a contiguous part of the list (the tiles of a problem
+// are contiguous), so tiles that share halo rows of input nodes share that XCD's L2.
+template <typename T, int MU, bool CONS>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense_list(const DenseArgs* __restrict__ probs,
+                                                            const int4* __restrict__ tiles, int n_tiles)
+{
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int nx = nb < 8 ? nb : 8;
+    const int xcd = b % nx, slot = b / nx;
+    const int per_xcd = (nb + nx - 1 - xcd) / nx;
+    const int chunk = (n_tiles + nx - 1) / nx;
+    const int t0 = xcd * chunk, t1 = min(n_tiles, t0 + chunk);
+    for (int t = t0 + slot; t < t1; t += per_xcd) {
+        // the tile and its problem are the same for the whole workgroup: read them as
+        // wave-uniform values, so that the descriptor and the cell map G stay on the scalar
+        // unit as in the single-problem kernel
+        const int4 tl = tiles[t];
+        const int pi = __builtin_amdgcn_readfirstlane(tl.x);
+        const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
+        const DenseArgs a = probs[pi];
+        const int tx = a.tile_x;
+        const int x = x0 + (int)threadIdx.x % tx;
+        const int y = y0 + (int)threadIdx.x / tx;
+        if (x < a.ext_to[0] && y < a.ext_to[1]) dense_cell<T, 2, MU, CONS>(a, x + (int64_t)a.ext_to[0] * y);
+    }
+}
+
 template <typename T, int D, int MU, bool CONS>
 hipError_t launch(const DenseArgs& a, hipStream_t st)
 {
+    const int tx = a.tile_x;
     const int64_t blocks = D == 1 ? (a.n_cells + DENSE_BLOCK - 1) / DENSE_BLOCK
-                                  : (int64_t)((a.ext_to[0] + 63) / 64) *
-                                        ((a.ext_to[1] + DENSE_BLOCK / 64 - 1) / (DENSE_BLOCK / 64));
+                                  : (int64_t)((a.ext_to[0] + tx - 1) / tx) *
+                                        ((a.ext_to[1] + DENSE_BLOCK / tx - 1) / (DENSE_BLOCK / tx));
     hipLaunchKernelGGL((k_dense<T, D, MU, CONS>), dim3((unsigned)blocks), dim3(DENSE_BLOCK), 0, st, a);
     return hipGetLastError();
+}
+
+template <typename T, int MU, bool CONS>
+hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_dense_list<T, MU, CONS>), dim3(grid), dim3(DENSE_BLOCK), 0, st, probs, tiles, n_tiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
+                         hipStream_t st)
+{
+    if (cons) {
+        switch (m) {
+        case 0: return launch_list<T, 1, true>(probs, tiles, n_tiles, grid, st);
+        case 1: return launch_list<T, 2, true>(probs, tiles, n_tiles, grid, st);
+        case 2: return launch_list<T, 3, true>(probs, tiles, n_tiles, grid, st);
+        case 3: return launch_list<T, 4, true>(probs, tiles, n_tiles, grid, st);
+        case 4: return launch_list<T, 5, true>(probs, tiles, n_tiles, grid, st);
+        case 5: return launch_list<T, 6, true>(probs, tiles, n_tiles, grid, st);
+        case 6: return launch_list<T, 7, true>(probs, tiles, n_tiles, grid, st);
+        }
+    } else {
+        switch (m) {
+        case 1: return launch_list<T, 2, false>(probs, tiles, n_tiles, grid, st);
+        case 2: return launch_list<T, 3, false>(probs, tiles, n_tiles, grid, st);
+        case 3: return launch_list<T, 4, false>(probs, tiles, n_tiles, grid, st);
+        case 4: return launch_list<T, 5, false>(probs, tiles, n_tiles, grid, st);
+        case 5: return launch_list<T, 6, false>(probs, tiles, n_tiles, grid, st);
+        case 6: return launch_list<T, 7, false>(probs, tiles, n_tiles, grid, st);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -238,9 +317,19 @@ hipError_t dispatch(const DenseArgs& a, int d, int m, bool cons, hipStream_t st)
 
 } // namespace
 
+hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
+                                bool fp64, hipStream_t st)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    if (grid < 1) grid = 1;
+    return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, grid, m, cons, st)
+                : dispatch_list<float>(probs, tiles, n_tiles, grid, m, cons, st);
+}
+
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
 {
     if (!a.G || a.n_cells < 0) return hipErrorInvalidValue;
+    if (d == 2 && (a.tile_x < 1 || a.tile_x > DENSE_BLOCK || DENSE_BLOCK % a.tile_x)) return hipErrorInvalidValue;
     if (a.n_cells == 0) return hipSuccess;
     for (int i = 0; i < d; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;

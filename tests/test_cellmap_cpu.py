@@ -28,8 +28,9 @@ def dump(tmp_path_factory):
                            "-o", exe])
 
     def run(d, m, method, c, dt, h, stages):
-        out = subprocess.check_output([exe, str(d), str(m), str(method), repr(c), repr(dt), repr(h[0]),
-                                       repr(h[1] if len(h) > 1 else 1.0), str(stages)], text=True).split()
+        args = [exe, str(d), str(m), str(method), repr(c), repr(dt), repr(h[0]),
+                repr(h[1] if len(h) > 1 else 1.0), str(stages)]
+        out = subprocess.check_output(args, text=True).split()
         n_in, n_out = int(out[0]), int(out[1])
         return np.array(out[2:], dtype=np.float64).reshape(n_in, n_out)
     return run
@@ -89,3 +90,21 @@ def test_cell_matrix_reflection_symmetry(dump, d, m, method, stages):
             for i in range(d):
                 e += ((c >> i) & 1) * (a_par[i] + lidx[i])
             assert np.array_equal(G[c * ni + l], np.where(e % 2 == 1, -G[l], G[l]))
+
+
+@pytest.mark.parametrize("n_tiles", [1, 5, 8, 9, 63, 1000, 4097])
+@pytest.mark.parametrize("grid", [1, 3, 8, 13, 2048])
+def test_batch_kernel_walk_covers_every_tile_once(n_tiles, grid):
+    """The persistent batched dense kernel's XCD-aware walk (workgroup b takes the chunk of
+    XCD b mod 8, stepping by the number of workgroups on that chunk; the index arithmetic
+    of k_dense_list) visits every tile exactly once."""
+    seen = np.zeros(n_tiles, dtype=np.int64)
+    nx = min(grid, 8)
+    chunk = (n_tiles + nx - 1) // nx
+    for b in range(grid):
+        xcd, slot = b % nx, b // nx
+        per = (grid + nx - 1 - xcd) // nx
+        t0, t1 = xcd * chunk, min(n_tiles, xcd * chunk + chunk)
+        for t in range(t0 + slot, t1, per):
+            seen[t] += 1
+    assert (seen == 1).all()

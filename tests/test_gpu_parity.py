@@ -559,3 +559,68 @@ def test_tiled_bf16_operands_match_oracle(n, bc):
     tol = 20.0 * BF16_U * n_half
     _log(f"[bf16] n={n} bc={bc} joint rel err {err:.3e} (tol {tol:.3g})")
     assert err <= tol
+
+
+BATCH_KERNEL_CASES = [
+    (m, meth, n, bc)
+    for m, meth, n, bc in [
+        (1, W.DISS_FULL, [9, 7], [W.PERIODIC, W.DIRICHLET]),
+        (2, W.DISS_FULL, [6, 11], [W.NEUMANN, W.PERIODIC]),
+        (3, W.DISS_SIMPLE, [13, 5], [W.DIRICHLET, W.NEUMANN]),
+        (4, W.DISS_FULL, [7, 7], [W.PERIODIC, W.PERIODIC]),
+        (5, W.DISS_FULL, [5, 6], [W.DIRICHLET, W.DIRICHLET]),
+        (6, W.DISS_FULL, [4, 5], [W.NEUMANN, W.NEUMANN]),
+        (0, W.CONSERVATIVE, [9, 8], [W.DIRICHLET, W.PERIODIC]),
+        (2, W.CONSERVATIVE, [70, 3], [W.PERIODIC, W.NEUMANN]),
+        (4, W.CONSERVATIVE, [6, 9], [W.DIRICHLET, W.DIRICHLET]),
+        (6, W.CONSERVATIVE, [4, 4], [W.NEUMANN, W.PERIODIC]),
+    ]
+]
+
+
+@pytest.mark.parametrize("case", BATCH_KERNEL_CASES, ids=lambda c: f"m{c[0]}-meth{c[1]}-n{c[2][0]}x{c[2][1]}")
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_kernel_single_problem_matches_oracle(case, prec):
+    """The batched 2-D path (persistent dense launch over a tile work list) on one problem
+    (ragged tiles, every wall type, both methods, m = 0..6): six half steps against the
+    oracle."""
+    B = _B()
+    m, meth, n, bc = case
+    spec = W.make_spec(2, m, n, 0.0, [1.0, 0.9], 1.1, cfl=0.9, bc=bc, method=meth)
+    u, w = _state(spec, 300 + m + meth)
+    s = B.Solver(spec, precision=B.HW_FP64 if prec == "fp64" else B.HW_FP32, kernel=B.HW_KERNEL_BATCH)
+    s.set_state(u, w)
+    u_in, w_in = (x.cpu().numpy() for x in s.get_state())
+    s.half_steps(6)
+    gu, gw = (x.cpu().numpy() for x in s.get_state())
+    s.close()
+    ou, ow = oracle_reference_run(spec, u_in, w_in, 6)
+    err, tol = state_err(spec, gu, gw, ou, ow, prec, 6)
+    _log(f"[batch kernel] m={m} meth={meth} n={n} {prec}: rel-L2 {err:.3e} (tol {tol:g})")
+    assert err <= tol
+
+
+def test_batch_kernel_graph_equals_plain_launches_and_reports_tuning():
+    """A mixed batch through the batched path (one persistent launch per (m, method)
+    class): the captured step loop equals plain launches bit for bit, and the
+    autotuner's choices are reported."""
+    B = _B()
+    specs = [W.make_spec(2, m, [20 + 7 * m, 11 + 3 * m], 0.0, 1.0, 0.6 + 0.2 * m, cfl=0.8,
+                         bc=[W.PERIODIC, W.DIRICHLET][m % 2], method=[W.DISS_FULL, W.CONSERVATIVE][m % 2])
+             for m in range(2, 7)]
+    states = [_state(sp, 500 + i) for i, sp in enumerate(specs)]
+    a = B.Solver(problems=specs, precision=B.HW_FP32)
+    b = B.Solver(problems=specs, precision=B.HW_FP32)
+    for s in (a, b):
+        for i, (u, w) in enumerate(states):
+            s.set_state(u, w, i=i)
+    a.advance(3)
+    b.half_steps(6)
+    for i in range(len(specs)):
+        ga, gb = a.get_state(i), b.get_state(i)
+        assert torch.equal(ga[0], gb[0]) and torch.equal(ga[1], gb[1])
+    rep = B.hw_tuning_report()
+    _log("[tuning]\n" + rep)
+    assert "dense_list" in rep
+    a.close()
+    b.close()

@@ -41,7 +41,7 @@ def test_validation_codes():
     p.dt = 1.01 * min(good.h(0), good.h(1)) / good.c
     assert _err(p) == B.HW_ECFL
     for field, val in [("d", 0), ("d", 4), ("m", 0), ("m", 7), ("method", 5), ("precision", 9),
-                       ("kernel", 6), ("taylor_stages", -1)]:
+                       ("kernel", 7), ("taylor_stages", -1)]:
         p = B.make_problem(good)
         setattr(p, field, val)
         assert _err(p) == B.HW_EINVAL, field
@@ -57,6 +57,11 @@ def test_validation_codes():
     p = B.make_problem(W.make_spec(2, 3, [6, 6], cfl=0.9), precision=B.HW_BF16, kernel=B.HW_KERNEL_DENSE)
     assert _err(p) == B.HW_EUNSUPPORTED
     p = B.make_problem(W.make_spec(2, 6, [6, 6], cfl=0.9, method=W.CONSERVATIVE), kernel=B.HW_KERNEL_DENSE)
+    assert _err(p) == B.HW_EUNSUPPORTED
+    # the batched kernel serves 2-D problems in FP64 / FP32 only
+    p = B.make_problem(W.make_spec(3, 2, [4, 4, 4], cfl=0.9), kernel=B.HW_KERNEL_BATCH)
+    assert _err(p) == B.HW_EUNSUPPORTED
+    p = B.make_problem(W.make_spec(2, 2, [6, 6], cfl=0.9), precision=B.HW_BF16, kernel=B.HW_KERNEL_BATCH)
     assert _err(p) == B.HW_EUNSUPPORTED
     p = B.make_problem(good)
     p.bc[0] = 7
