@@ -72,14 +72,24 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
     // (-1)^(sum_i s_i (a_i + l_i)) times corner 0's entry, so the corners are first
     // combined into the 2^d sums S_p = sum_c (-1)^(p . s) x_c and each entry of G
     // multiplies the one S_p whose parities p = a + l (mod 2) it needs
-    const T* __restrict__ G = static_cast<const T*>(a.G);
-    const T* __restrict__ uin = static_cast<const T*>(a.u_in);
-    const T* __restrict__ vin = static_cast<const T*>(a.v_in);
+    // G is read through the constant address space: its loads are wave-uniform and the
+    // kernel never writes it, so they go through the scalar unit also where the pointer
+    // itself comes from memory (the batch kernel's per-problem descriptors), not only
+    // from a kernel argument
+    typedef const __attribute__((address_space(4))) T* ConstPtr;
+    const ConstPtr G = reinterpret_cast<ConstPtr>(reinterpret_cast<uintptr_t>(a.G));
+    // the node arrays are global memory: said explicitly, so that pointers read from
+    // memory (batch descriptors) load and store as global, not generic, accesses
+    typedef const __attribute__((address_space(1))) T* GIn;
+    typedef __attribute__((address_space(1))) T* GOut;
+    const GIn uin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
+    const GIn vin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
+    const GIn uold_in = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old));
     // conservative: the old level is read first, so that its latency overlaps the products
     T uold[EARLY_OLD ? NU : 1];
     if constexpr (EARLY_OLD) {
 #pragma unroll
-        for (int o = 0; o < NU; ++o) uold[o] = static_cast<const T*>(a.u_old)[cell * NU + o];
+        for (int o = 0; o < NU; ++o) uold[o] = uold_in[cell * NU + o];
     }
     T acc[NO];
 #pragma unroll
@@ -106,7 +116,7 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
         return (i == 0 ? oo % md : (oo / md) % md) & 1;
     };
     // one block (u: extent MU per dimension, v: MV) of the corners against G
-    auto block = [&](const T* __restrict__ base, auto md_tag, int in0) {
+    auto block = [&](const GIn base, auto md_tag, int in0) {
         constexpr int MD = decltype(md_tag)::value;
         constexpr int NB = cpow(MD, D);
         // input l = lx + MD ly; ly_odd: the y parity of l when it is not known at compile time
@@ -132,7 +142,7 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
                 S[2] = ly_odd ? p + r : p - r;
                 S[3] = ly_odd ? q + t : q - t;
             }
-            const T* g = G + (int64_t)(in0 + l) * NO;
+            const ConstPtr g = G + (int64_t)(in0 + l) * NO;
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
                 const int px = (opar(o, 0) + lx) & 1;
@@ -155,16 +165,16 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
     block(uin, std::integral_constant<int, MU>{}, 0);
     if constexpr (!CONS) block(vin, std::integral_constant<int, MV>{}, NU);
 
-    T* __restrict__ uo = static_cast<T*>(a.u_out) + cell * NU;
+    const GOut uo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + cell * NU;
     if constexpr (EARLY_OLD) {
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - uold[o];
     } else if constexpr (CONS) {
-        const T* __restrict__ old = static_cast<const T*>(a.u_old) + cell * NU;
+        const GIn old = uold_in + cell * NU;
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - old[o];
     } else {
-        T* __restrict__ vo = static_cast<T*>(a.v_out) + cell * NV;
+        const GOut vo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + cell * NV;
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = acc[o];
 #pragma unroll
