@@ -40,16 +40,24 @@ namespace {
 constexpr int CX = 4;                         // cells along x of a workgroup's column
 constexpr int NXL = CX + 1;
 constexpr int NI = 91;                        // inputs per node: u 64 + v 27
-constexpr int NDP = 93;                       // LDS node stride (odd: spreads the banks)
 constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded to 92)
 constexpr int TL = 92;                        // stride of one butterfly sum over l
-// cell stride of the butterfly sums [p][k] (k: the K position of the input in the
-// products): with 16 cells of a product group at this stride and the 4 positions of a
-// K-step (k = 4 ks + 0..3) in the four residues mod 4, the operand reads of a wave touch
-// every LDS bank once (FP32: stride 4 x odd; FP64, two banks per value, once per half
-// wave: stride 2 x odd)
+// LDS strides, chosen for its 32 banks of 4 bytes, which serve a 32-bit access of a wave
+// 32 lanes at a time and a 64-bit access 16 lanes at a time.  Every LDS pass of the
+// kernel puts the 16 cells of a product group (4 x 4 in x, y) on distinct banks:
+//   * nodes: node (x, y) of a layer at x SX + y SY (its inputs contiguous); FP32:
+//     SX = 2, SY = 8 (mod 32), so that a corner's 16 nodes fall on the 16 even banks
+//     (2 (x + 4 y) mod 32) and the second input of the pass, whose index has the other
+//     parity, on the odd ones; FP64: SX = 1, SY = 4 (mod 16), one input per pass;
+//   * butterfly sums [cell][p][k] (k: the K position of the input): cell stride = 2
+//     (mod 32) in FP32 (K positions 4 ks and 4 ks + 1 of a product's operand pass on the
+//     even and odd banks), odd in FP64
 template <typename T>
-constexpr int tsz() { return sizeof(T) == 4 ? 740 : 738; }
+constexpr int ndx() { return sizeof(T) == 4 ? 98 : 97; }
+template <typename T>
+constexpr int ndy() { return sizeof(T) == 4 ? 520 : 500; }
+template <typename T>
+constexpr int tsz() { return sizeof(T) == 4 ? 738 : 737; }
 constexpr int OUS = 68;                       // cell stride of the staged u outputs
 
 
@@ -76,6 +84,8 @@ struct Mf<double> {
 //                  K position k = 4 ks + lane / 16; the padding position k = 91 reads the
 //                  zero sums of the zero node slot 91
 //   kl[4 KS]       input at K position k (91 for the padding position)
+//   bk[4 KS]       K positions of the butterfly passes, two per pass of 16 cells: an even
+//                  and an odd position whose inputs have indices of opposite parity
 //   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
 template <typename T>
 struct CTables {
@@ -83,6 +93,7 @@ struct CTables {
     int tb[8][KS][4];
     int tr[8][16];
     int kl[4 * KS];
+    int bk[4 * KS];
 };
 
 // column of CX x CY cells: NC cells per layer
@@ -91,7 +102,7 @@ struct CShared {
     static constexpr int NC = CX * CY, NNODE = NXL * (CY + 1);
     alignas(16) T tsum[NC * tsz<T>()];
     alignas(16) T out[NC * (OUS + 27)];
-    T nd[NNODE * NDP];
+    T nd[CY * ndy<T>() + NXL * ndx<T>()];
 };
 
 struct Map1 {
@@ -166,7 +177,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
     constexpr int TSZ = tsz<T>();
     // slot 91 of every node (the padding input) holds zero, so the butterflies write
     // zero sums for it; the stash never writes it
-    for (int i = tid; i < NNODE; i += NT) sh.nd[i * NDP + 91] = T(0);
+    constexpr int SX = ndx<T>(), SY = ndy<T>();
+    for (int i = tid; i < NNODE; i += NT) sh.nd[(i % NXL) * SX + (i / NXL) * SY + 91] = T(0);
 
     auto grp_of = [&](int g) { return NW >= 8 ? wave / 8 + (NW / 8) * g : g; };
     // the wave's classes: A operands, B offsets, output targets (registers)
@@ -234,7 +246,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
             const int m = ld_msk[i];
             bool neg = (m & 2) != 0;
             if (zghost && (((m >> 3) & 1) != 0) == zflip_odd) neg = !neg;
-            sh.nd[(e / NI) * NDP + e % NI] = neg ? -rl[i] : rl[i];
+            const int n = e / NI;
+            sh.nd[(n % NXL) * SX + (n / NXL) * SY + e % NI] = neg ? -rl[i] : rl[i];
         }
     };
 
@@ -262,11 +275,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
 
     constexpr int NBF = (NC * TL + NT - 1) / NT; // butterfly slots per thread
     T prev[NBF][4];                              // T_pxy of the lower node layer
-    int bl[NBF];                                 // input of each slot
+    int bkp[NBF], bl[NBF];                       // K position and input of each slot
 #pragma unroll
     for (int k = 0; k < NBF; ++k) {
         const int t = tid + k * NT;
-        bl[k] = t < NC * TL ? tabs->kl[4 * ((t >> 6) / (NC / 16)) + ((t >> 4) & 3)] : 0;
+        bkp[k] = t < NC * TL ? tabs->bk[2 * ((t >> 5) / (NC / 16)) + ((t >> 4) & 1)] : 0;
+        bl[k] = tabs->kl[bkp[k]];
     }
     fetch(cz0 + off);
     for (int step = 0; step < nlayers; ++step) {
@@ -276,19 +290,18 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
 
         // ---- 2. butterflies: T_pxy[l] of this layer (pxy = px + 2 py), combined with
-        //      the lower layer's into S_p[l], stored at the input's K position kp; a
-        //      wave covers 16 cells x 4 positions, and a thread keeps the same (cell, kp)
-        //      slots in every pass ----
+        //      the lower layer's into S_p[l], stored at the input's K position kp; 32
+        //      lanes cover 16 cells x the two positions of a pair, and a thread keeps the
+        //      same (cell, kp) slots in every pass ----
 #pragma unroll
         for (int k = 0; k < NBF; ++k) {
             const int t = tid + k * NT;
             if (t >= NC * TL) break;
-            const int hi = t >> 6;
-            const int cell = (t & 15) + 16 * (hi % (NC / 16)), kp = 4 * (hi / (NC / 16)) + ((t >> 4) & 3);
+            const int cell = (t & 15) + 16 * ((t >> 5) % (NC / 16)), kp = bkp[k];
             const int l = bl[k];
-            const int n00 = (cell % CX) + NXL * (cell / CX);
-            const T x00 = sh.nd[n00 * NDP + l], x10 = sh.nd[(n00 + 1) * NDP + l];
-            const T x01 = sh.nd[(n00 + NXL) * NDP + l], x11 = sh.nd[(n00 + NXL + 1) * NDP + l];
+            const int nb = (cell % CX) * SX + (cell / CX) * SY + l;
+            const T x00 = sh.nd[nb], x10 = sh.nd[nb + SX];
+            const T x01 = sh.nd[nb + SY], x11 = sh.nd[nb + SX + SY];
             const T p = x00 + x10, q = x00 - x10, r = x01 + x11, s = x01 - x11;
             const T cur[4] = {p + r, q + s, p - r, q - s};
             if (step > 0) {
@@ -387,6 +400,26 @@ hipError_t create(const ProblemDesc& D, void** out)
     CTables<T>* h = new CTables<T>();
     std::memset(h, 0, sizeof *h);
     for (int k = 0; k < 4 * KS; ++k) h->kl[k] = perm[k] < 0 ? 91 : perm[k];
+    // butterfly pairs: (even K position, odd K position) with inputs of opposite index
+    // parity.  There are as many even positions holding even inputs as odd positions
+    // holding odd ones (46 of each parity among both), so the pairs always exist.
+    {
+        std::vector<int> cls[4]; // [position parity][input parity]
+        for (int k = 0; k < 4 * KS; ++k) cls[2 * (k & 1) + (h->kl[k] & 1)].push_back(k);
+        if (cls[0].size() != cls[3].size() || cls[1].size() != cls[2].size()) {
+            delete h;
+            return hipErrorInvalidValue;
+        }
+        int j = 0;
+        for (size_t i = 0; i < cls[0].size(); ++i, ++j) {
+            h->bk[2 * j] = cls[0][i];
+            h->bk[2 * j + 1] = cls[3][i];
+        }
+        for (size_t i = 0; i < cls[1].size(); ++i, ++j) {
+            h->bk[2 * j] = cls[1][i];
+            h->bk[2 * j + 1] = cls[2][i];
+        }
+    }
     for (int q = 0; q < 8; ++q) {
         const int qx = q & 1, qy = (q >> 1) & 1, qz = (q >> 2) & 1;
         // rows: the 8 u outputs of the class, then its v outputs
