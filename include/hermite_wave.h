@@ -254,7 +254,11 @@ const char* hw_last_error(void);
 /* The autotuner's choices so far in this process, one line per key (kernel, d, m,
  * method, precision, size class -> chosen launch shape, its time).  Launch shapes are
  * timed on the problem itself when a solver is created (HW_AUTOTUNE=0 in the environment
- * turns this off; HW_TUNE_CACHE=<file> keeps the choices across processes).  The text is
+ * turns this off; HW_TUNE_CACHE=<file> keeps the choices across processes;
+ * HW_TUNE_FORCE=<kernel>=<choice>[,...] imposes a choice, e.g. "dense=-64,dense_list=16").
+ * For the 2-D dense kernels ("dense", "dense_list") a choice c > 0 is the per-lane gather
+ * form with tiles of c x (256 / c) cells, c < 0 the LDS-staged form with tiles of
+ * |c| x (256 / |c|) cells (|c| = 32 or 64).  The text is
  * thread-local and valid until the next call from the same thread.  This is about the
  * implementation's launch configuration, not the method of the paper. */
 const char* hw_tuning_report(void);

@@ -81,10 +81,10 @@ struct hw_solver {
         int4* tiles[2] = {nullptr, nullptr}; // work list per phase: {member, x0, y0, 0}
         int ntiles[2] = {0, 0};
         int grid = 0;
-        int tx = 64;
+        int tx = 64;                       // tile code (see set_tile)
     };
     std::vector<BatchClass> bclasses;
-    std::vector<int> dense_tx;    // per problem: tile width of the dense kernel (autotuned)
+    std::vector<int> dense_tx;    // per problem: tile code of the dense kernel (autotuned, see set_tile)
     void* cmap_tables = nullptr;
     bool state_set = false;
     int64_t half_steps = 0;
@@ -277,6 +277,25 @@ hw_status check_solver(const hw_solver* s)
 
 DenseArgs dense_args(const hw_solver* s, int k, int i);
 
+// A 2-D dense kernel variant as one tile code: tx > 0 is the per-lane gather form with
+// tiles of tx x (256 / tx) cells, tx < 0 the LDS-staged form with tiles of |tx| x (256 / |tx|)
+void set_tile(DenseArgs& a, int code)
+{
+    a.tile_x = code < 0 ? -code : code;
+    a.staged = code < 0 ? 1 : 0;
+}
+int staged_width(int code) { return code < 0 ? -code : 0; }
+
+// a tile code the dense kernels can launch (a choice imposed through HW_TUNE_FORCE may not be)
+hw_status check_tile(int code, int m, bool cons, bool fp64)
+{
+    if (code > 0 && code <= 256 && 256 % code == 0) return HW_OK;
+    if ((code == -32 || code == -64) && hw_dense_staged_fits(m, cons, fp64, -code)) return HW_OK;
+    return fail(HW_EUNSUPPORTED, "dense tile choice %d not available for m=%d method=%s %s", code, m,
+                cons ? "conservative" : "dissipative", fp64 ? "fp64" : "fp32");
+}
+int tile_width(int code) { return code < 0 ? -code : code; }
+
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
 {
     const int np = (int)s->probs.size();
@@ -284,7 +303,7 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         for (const auto& C : s->bclasses) {
             const size_t n = C.probs.size();
             HIP_TRY(hw_launch_dense_list(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.grid,
-                                         C.m, C.cons, s->fp64, st));
+                                         C.m, C.cons, s->fp64, staged_width(C.tx), st));
         }
         return HW_OK;
     }
@@ -355,7 +374,7 @@ DenseArgs dense_args(const hw_solver* s, int k, int i)
     a.v_out = D.v_out;
     a.G = s->dense_G[i];
     a.n_cells = D.n_out;
-    a.tile_x = s->dense_tx.empty() ? 64 : s->dense_tx[i];
+    set_tile(a, s->dense_tx.empty() ? 64 : s->dense_tx[i]);
     return a;
 }
 
@@ -405,22 +424,23 @@ void zero_state(hw_solver* s, int i)
     }
 }
 
-const std::vector<int> kTileCandidates = {16, 32, 64, 128};
+const std::vector<int> kTileCandidates = {16, 32, 64, 128, -32, -64};
 
 // Tile width of the single-problem dense kernel for 2-D problem i (autotuned).
-void tune_dense_single(hw_solver* s, int i)
+hw_status tune_dense_single(hw_solver* s, int i)
 {
     const Prob& P = s->probs[i];
-    if (P.p.d != 2 || !hw_tune_enabled()) return;
+    if (P.p.d != 2 || !hw_tune_enabled()) return HW_OK;
     zero_state(s, i);
     const bool cons = P.p.method == HW_CONSERVATIVE;
     auto time_us = [&](int cand) {
         DenseArgs a = dense_args(s, 0, i);
-        a.tile_x = cand;
+        set_tile(a, cand);
         return time_launches([&](hipStream_t ts) { return hw_launch_dense(a, 2, P.p.m, cons, s->fp64, ts); });
     };
     s->dense_tx[i] = hw_tune_choose("dense", 2, P.p.m, P.p.method, s->fp64, hw_tune_size_class(P.nodes[1]),
                                     kTileCandidates, time_us);
+    return check_tile(s->dense_tx[i], P.p.m, cons, s->fp64);
 }
 
 // The batched 2-D path: the problems grouped by (m, method); per class the dense
@@ -449,7 +469,7 @@ hw_status setup_batch_classes(hw_solver* s)
         if (hipMalloc((void**)&C.args, ha.size() * sizeof(DenseArgs)) != hipSuccess)
             return fail(HW_ENOMEM, "batch descriptor allocation failed");
         auto upload_args = [&](int tx) {
-            for (auto& a : ha) a.tile_x = tx;
+            for (auto& a : ha) set_tile(a, tx);
             return hipMemcpy(C.args, ha.data(), ha.size() * sizeof(DenseArgs), hipMemcpyHostToDevice);
         };
         if (hw_tune_enabled()) {
@@ -460,7 +480,7 @@ hw_status setup_batch_classes(hw_solver* s)
             int4* dt = nullptr;
             auto time_us = [&](int cand) -> double {
                 std::vector<int4> tl;
-                class_tiles(s, 0, std::vector<int>{C.probs[rep]}, cand, tl);
+                class_tiles(s, 0, std::vector<int>{C.probs[rep]}, tile_width(cand), tl);
                 for (auto& t : tl) t.x = rep;  // the list names the member's own descriptor
                 if (upload_args(cand) != hipSuccess) return -1.0;
                 if (dt) (void)hipFree(dt);
@@ -470,17 +490,20 @@ hw_status setup_batch_classes(hw_solver* s)
                     return -1.0;
                 const int grid = (int)std::min<size_t>(tl.size(), 2048);
                 return time_launches([&](hipStream_t ts) {
-                    return hw_launch_dense_list(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64, ts);
+                    return hw_launch_dense_list(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64,
+                                                staged_width(cand), ts);
                 });
             };
             C.tx = hw_tune_choose("dense_list", 2, C.m, C.cons ? HW_CONSERVATIVE : HW_DISS_FULL, s->fp64,
                                   hw_tune_size_class(s->probs[C.probs[rep]].nodes[1]), kTileCandidates, time_us);
             if (dt) (void)hipFree(dt);
+            const hw_status st = check_tile(C.tx, C.m, C.cons, s->fp64);
+            if (st != HW_OK) return st;
         }
         if (upload_args(C.tx) != hipSuccess) return fail(HW_EHIP, "batch descriptor upload failed");
         for (int ph = 0; ph < 2; ++ph) {
             std::vector<int4> tl;
-            class_tiles(s, ph, C.probs, C.tx, tl);
+            class_tiles(s, ph, C.probs, tile_width(C.tx), tl);
             C.ntiles[ph] = (int)tl.size();
             if (hipMalloc((void**)&C.tiles[ph], std::max<size_t>(tl.size(), 1) * sizeof(int4)) != hipSuccess)
                 return fail(HW_ENOMEM, "batch work list allocation failed");
@@ -760,7 +783,10 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         s->dense.clear();  // the classes' launches replace the per-problem dense launches
     } else {
         for (int i = 0; i < count; ++i)
-            if (!s->dense.empty() && s->dense[i]) tune_dense_single(s, i);
+            if (!s->dense.empty() && s->dense[i]) {
+                const hw_status st = tune_dense_single(s, i);
+                if (st != HW_OK) return cleanup(st);
+            }
     }
     if (s->use_cmap && hw_cmap3d_tables_create(s->h_descs[0], s->fp64, &s->cmap_tables) != hipSuccess)
         return cleanup(fail(HW_EHIP, "composed-map table setup failed"));

@@ -82,9 +82,9 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
     // memory (batch descriptors) load and store as global, not generic, accesses
     typedef const __attribute__((address_space(1))) T* GIn;
     typedef __attribute__((address_space(1))) T* GOut;
-    const GIn uin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
-    const GIn vin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
-    const GIn uold_in = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old));
+    const GIn __restrict__ uin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
+    const GIn __restrict__ vin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
+    const GIn __restrict__ uold_in = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old));
     // conservative: the old level is read first, so that its latency overlaps the products
     T uold[EARLY_OLD ? NU : 1];
     if constexpr (EARLY_OLD) {
@@ -165,16 +165,28 @@ __device__ void dense_cell(const DenseArgs& a, int64_t cell)
     block(uin, std::integral_constant<int, MU>{}, 0);
     if constexpr (!CONS) block(vin, std::integral_constant<int, MV>{}, NU);
 
-    const GOut uo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + cell * NU;
+    const GOut __restrict__ uo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + cell * NU;
     if constexpr (EARLY_OLD) {
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - uold[o];
     } else if constexpr (CONS) {
-        const GIn old = uold_in + cell * NU;
+        // the old level in chunks of 16, each chunk's loads issued before its stores (the
+        // compiler cannot tell that the old and new levels do not overlap, and would
+        // otherwise wait for every load after the previous store)
+        const GIn __restrict__ old = uold_in + cell * NU;
+        constexpr int CH = 16;
 #pragma unroll
-        for (int o = 0; o < NU; ++o) uo[o] = T(2) * acc[o] - old[o];
+        for (int o0 = 0; o0 < NU; o0 += CH) {
+            T ov[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (o0 + j < NU) ov[j] = old[o0 + j];
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (o0 + j < NU) uo[o0 + j] = T(2) * acc[o0 + j] - ov[j];
+        }
     } else {
-        const GOut vo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + cell * NV;
+        const GOut __restrict__ vo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + cell * NV;
 #pragma unroll
         for (int o = 0; o < NU; ++o) uo[o] = acc[o];
 #pragma unroll
@@ -201,6 +213,201 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
         cell = x + (int64_t)a.ext_to[0] * y;
     }
     dense_cell<T, D, MU, CONS>(a, cell);
+}
+
+// ---------------------------------------------------------------------------------
+// LDS-staged 2-D form: a workgroup's tile of TX x TY cells (TX TY = 256) first copies the
+// (TX+1) x (TY+1) input nodes it needs into LDS with coalesced loads (a row of nodes is
+// contiguous in memory), ghost nodes mirrored there; the lanes then read their corners
+// from LDS, and the outputs go back through LDS so that they too are stored (and the
+// conservative old level read) with coalesced accesses.  Per cell the arithmetic is the
+// per-lane dense form above.
+template <typename T, int MU, bool CONS>
+struct StagedShape {
+    static constexpr int MV = CONS ? 0 : MU - 1;
+    static constexpr int NU = MU * MU, NV = MV * MV, NI = NU + NV, NO = NI;
+    // odd strides: a lane per cell (or node) at this stride touches distinct banks
+    static constexpr int NIP = NI | 1, NOP = NO | 1;
+    static constexpr size_t lds_words(int tx)
+    {
+        const size_t in = (size_t)(tx + 1) * (DENSE_BLOCK / tx + 1) * NIP, out = (size_t)DENSE_BLOCK * NOP;
+        return in > out ? in : out;
+    }
+};
+
+__device__ inline int wrap_node(int j, int ext, int bc, bool& ghost)
+{
+    ghost = false;
+    if (bc == 0) {
+        j %= ext;
+        return j < 0 ? j + ext : j;
+    }
+    if (j < 0) {
+        ghost = true;
+        return 0;
+    }
+    if (j >= ext) {
+        ghost = true;
+        return ext - 1;
+    }
+    return j;
+}
+
+template <typename T, int MU, bool CONS, int TX>
+__device__ void dense_tile_staged(const DenseArgs& a, int x0, int y0, T* __restrict__ sm)
+{
+    using S = StagedShape<T, MU, CONS>;
+    constexpr int TY = DENSE_BLOCK / TX, NXT = TX + 1, NYT = TY + 1;
+    constexpr int MV = S::MV, NU = S::NU, NV = S::NV, NO = S::NO, NIP = S::NIP, NOP = S::NOP;
+    typedef const __attribute__((address_space(1))) T* GIn;
+    typedef __attribute__((address_space(1))) T* GOut;
+    typedef const __attribute__((address_space(4))) T* ConstPtr;
+    const int tid = threadIdx.x;
+    const int off = a.to_grid == 1 ? 0 : -1; // input node of corner s = cell + off + s
+    const int ex0 = a.ext_from[0], ex1 = a.ext_from[1];
+
+    // ---- stage the input nodes (u block, then v block of every node): row by row of
+    //      the tile, each thread keeping the same (node column, coefficient) slots in
+    //      every row, so that the column's index and x ghost sign are computed once ----
+    auto stage = [&](const GIn src, auto md_tag, int base) {
+        constexpr int MD = decltype(md_tag)::value, NB = MD * MD;
+        constexpr int PER_ROW = NXT * NB, SLOTS = (PER_ROW + DENSE_BLOCK - 1) / DENSE_BLOCK;
+        int col[SLOTS], dst[SLOTS];
+        bool negx[SLOTS], ylflip_even[SLOTS];
+#pragma unroll
+        for (int k = 0; k < SLOTS; ++k) {
+            const int e = tid + k * DENSE_BLOCK;
+            const int xx = e / NB, l = e - xx * NB;
+            bool gxg;
+            const int gx = wrap_node(x0 + xx + off, ex0, a.bc[0], gxg);
+            col[k] = gx * NB + l;
+            dst[k] = xx * NIP + base + l;
+            negx[k] = gxg && flips(a.bc[0], l % MD);
+            ylflip_even[k] = ((l / MD) & 1) == 0;
+        }
+        for (int yy = 0; yy < NYT; ++yy) {
+            bool gyg;
+            const int gy = wrap_node(y0 + yy + off, ex1, a.bc[1], gyg);
+            const GIn row = src + (int64_t)gy * ex0 * NB;
+            // Dirichlet (bc 1) mirrors flip the even l_y, Neumann (bc 2) the odd ones
+            const bool yflip_even = a.bc[1] == 1;
+#pragma unroll
+            for (int k = 0; k < SLOTS; ++k) {
+                if (k * DENSE_BLOCK + tid >= PER_ROW) break;
+                const T v = row[col[k]];
+                const bool neg = negx[k] != (gyg && ylflip_even[k] == yflip_even);
+                sm[yy * NXT * NIP + dst[k]] = neg ? -v : v;
+            }
+        }
+    };
+    stage(reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in)), std::integral_constant<int, MU>{}, 0);
+    if constexpr (!CONS)
+        stage(reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in)), std::integral_constant<int, MV>{}, NU);
+    __syncthreads();
+
+    // ---- per lane: corners from LDS, sums S_p, products with G (scalar operands) ----
+    const int tx = tid % TX, ty = tid / TX;
+    const ConstPtr G = reinterpret_cast<ConstPtr>(reinterpret_cast<uintptr_t>(a.G));
+    T acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = T(0);
+    auto opar = [](int o, int i) {
+        const int md = o < NU ? MU : MV, oo = o < NU ? o : o - NU;
+        return (i == 0 ? oo % md : (oo / md) % md) & 1;
+    };
+    const T* __restrict__ n00 = sm + (ty * NXT + tx) * NIP;
+    auto block = [&](auto md_tag, int in0) {
+        constexpr int MD = decltype(md_tag)::value;
+#pragma unroll 1
+        for (int ly = 0; ly < MD; ++ly)
+#pragma unroll
+            for (int lx = 0; lx < MD; ++lx) {
+                const int l = in0 + lx + MD * ly;
+                const T x00 = n00[l], x10 = n00[NIP + l], x01 = n00[NXT * NIP + l], x11 = n00[(NXT + 1) * NIP + l];
+                const T p = x00 + x10, q = x00 - x10, r = x01 + x11, t = x01 - x11;
+                const bool ly_odd = (ly & 1) != 0;
+                T Sv[4];
+                Sv[0] = ly_odd ? p - r : p + r;
+                Sv[1] = ly_odd ? q - t : q + t;
+                Sv[2] = ly_odd ? p + r : p - r;
+                Sv[3] = ly_odd ? q + t : q - t;
+                const ConstPtr g = G + (int64_t)l * NO;
+#pragma unroll
+                for (int o = 0; o < NO; ++o) acc[o] += g[o] * Sv[((opar(o, 0) + lx) & 1) + 2 * opar(o, 1)];
+            }
+    };
+    block(std::integral_constant<int, MU>{}, 0);
+    if constexpr (!CONS) block(std::integral_constant<int, MV>{}, NU);
+    __syncthreads(); // every lane is done with the nodes: the outputs reuse the LDS
+
+#pragma unroll
+    for (int o = 0; o < NO; ++o) sm[tid * NOP + o] = acc[o];
+    __syncthreads();
+
+    // ---- coalesced stores of the tile's rows (conservative: u_new = 2 S - u_old), row by
+    //      row, each thread keeping the same (cell column, coefficient) slots ----
+    auto put = [&](GOut dst, const GIn old, int nb_tag, auto nbc) {
+        constexpr int NB = decltype(nbc)::value, PER_ROW = TX * NB;
+        constexpr int SLOTS = (PER_ROW + DENSE_BLOCK - 1) / DENSE_BLOCK;
+        const int base = nb_tag;
+        int gofs[SLOTS], sofs[SLOTS];
+        bool okx[SLOTS];
+#pragma unroll
+        for (int k = 0; k < SLOTS; ++k) {
+            const int e = tid + k * DENSE_BLOCK;
+            const int xx = e / NB, o = e - xx * NB;
+            okx[k] = e < PER_ROW && x0 + xx < a.ext_to[0];
+            gofs[k] = (x0 + xx) * NB + o;
+            sofs[k] = xx * NOP + base + o;
+        }
+        for (int yy = 0; yy < TY; ++yy) {
+            const int gy = y0 + yy;
+            if (gy >= a.ext_to[1]) break;
+            const int64_t rb = (int64_t)gy * a.ext_to[0] * NB;
+#pragma unroll
+            for (int k = 0; k < SLOTS; ++k) {
+                if (!okx[k]) continue;
+                const T sv = sm[yy * TX * NOP + sofs[k]];
+                if constexpr (CONS) dst[rb + gofs[k]] = T(2) * sv - old[rb + gofs[k]];
+                else dst[rb + gofs[k]] = sv;
+            }
+        }
+    };
+    put(reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)),
+        reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old)), 0, std::integral_constant<int, NU>{});
+    if constexpr (!CONS)
+        put(reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)), nullptr, NU,
+            std::integral_constant<int, NV>{});
+}
+
+template <typename T, int MU, bool CONS, int TX>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged(DenseArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tiles_x = (a.ext_to[0] + TX - 1) / TX;
+    const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * (DENSE_BLOCK / TX);
+    dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+}
+
+template <typename T, int MU, bool CONS, int TX>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged_list(const DenseArgs* __restrict__ probs,
+                                                                   const int4* __restrict__ tiles, int n_tiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int nx = nb < 8 ? nb : 8;
+    const int xcd = b % nx, slot = b / nx;
+    const int per_xcd = (nb + nx - 1 - xcd) / nx;
+    const int chunk = (n_tiles + nx - 1) / nx;
+    const int t0 = xcd * chunk, t1 = min(n_tiles, t0 + chunk);
+    for (int t = t0 + slot; t < t1; t += per_xcd) {
+        const int4 tl = tiles[t];
+        const int pi = __builtin_amdgcn_readfirstlane(tl.x);
+        const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
+        const DenseArgs a = probs[pi];
+        dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+        __syncthreads(); // the next tile's staging overwrites the LDS
+    }
 }
 
 // many 2-D problems of one (m, method): a persistent grid walks a work list of tiles
@@ -232,9 +439,32 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_list(const DenseArgs* __r
     }
 }
 
+// the staged form's LDS: at most the 160 KB of a CU
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <typename T, int MU, bool CONS, int TX>
+hipError_t launch_staged(const DenseArgs& a, hipStream_t st)
+{
+    const size_t lds = StagedShape<T, MU, CONS>::lds_words(TX) * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = k_dense_staged<T, MU, CONS, TX>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int blocks = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + DENSE_BLOCK / TX - 1) / (DENSE_BLOCK / TX));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(DENSE_BLOCK), lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename T, int D, int MU, bool CONS>
 hipError_t launch(const DenseArgs& a, hipStream_t st)
 {
+    if constexpr (D == 2) {
+        if (a.staged) {
+            if (a.tile_x == 32) return launch_staged<T, MU, CONS, 32>(a, st);
+            if (a.tile_x == 64) return launch_staged<T, MU, CONS, 64>(a, st);
+            return hipErrorInvalidValue;
+        }
+    }
     const int tx = a.tile_x;
     const int64_t blocks = D == 1 ? (a.n_cells + DENSE_BLOCK - 1) / DENSE_BLOCK
                                   : (int64_t)((a.ext_to[0] + tx - 1) / tx) *
@@ -243,35 +473,51 @@ hipError_t launch(const DenseArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int MU, bool CONS>
-hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, hipStream_t st)
+template <typename T, int MU, bool CONS, int TX>
+hipError_t launch_staged_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, hipStream_t st)
 {
+    const size_t lds = StagedShape<T, MU, CONS>::lds_words(TX) * sizeof(T);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    auto kern = k_dense_staged_list<T, MU, CONS, TX>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(DENSE_BLOCK), lds, st, probs, tiles, n_tiles);
+    return hipGetLastError();
+}
+
+template <typename T, int MU, bool CONS>
+hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int staged_tx,
+                       hipStream_t st)
+{
+    if (staged_tx == 32) return launch_staged_list<T, MU, CONS, 32>(probs, tiles, n_tiles, grid, st);
+    if (staged_tx == 64) return launch_staged_list<T, MU, CONS, 64>(probs, tiles, n_tiles, grid, st);
+    if (staged_tx != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_dense_list<T, MU, CONS>), dim3(grid), dim3(DENSE_BLOCK), 0, st, probs, tiles, n_tiles);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t dispatch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
-                         hipStream_t st)
+                         int staged_tx, hipStream_t st)
 {
     if (cons) {
         switch (m) {
-        case 0: return launch_list<T, 1, true>(probs, tiles, n_tiles, grid, st);
-        case 1: return launch_list<T, 2, true>(probs, tiles, n_tiles, grid, st);
-        case 2: return launch_list<T, 3, true>(probs, tiles, n_tiles, grid, st);
-        case 3: return launch_list<T, 4, true>(probs, tiles, n_tiles, grid, st);
-        case 4: return launch_list<T, 5, true>(probs, tiles, n_tiles, grid, st);
-        case 5: return launch_list<T, 6, true>(probs, tiles, n_tiles, grid, st);
-        case 6: return launch_list<T, 7, true>(probs, tiles, n_tiles, grid, st);
+        case 0: return launch_list<T, 1, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 1: return launch_list<T, 2, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 2: return launch_list<T, 3, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 3: return launch_list<T, 4, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 4: return launch_list<T, 5, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 5: return launch_list<T, 6, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 6: return launch_list<T, 7, true>(probs, tiles, n_tiles, grid, staged_tx, st);
         }
     } else {
         switch (m) {
-        case 1: return launch_list<T, 2, false>(probs, tiles, n_tiles, grid, st);
-        case 2: return launch_list<T, 3, false>(probs, tiles, n_tiles, grid, st);
-        case 3: return launch_list<T, 4, false>(probs, tiles, n_tiles, grid, st);
-        case 4: return launch_list<T, 5, false>(probs, tiles, n_tiles, grid, st);
-        case 5: return launch_list<T, 6, false>(probs, tiles, n_tiles, grid, st);
-        case 6: return launch_list<T, 7, false>(probs, tiles, n_tiles, grid, st);
+        case 1: return launch_list<T, 2, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 2: return launch_list<T, 3, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 3: return launch_list<T, 4, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 4: return launch_list<T, 5, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 5: return launch_list<T, 6, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 6: return launch_list<T, 7, false>(probs, tiles, n_tiles, grid, staged_tx, st);
         }
     }
     return hipErrorInvalidValue;
@@ -327,19 +573,29 @@ hipError_t dispatch(const DenseArgs& a, int d, int m, bool cons, hipStream_t st)
 
 } // namespace
 
+bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx)
+{
+    if (m < 0 || m > 6 || (!cons && m < 1) || (tx != 32 && tx != 64)) return false;
+    const int mu = m + 1, mv = cons ? 0 : m;
+    const size_t nip = (size_t)(mu * mu + mv * mv) | 1;
+    const size_t in = (size_t)(tx + 1) * (DENSE_BLOCK / tx + 1) * nip, out = (size_t)DENSE_BLOCK * nip;
+    return (in > out ? in : out) * (fp64 ? 8 : 4) <= kMaxLds;
+}
+
 hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
-                                bool fp64, hipStream_t st)
+                                bool fp64, int staged_tx, hipStream_t st)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (grid < 1) grid = 1;
-    return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, grid, m, cons, st)
-                : dispatch_list<float>(probs, tiles, n_tiles, grid, m, cons, st);
+    return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, grid, m, cons, staged_tx, st)
+                : dispatch_list<float>(probs, tiles, n_tiles, grid, m, cons, staged_tx, st);
 }
 
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
 {
     if (!a.G || a.n_cells < 0) return hipErrorInvalidValue;
     if (d == 2 && (a.tile_x < 1 || a.tile_x > DENSE_BLOCK || DENSE_BLOCK % a.tile_x)) return hipErrorInvalidValue;
+    if (a.staged && (d != 2 || (a.tile_x != 32 && a.tile_x != 64))) return hipErrorInvalidValue;
     if (a.n_cells == 0) return hipSuccess;
     for (int i = 0; i < d; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;

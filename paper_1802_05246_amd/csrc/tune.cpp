@@ -3,7 +3,8 @@
 // keeps the fastest in a process-wide cache.  With HW_TUNE_CACHE=<file> the cache is read
 // from and appended to that text file (one "kernel d m method fp64 size choice us" line
 // per key), so later processes reuse the choices; HW_AUTOTUNE=0 turns the timing off
-// (every kernel then takes its default shape).
+// (every kernel then takes its default shape); HW_TUNE_FORCE="kernel=choice,..." imposes
+// a choice for the named kernels (tests use it to run every variant).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -49,6 +50,31 @@ void load_locked()
     std::fclose(fp);
 }
 
+// the choice HW_TUNE_FORCE imposes on `kernel`, if any
+bool forced_choice(const char* kernel, int& choice)
+{
+    const char* f = std::getenv("HW_TUNE_FORCE");
+    if (!f) return false;
+    const std::string spec(f), name(kernel);
+    size_t pos = 0;
+    while (pos < spec.size()) {
+        size_t end = spec.find(',', pos);
+        if (end == std::string::npos) end = spec.size();
+        const std::string item = spec.substr(pos, end - pos);
+        const size_t eq = item.find('=');
+        if (eq != std::string::npos && item.substr(0, eq) == name) {
+            char* rest = nullptr;
+            const long v = std::strtol(item.c_str() + eq + 1, &rest, 10);
+            if (rest && *rest == '\0' && rest != item.c_str() + eq + 1) {
+                choice = (int)v;
+                return true;
+            }
+        }
+        pos = end + 1;
+    }
+    return false;
+}
+
 } // namespace
 
 bool hw_tune_enabled()
@@ -70,6 +96,8 @@ int hw_tune_choose(const char* kernel, int d, int m, int method, bool fp64, int 
                    const std::vector<int>& candidates, const std::function<double(int)>& time_us)
 {
     const Key key(kernel, d, m, method, fp64 ? 1 : 0, size_class);
+    int forced = 0;
+    if (forced_choice(kernel, forced)) return forced;
     {
         std::lock_guard<std::mutex> lock(g_mu);
         load_locked();
