@@ -353,12 +353,17 @@ def main():
     torch.cuda.empty_cache()
     probes = None
     if not args.no_probes:
-        log("[bench] peak probes: STREAM triad, matrix-core FP32 / FP64")
+        log("[bench] peak probes: STREAM triad, matrix-core FP32 / FP64, co-execution")
+        co = B.hw_probe_coexec()
         probes = {"hbm_triad_gbs": B.hw_probe_stream_triad(1 << 28),
                   "mfma_fp32_tflops": B.hw_probe_mfma(B.HW_FP32),
                   "mfma_fp64_tflops": B.hw_probe_mfma(B.HW_FP64),
+                  "coexec_ms": {"products": co[0], "vector_fmas": co[1], "both": co[2],
+                                "overlap_frac": (co[0] + co[1] - co[2]) / min(co[0], co[1])},
                   "note": "attainable peaks measured on this GPU (triad over three 2 GiB FP64 arrays; "
-                          "independent 16x16x4 matrix-core products)"}
+                          "independent 16x16x4 matrix-core products); coexec: the same products and "
+                          "independent FP32 FMAs timed alone and together in every wave "
+                          "(overlap_frac 1: fully overlapped, 0: taking turns)"}
 
     # roofline of the dominant kernel (the half-step kernel of the FP32 form)
     launches = 2 * K

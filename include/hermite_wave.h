@@ -272,9 +272,15 @@ const char* hw_tuning_report(void);
  *   *gbs_out = 24 n bytes per pass / time, in GB/s.
  * hw_probe_mfma: 2048 workgroups of 4 waves, each wave 4096 rounds of 8 independent
  *   16x16x4 matrix-core products (2048 flops each) in HW_FP32 or HW_FP64, no memory
- *   traffic; *tflops_out in TFLOP/s. */
+ *   traffic; *tflops_out in TFLOP/s.
+ * hw_probe_coexec: whether matrix-core and vector work overlap on a SIMD.  4096
+ *   workgroups of 4 waves, each wave 4096 rounds; a round is 4 independent FP32 16x16x4
+ *   products and/or 32 independent FP32 vector FMAs.  ms_out[0]: products only, [1]: FMAs
+ *   only, [2]: both in every wave (milliseconds per launch).  [2] near max([0], [1]) means
+ *   the two overlap, near [0] + [1] that they take turns. */
 hw_status hw_probe_stream_triad(int64_t n, double* gbs_out);
 hw_status hw_probe_mfma(int precision, double* tflops_out);
+hw_status hw_probe_coexec(double ms_out[3]);
 
 /* ---- batches: independent problems advanced together --------------------------
  * Many independent problems of the kind above (each one the problem statement of

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ECFL", -3: "HW_ENOMEM",
 ENTRY_POINTS = ["hw_create", "hw_destroy", "hw_layout", "hw_set_state", "hw_cons_startup",
                 "hw_advance", "hw_prepare_advance", "hw_half_steps", "hw_half_step_forced", "hw_half_step_ext", "hw_get_state", "hw_state_grid", "hw_energy",
                 "hw_energy_noalloc",
-                "hw_time", "hw_last_error", "hw_tuning_report", "hw_probe_stream_triad", "hw_probe_mfma", "hw_batch_create", "hw_batch_layout",
+                "hw_time", "hw_last_error", "hw_tuning_report", "hw_probe_stream_triad", "hw_probe_mfma", "hw_probe_coexec", "hw_batch_create", "hw_batch_layout",
                 "hw_batch_set_state", "hw_batch_cons_startup", "hw_batch_advance",
                 "hw_batch_get_state"]
 
@@ -84,6 +84,7 @@ def lib():
             "hw_tuning_report": ([], ctypes.c_char_p),
             "hw_probe_stream_triad": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "hw_probe_mfma": ([ctypes.c_int, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "hw_probe_coexec": ([ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "hw_batch_create": ([pp, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
             "hw_batch_layout": ([vp, ctypes.c_int, ctypes.c_int, i64p, ip, ip], ctypes.c_int),
             "hw_batch_set_state": ([vp, ctypes.c_int, dp, dp, vp], ctypes.c_int),
@@ -109,6 +110,13 @@ def hw_probe_mfma(precision: int) -> float:
     t = ctypes.c_double()
     _check(lib().hw_probe_mfma(int(precision), ctypes.byref(t)))
     return t.value
+
+
+def hw_probe_coexec():
+    """(products only, FMAs only, both) in ms per launch: see include/hermite_wave.h."""
+    out = (ctypes.c_double * 3)()
+    _check(lib().hw_probe_coexec(out))
+    return tuple(out)
 
 
 def hw_tuning_report() -> str:

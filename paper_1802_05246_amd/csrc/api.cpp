@@ -1272,4 +1272,37 @@ hw_status hw_probe_mfma(int precision, double* tflops_out)
     return r;
 }
 
+hw_status hw_probe_coexec(double ms_out[3])
+{
+    if (!ms_out) return fail(HW_EINVAL, "output pointer is null");
+    const int groups = 4096, iters = 4096;
+    float* sink = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hw_status r = HW_OK;
+    if (hipMalloc((void**)&sink, (size_t)groups * 256 * sizeof(float)) != hipSuccess) {
+        r = fail(HW_ENOMEM, "probe sink allocation failed");
+    } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+               hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        r = fail(HW_EHIP, "probe stream setup failed");
+    } else {
+        for (int mode = 0; mode < 3 && r == HW_OK; ++mode) {
+            bool ok = hw_probe_coexec_launch(mode, sink, groups, iters, st) == hipSuccess;
+            ok = ok && hipEventRecord(e0, st) == hipSuccess;
+            ok = ok && hw_probe_coexec_launch(mode, sink, groups, iters, st) == hipSuccess;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f)
+                ms_out[mode] = ms;
+            else
+                r = fail(HW_EHIP, "co-execution probe failed");
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (sink) (void)hipFree(sink);
+    return r;
+}
+
 } // extern "C"

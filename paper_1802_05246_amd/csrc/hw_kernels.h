@@ -99,3 +99,5 @@ std::string hw_tune_report_text();
 // chains over `groups` workgroups of 256 threads, `iters` rounds of 8 products per wave.
 hipError_t hw_probe_triad_launch(double* a, const double* b, const double* c, int64_t n, hipStream_t st);
 hipError_t hw_probe_mfma_launch(bool fp64, void* sink, int groups, int iters, hipStream_t st);
+// mode 0: matrix-core products only, 1: vector FMAs only, 2: both in every wave
+hipError_t hw_probe_coexec_launch(int mode, float* sink, int groups, int iters, hipStream_t st);

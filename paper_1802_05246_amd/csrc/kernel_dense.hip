@@ -285,18 +285,32 @@ __device__ void dense_tile_staged(const DenseArgs& a, int x0, int y0, T* __restr
             negx[k] = gxg && flips(a.bc[0], l % MD);
             ylflip_even[k] = ((l / MD) & 1) == 0;
         }
-        for (int yy = 0; yy < NYT; ++yy) {
-            bool gyg;
-            const int gy = wrap_node(y0 + yy + off, ex1, a.bc[1], gyg);
-            const GIn row = src + (int64_t)gy * ex0 * NB;
-            // Dirichlet (bc 1) mirrors flip the even l_y, Neumann (bc 2) the odd ones
-            const bool yflip_even = a.bc[1] == 1;
+        // Dirichlet (bc 1) mirrors flip the even l_y, Neumann (bc 2) the odd ones
+        const bool yflip_even = a.bc[1] == 1;
+        // groups of rows whose loads are all issued before the first is written to LDS
+        // (at most 32 values in flight per thread)
+        constexpr int RG = SLOTS >= 32 ? 1 : (32 / SLOTS < NYT ? 32 / SLOTS : NYT);
+        for (int yg = 0; yg < NYT; yg += RG) {
+            T v[RG][SLOTS];
+            bool gyg[RG];
 #pragma unroll
-            for (int k = 0; k < SLOTS; ++k) {
-                if (k * DENSE_BLOCK + tid >= PER_ROW) break;
-                const T v = row[col[k]];
-                const bool neg = negx[k] != (gyg && ylflip_even[k] == yflip_even);
-                sm[yy * NXT * NIP + dst[k]] = neg ? -v : v;
+            for (int r = 0; r < RG; ++r) {
+                if (yg + r >= NYT) break;
+                const int gy = wrap_node(y0 + yg + r + off, ex1, a.bc[1], gyg[r]);
+                const GIn row = src + (int64_t)gy * ex0 * NB;
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k)
+                    if (k * DENSE_BLOCK + tid < PER_ROW) v[r][k] = row[col[k]];
+            }
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                if (yg + r >= NYT) break;
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k) {
+                    if (k * DENSE_BLOCK + tid >= PER_ROW) break;
+                    const bool neg = negx[k] != (gyg[r] && ylflip_even[k] == yflip_even);
+                    sm[(yg + r) * NXT * NIP + dst[k]] = neg ? -v[r][k] : v[r][k];
+                }
             }
         }
     };
@@ -360,16 +374,33 @@ __device__ void dense_tile_staged(const DenseArgs& a, int x0, int y0, T* __restr
             gofs[k] = (x0 + xx) * NB + o;
             sofs[k] = xx * NOP + base + o;
         }
-        for (int yy = 0; yy < TY; ++yy) {
-            const int gy = y0 + yy;
-            if (gy >= a.ext_to[1]) break;
-            const int64_t rb = (int64_t)gy * a.ext_to[0] * NB;
+        // conservative: the old level of a group of rows is read before any of its stores
+        constexpr int RG = !CONS ? 1 : (SLOTS >= 32 ? 1 : (32 / SLOTS < TY ? 32 / SLOTS : TY));
+        for (int yg = 0; yg < TY; yg += RG) {
+            T ov[RG][SLOTS];
+            if constexpr (CONS) {
 #pragma unroll
-            for (int k = 0; k < SLOTS; ++k) {
-                if (!okx[k]) continue;
-                const T sv = sm[yy * TX * NOP + sofs[k]];
-                if constexpr (CONS) dst[rb + gofs[k]] = T(2) * sv - old[rb + gofs[k]];
-                else dst[rb + gofs[k]] = sv;
+                for (int r = 0; r < RG; ++r) {
+                    const int gy = y0 + yg + r;
+                    if (yg + r >= TY || gy >= a.ext_to[1]) break;
+                    const int64_t rb = (int64_t)gy * a.ext_to[0] * NB;
+#pragma unroll
+                    for (int k = 0; k < SLOTS; ++k)
+                        if (okx[k]) ov[r][k] = old[rb + gofs[k]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RG; ++r) {
+                const int gy = y0 + yg + r;
+                if (yg + r >= TY || gy >= a.ext_to[1]) break;
+                const int64_t rb = (int64_t)gy * a.ext_to[0] * NB;
+#pragma unroll
+                for (int k = 0; k < SLOTS; ++k) {
+                    if (!okx[k]) continue;
+                    const T sv = sm[(yg + r) * TX * NOP + sofs[k]];
+                    if constexpr (CONS) dst[rb + gofs[k]] = T(2) * sv - ov[r][k];
+                    else dst[rb + gofs[k]] = sv;
+                }
             }
         }
     };
