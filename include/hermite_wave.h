@@ -65,8 +65,8 @@ typedef enum {
 } hw_precision;
 
 typedef enum {
-    HW_KERNEL_AUTO = 0,    /* 3-D dissipative m = 3: composed in FP64 and FP32, tiled for
-                              BF16 operands; 2-D batches: batched; single problems with
+    HW_KERNEL_AUTO = 0,    /* 3-D m = 3 (either method): composed in FP64 and FP32, tiled
+                              for BF16 operands; 2-D batches: batched; single problems with
                               d <= 2: dense where it exists; else generic */
     HW_KERNEL_GENERIC = 1, /* one workgroup per cell, any d <= 3, any supported m */
     HW_KERNEL_TILED = 2,   /* LDS-tiled MFMA kernel (3-D dissipative full, m = 3) */
@@ -83,11 +83,13 @@ typedef enum {
                               d = 2 conservative m <= 5, FP64 or FP32 (HW_EUNSUPPORTED
                               otherwise; with HW_KERNEL_AUTO the other problems of a batch
                               share one generic launch) */
-    HW_KERNEL_COMPOSED = 5, /* 3-D dissipative (full or simple variant, any truncation), m = 3,
-                              FP64 or FP32, single problems: each cell's half step as its
-                              composed matrix, corners combined by the reflection symmetry
-                              of the Hermite operators, applied per output parity class to 16
-                              cells at a time on the matrix cores (HW_EUNSUPPORTED otherwise) */
+    HW_KERNEL_COMPOSED = 5, /* 3-D, m = 3, dissipative (full or simple variant, any
+                              truncation) or conservative, FP64 or FP32, single problems: each
+                              cell's half step as its composed matrix (conservative: the even
+                              time sum S, then u_new = 2 S - u_old), corners combined by the
+                              reflection symmetry of the Hermite operators, applied per output
+                              parity class to 16 cells at a time on the matrix cores
+                              (HW_EUNSUPPORTED otherwise) */
     HW_KERNEL_BATCH = 6    /* 2-D, FP64 or FP32, any m and method, batches or single problems:
                               the problems grouped by (m, method); per group and half step one
                               persistent launch of the dense kernel walks a work list of tiles

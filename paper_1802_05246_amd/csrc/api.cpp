@@ -324,6 +324,8 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
         a.v_out = D.v_out;
         a.tau = D.tau;
         a.tables = s->use_cmap ? s->cmap_tables : s->tiled_tables;
+        a.u_old = D.u_old;
+        a.cons = D.variant == HWV_CONS ? 1 : 0;
         (void)P;
         if (s->use_cmap) HIP_TRY(hw_launch_cmap3d(a, s->fp64, st));
         else HIP_TRY(hw_launch_tiled(a, s->precision, st));
@@ -535,11 +537,11 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (p0.kernel == HW_KERNEL_TILED && !tiled_ok)
         return fail(HW_EUNSUPPORTED, "no tiled kernel for d=%d m=%d method=%d precision=%d", p0.d,
                     p0.m, p0.method, p0.precision);
-    const bool cmap_ok = count == 1 && p0.d == 3 && p0.m == 3 && p0.method != HW_CONSERVATIVE &&
+    const bool cmap_ok = count == 1 && p0.d == 3 && p0.m == 3 &&
                          (p0.precision == HW_FP64 || p0.precision == HW_FP32);
     if (p0.kernel == HW_KERNEL_COMPOSED && !cmap_ok)
-        return fail(HW_EUNSUPPORTED, "the composed-map kernel serves single 3-D dissipative problems with "
-                                     "m = 3 in FP64 or FP32");
+        return fail(HW_EUNSUPPORTED, "the composed-map kernel serves single 3-D problems with m = 3 in FP64 "
+                                     "or FP32");
     if (p0.kernel == HW_KERNEL_DENSE)
         for (int i = 0; i < count; ++i)
             if (!hw_dense_supported(ps[i].d, ps[i].m, ps[i].method, ps[i].precision))

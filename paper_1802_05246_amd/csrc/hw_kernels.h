@@ -39,7 +39,9 @@ struct TiledArgs {
     void* u_out;
     void* v_out;
     double tau, lam2[3];
-    const void* tables; // from hw_tiled_tables_create with the same precision, lam2 and tau
+    const void* tables;           // from hw_tiled_tables_create / hw_cmap3d_tables_create
+    const void* u_old = nullptr;  // composed-map kernel, conservative: old level on the grid written
+    int cons = 0;                 // composed-map kernel: 1 = conservative method
 };
 // Per-lane dense kernel for d <= 2 (kernel_dense.hip): each output node is the product
 // of the problem's cell matrix G (hw_cell_map, FP64 on the host, uploaded in the state
@@ -73,7 +75,7 @@ hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n
 // whether the LDS-staged form with tiles tx cells wide fits a CU's LDS for (m, method, precision)
 bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx);
 
-// Composed-map MFMA kernel for the 3-D dissipative method, m = 3 (kernel_cmap3d.hip):
+// Composed-map MFMA kernel for the 3-D dissipative and conservative methods, m = 3 (kernel_cmap3d.hip):
 // the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are
 // passed in TiledArgs::tables.
 hipError_t hw_cmap3d_tables_create(const ProblemDesc& D, bool fp64, void** out);

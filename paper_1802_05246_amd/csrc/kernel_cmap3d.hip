@@ -1,10 +1,11 @@
-// Composed-map half-step kernel for the 3-D dissipative method (Sec. 3.3, d = 3; the
-// modified first step or the straightforward variant, exact or truncated series), nodal
-// degree m = 3, element type T = float or double.
+// Composed-map half-step kernel for 3-D problems of nodal degree m = 3, element type
+// T = float or double: the dissipative method (Sec. 3.3; the modified first step or the
+// straightforward variant, exact or truncated series) and the conservative method
+// (Sec. 4.1: the even time sum S of the other grid's u, then u_new = 2 S - u_old).
 //
-// One half step maps a cell's 8 corner nodes (u: 64, v: 27 coefficients each) linearly
-// to its output node (Sec. 3.1: interpolate, sum the Taylor series in time, evaluate at
-// the centre).  The host composes that map into a matrix (cellmap.cpp).  Because the
+// One half step maps a cell's 8 corner nodes (u: 64, v: 27 coefficients each; the
+// conservative method u only) linearly to its output node (Sec. 3.1: interpolate, sum the
+// Taylor series in time, evaluate at the centre).  The host composes that map into a matrix (cellmap.cpp).  Because the
 // Hermite operators are symmetric under reflection about the cell centre and the time
 // sums keep the parity of every index, corner s = (s_x, s_y, s_z) enters output a with
 // (-1)^(sum_i s_i (a_i + l_i)) times corner 0's entry.  So the corners are first combined
@@ -39,9 +40,6 @@ namespace {
 
 constexpr int CX = 4;                         // cells along x of a workgroup's column
 constexpr int NXL = CX + 1;
-constexpr int NI = 91;                        // inputs per node: u 64 + v 27
-constexpr int KS = 23;                        // K-steps of 4 (91 inputs padded to 92)
-constexpr int TL = 92;                        // stride of one butterfly sum over l
 // LDS strides, chosen for its 32 banks of 4 bytes, which serve a 32-bit access of a wave
 // 32 lanes at a time and a 64-bit access 16 lanes at a time.  Every LDS pass of the
 // kernel puts the 16 cells of a product group (4 x 4 in x, y) on distinct banks:
@@ -52,12 +50,20 @@ constexpr int TL = 92;                        // stride of one butterfly sum ove
 //   * butterfly sums [cell][p][k] (k: the K position of the input): cell stride = 2
 //     (mod 32) in FP32 (K positions 4 ks and 4 ks + 1 of a product's operand pass on the
 //     even and odd banks), odd in FP64
-template <typename T>
-constexpr int ndx() { return sizeof(T) == 4 ? 98 : 97; }
-template <typename T>
-constexpr int ndy() { return sizeof(T) == 4 ? 520 : 500; }
-template <typename T>
-constexpr int tsz() { return sizeof(T) == 4 ? 738 : 737; }
+// Dissipative method: 91 inputs per node (u 64, v 27) in 23 K-steps (K position 91 reads
+// a zero slot of every node), 91 outputs; conservative method (Sec. 4.1): the even time
+// sum S of the u inputs, 64 inputs in 16 K-steps, 64 outputs, u_new = 2 S - u_old.
+template <typename T, bool CONS>
+struct Shape {
+    static constexpr int NI = CONS ? 64 : 91;                 // inputs per node
+    static constexpr int KS = CONS ? 16 : 23;                 // K-steps of 4
+    static constexpr int TL = 4 * KS;                         // K positions
+    static constexpr int NV = CONS ? 0 : 27;                  // v outputs per cell
+    static constexpr int SX = CONS ? (sizeof(T) == 4 ? 66 : 65) : (sizeof(T) == 4 ? 98 : 97);
+    static constexpr int SY = CONS ? (sizeof(T) == 4 ? 360 : 340) : (sizeof(T) == 4 ? 520 : 500);
+    static constexpr int TSZ = CONS ? (sizeof(T) == 4 ? 514 : 513) : (sizeof(T) == 4 ? 738 : 737);
+    static_assert(SX >= TL && SY >= (CX + 1) * SX && TSZ >= 8 * TL, "strides too small");
+};
 constexpr int OUS = 68;                       // cell stride of the staged u outputs
 
 
@@ -87,8 +93,9 @@ struct Mf<double> {
 //   bk[4 KS]       K positions of the butterfly passes, two per pass of 16 cells: an even
 //                  and an odd position whose inputs have indices of opposite parity
 //   tr[8][16]      output of (class, row): -1 unused, else is_v << 12 | flat alpha index
-template <typename T>
+template <typename T, bool CONS>
 struct CTables {
+    static constexpr int KS = Shape<T, CONS>::KS;
     T ta[8][KS][64];
     int tb[8][KS][4];
     int tr[8][16];
@@ -97,12 +104,13 @@ struct CTables {
 };
 
 // column of CX x CY cells: NC cells per layer
-template <typename T, int CY>
+template <typename T, int CY, bool CONS>
 struct CShared {
+    using S = Shape<T, CONS>;
     static constexpr int NC = CX * CY, NNODE = NXL * (CY + 1);
-    alignas(16) T tsum[NC * tsz<T>()];
-    alignas(16) T out[NC * (OUS + 27)];
-    T nd[CY * ndy<T>() + NXL * ndx<T>()];
+    alignas(16) T tsum[NC * S::TSZ];
+    alignas(16) T out[NC * (OUS + S::NV)];
+    T nd[CY * S::SY + NXL * S::SX];
 };
 
 struct Map1 {
@@ -151,11 +159,13 @@ __host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
 // workgroups of 8 waves per CU, i.e. 4 waves per SIMD, which caps the registers at 128
 // per lane (the LDS footprint allows two workgroups); FP64: one workgroup, 2 waves per
 // SIMD (at most 256 registers)
-template <typename T, int CY, int NT>
-__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs a, int tz, const CTables<T>* __restrict__ tabs)
+template <typename T, int CY, int NT, bool CONS>
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs a, int tz, const CTables<T, CONS>* __restrict__ tabs)
 {
     using MF = Mf<T>;
-    using SH = CShared<T, CY>;
+    using SH = CShared<T, CY, CONS>;
+    using S = Shape<T, CONS>;
+    constexpr int NI = S::NI, KS = S::KS, TL = S::TL;
     constexpr int NC = SH::NC, NNODE = SH::NNODE, NW = NT / 64;
     // the 8 classes x NC/16 cell groups of a layer's products over the waves: a wave
     // keeps CPW classes (A operands in registers) and applies each to GPW groups
@@ -174,11 +184,11 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
     const T* __restrict__ gu = (const T*)a.u_in;
     const T* __restrict__ gv = (const T*)a.v_in;
 
-    constexpr int TSZ = tsz<T>();
-    // slot 91 of every node (the padding input) holds zero, so the butterflies write
-    // zero sums for it; the stash never writes it
-    constexpr int SX = ndx<T>(), SY = ndy<T>();
-    for (int i = tid; i < NNODE; i += NT) sh.nd[(i % NXL) * SX + (i / NXL) * SY + 91] = T(0);
+    constexpr int TSZ = S::TSZ, SX = S::SX, SY = S::SY;
+    // dissipative: slot 91 of every node (the padding input) holds zero, so the
+    // butterflies write zero sums for it; the stash never writes it
+    if constexpr (!CONS)
+        for (int i = tid; i < NNODE; i += NT) sh.nd[(i % NXL) * SX + (i / NXL) * SY + 91] = T(0);
 
     auto grp_of = [&](int g) { return NW >= 8 ? wave / 8 + (NW / 8) * g : g; };
     // the wave's classes: A operands, B offsets, output targets (registers)
@@ -232,7 +242,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
         // stay in flight until the stash of the next pass
 #pragma unroll
         for (int i = 0; i < NLOAD; ++i) {
-            const T* src = (ld_msk[i] & 4) ? gu + zn * 64 : gv + zn * 27;
+            const T* src = (CONS || (ld_msk[i] & 4)) ? gu + zn * 64 : gv + zn * 27;
             rl[i] = src[ld_off[i]];
         }
     };
@@ -253,12 +263,39 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
 
     // ---- staged outputs of a cell layer, stored coalesced ----
     const int nlayers = cz1 - cz0 + 1;
+    // conservative: the old level of the cell layer stored in the next pass, loaded at the
+    // end of this pass's loads so that its latency overlaps the layer's work
+    constexpr int NSU = CONS ? (NC * 64 + NT - 1) / NT : 1;
+    T ov[NSU];
+    long long ogi[NSU];
+    auto old_fetch = [&](int cz) {
+        const T* __restrict__ old_u = (const T*)a.u_old;
+#pragma unroll
+        for (int k = 0; k < NSU; ++k) {
+            const int i = tid + k * NT, c = i >> 6, coef = i & 63;
+            const int gx = x0 + c % CX, gy = y0 + c / CX;
+            ogi[k] = -1;
+            if (i >= NC * 64 || gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
+            ogi[k] = (gx + (long long)a.ext_to[0] * gy + (long long)a.ext_to[0] * a.ext_to[1] * cz) * 64 + coef;
+            ov[k] = old_u[ogi[k]];
+        }
+    };
     T* const ou_base = sh.out;
     T* const ov_base = sh.out + NC * OUS;
     const long long plane_to = (long long)a.ext_to[0] * a.ext_to[1];
     auto store_layer = [&](int cz) {
         T* __restrict__ out_u = (T*)a.u_out;
         T* __restrict__ out_v = (T*)a.v_out;
+        if constexpr (CONS) {
+            // u_new = 2 S - u_old, the old values loaded one pass earlier (old_fetch)
+            (void)cz;
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) {
+                const int i = tid + k * NT, c = i >> 6, coef = i & 63;
+                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * ou_base[c * OUS + coef] - ov[k];
+            }
+            return;
+        }
         for (int i = tid; i < NC * 64; i += NT) {
             const int c = i >> 6, coef = i & 63;
             const int gx = x0 + c % CX, gy = y0 + c / CX;
@@ -288,6 +325,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
         __syncthreads();
         if (step >= 2) store_layer(cz0 + step - 2);
         if (step + 1 < nlayers) fetch(cz0 + off + step + 1);
+        if constexpr (CONS)
+            if (step >= 1) old_fetch(cz0 + step - 1); // the cell layer computed in this pass
 
         // ---- 2. butterflies: T_pxy[l] of this layer (pxy = px + 2 py), combined with
         //      the lower layer's into S_p[l], stored at the input's K position kp; 32
@@ -374,18 +413,21 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
 // ---------------------------------------------------------------------------
 // host: tables and launch
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool CONS>
 hipError_t create(const ProblemDesc& D, void** out)
 {
+    using S = Shape<T, CONS>;
+    constexpr int NI = S::NI, KS = S::KS, TL = S::TL;
+    using Tab = CTables<T, CONS>;
     std::vector<double> G;
     int n_in = 0, n_out = 0;
-    hw_cell_map(D, G, n_in, n_out); // [8 * 91][91], corner 0's rows first
+    hw_cell_map(D, G, n_in, n_out); // [8 * NI][NI], corner 0's rows first
     if (n_out != NI || n_in != 8 * NI) return hipErrorInvalidValue;
     // K order of the inputs (the products accumulate in it, in the element type):
     // higher-degree coefficients first.  On smooth data those are the smaller terms, so
     // the running sums stay small until the large low-degree terms enter; in FP32 that
-    // order leaves several times less rounding error than the natural one.  Position
-    // 91 is the padding input.
+    // order leaves several times less rounding error than the natural one.  Dissipative:
+    // position 91 is the padding input.
     int perm[4 * KS];
     {
         int k = 0;
@@ -397,12 +439,13 @@ hipError_t create(const ProblemDesc& D, void** out)
             }
         while (k < 4 * KS) perm[k++] = -1;
     }
-    CTables<T>* h = new CTables<T>();
+    Tab* h = new Tab();
     std::memset(h, 0, sizeof *h);
     for (int k = 0; k < 4 * KS; ++k) h->kl[k] = perm[k] < 0 ? 91 : perm[k];
     // butterfly pairs: (even K position, odd K position) with inputs of opposite index
     // parity.  There are as many even positions holding even inputs as odd positions
-    // holding odd ones (46 of each parity among both), so the pairs always exist.
+    // holding odd ones (half the positions hold inputs of each parity), so the pairs
+    // always exist.
     {
         std::vector<int> cls[4]; // [position parity][input parity]
         for (int k = 0; k < 4 * KS; ++k) cls[2 * (k & 1) + (h->kl[k] & 1)].push_back(k);
@@ -422,13 +465,14 @@ hipError_t create(const ProblemDesc& D, void** out)
     }
     for (int q = 0; q < 8; ++q) {
         const int qx = q & 1, qy = (q >> 1) & 1, qz = (q >> 2) & 1;
-        // rows: the 8 u outputs of the class, then its v outputs
+        // rows: the 8 u outputs of the class, then (dissipative) its v outputs
         int rows[16], nrow = 0;
         for (int o = 0; o < 8; ++o)
             rows[nrow++] = (qx + 2 * (o & 1)) + 4 * (qy + 2 * ((o >> 1) & 1)) + 16 * (qz + 2 * (o >> 2));
-        for (int az = qz; az <= 2; az += 2)
-            for (int ay = qy; ay <= 2; ay += 2)
-                for (int ax = qx; ax <= 2; ax += 2) rows[nrow++] = 64 + ax + 3 * ay + 9 * az;
+        if (!CONS)
+            for (int az = qz; az <= 2; az += 2)
+                for (int ay = qy; ay <= 2; ay += 2)
+                    for (int ax = qx; ax <= 2; ax += 2) rows[nrow++] = 64 + ax + 3 * ay + 9 * az;
         for (int r = 0; r < 16; ++r)
             h->tr[q][r] = r < nrow ? (rows[r] >= 64 ? 0x1000 | (rows[r] - 64) : rows[r]) : -1;
         for (int ks = 0; ks < KS; ++ks) {
@@ -450,8 +494,8 @@ hipError_t create(const ProblemDesc& D, void** out)
         }
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(CTables<T>));
-    if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(CTables<T>), hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc(&p, sizeof(Tab));
+    if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(Tab), hipMemcpyHostToDevice);
     delete h;
     if (e != hipSuccess) {
         if (p) (void)hipFree(p);
@@ -461,11 +505,11 @@ hipError_t create(const ProblemDesc& D, void** out)
     return hipSuccess;
 }
 
-template <typename T, int CY, int NT>
+template <typename T, int CY, int NT, bool CONS>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
-    const size_t lds = sizeof(CShared<T, CY>);
-    auto kern = k_cmap3d<T, CY, NT>;
+    const size_t lds = sizeof(CShared<T, CY, CONS>);
+    auto kern = k_cmap3d<T, CY, NT, CONS>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // z-chunks of 64 cell layers, doubled while at least 2048 workgroups remain (each
@@ -475,7 +519,7 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
     while (tz < a.ext_to[2] && (int64_t)tiles * ((a.ext_to[2] + 2 * tz - 1) / (2 * tz)) >= 2048) tz *= 2;
     const int chunks = (a.ext_to[2] + tz - 1) / tz;
     hipLaunchKernelGGL(kern, dim3(tiles, chunks), dim3(NT), lds, st, a, tz,
-                       static_cast<const CTables<T>*>(a.tables));
+                       static_cast<const CTables<T, CONS>*>(a.tables));
     return hipGetLastError();
 }
 
@@ -484,20 +528,22 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
 hipError_t hw_cmap3d_tables_create(const ProblemDesc& D, bool fp64, void** out)
 {
     *out = nullptr;
-    if (D.d != 3 || D.m != 3 || (D.variant != HWV_DISS_FULL && D.variant != HWV_DISS_SIMPLE))
-        return hipErrorInvalidValue;
-    return fp64 ? create<double>(D, out) : create<float>(D, out);
+    if (D.d != 3 || D.m != 3) return hipErrorInvalidValue;
+    if (D.variant == HWV_CONS) return fp64 ? create<double, true>(D, out) : create<float, true>(D, out);
+    if (D.variant != HWV_DISS_FULL && D.variant != HWV_DISS_SIMPLE) return hipErrorInvalidValue;
+    return fp64 ? create<double, false>(D, out) : create<float, false>(D, out);
 }
 
 hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
 {
     if (!a.tables) return hipErrorInvalidValue;
+    if (a.cons && !a.u_old) return hipErrorInvalidValue;
     for (int i = 0; i < 3; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;
     // 4 x 4-cell columns, 512 threads: one class and one group of 16 cells per wave.
-    // FP32: 63 KB of LDS and at most 128 registers, so two workgroups share a CU (four
-    // waves per SIMD) and one's products overlap the other's butterflies (5% faster than
-    // one 4 x 8-cell workgroup of 1024 threads); FP64: 125 KB, one workgroup per CU (two
-    // waves per SIMD)
-    return fp64 ? launch<double, 4, 512>(a, st) : launch<float, 4, 512>(a, st);
+    // FP32: 62 KB (dissipative) / 46 KB (conservative) of LDS and at most 128 registers:
+    // two workgroups per CU, four waves per SIMD; FP64: 123 / 92 KB, one workgroup per CU
+    // (two waves per SIMD)
+    if (a.cons) return fp64 ? launch<double, 4, 512, true>(a, st) : launch<float, 4, 512, true>(a, st);
+    return fp64 ? launch<double, 4, 512, false>(a, st) : launch<float, 4, 512, false>(a, st);
 }

@@ -214,7 +214,8 @@ def test_graph_advance_equals_plain_launches_bitwise(prec):
 
 
 @pytest.mark.parametrize("d,m,bc", [(2, 2, W.PERIODIC), (2, 3, W.DIRICHLET), (1, 4, W.NEUMANN),
-                                    (3, 1, W.PERIODIC), (2, 4, W.DIRICHLET)])
+                                    (3, 1, W.PERIODIC), (2, 4, W.DIRICHLET), (3, 3, W.NEUMANN),
+                                    (3, 3, W.PERIODIC)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_energy_matches_oracle_and_is_conserved(d, m, bc, prec):
     """hw_energy (FP64 accumulation, in both state precisions) against the oracle's
@@ -393,6 +394,27 @@ def test_long_columns_3d_m3_sampled(prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_3d_cons_m3_sampled(prec):
+    """The conservative method in 3-D, m = 3, on the composed-map kernel: 256^3 periodic
+    and 96 x 80 x 200 cells with Dirichlet / Neumann / periodic walls (z-chunks of the
+    column walk), random data on both grids; both grids, sampled (wall nodes included)."""
+    B = _B()
+    precision = B.HW_FP64 if prec == "fp64" else B.HW_FP32
+    for n, bc, seed in (([256, 256, 256], [W.PERIODIC] * 3, 21),
+                        ([96, 80, 200], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], 22)):
+        _log(f"[full-size] 3-D conservative m=3 n={n} bc={bc} {prec}")
+        spec = W.make_spec(3, 3, n, 0.0, [1.0, 0.9, 1.1], 1.0, cfl=0.9, bc=bc, method=W.CONSERVATIVE)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        up = torch.rand(spec.nodes(W.PRIMAL), 64, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        ud = torch.rand(spec.nodes(W.DUAL), 64, generator=g, device="cuda", dtype=torch.float64) * 2 - 1
+        for steps_half in (1, 2):
+            _sampled_check(spec, precision, 40, seed + steps_half, (up, ud), steps_half)
+        del up, ud
+        torch.cuda.empty_cache()
+
+
 def test_full_size_2d_cons_m4_sampled():
     """2048^2, m = 4, Dirichlet, conservative: both grids, wall nodes included."""
     B = _B()
@@ -449,6 +471,10 @@ COMPOSED_CASES = [(n, bc, W.DISS_FULL, 0) for n, bc in TILED_CASES] + [
     ([6, 4, 5], [W.NEUMANN, W.PERIODIC, W.DIRICHLET], W.DISS_SIMPLE, 0),
     ([5, 5, 4], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 7),
     ([4, 5, 6], [W.DIRICHLET, W.PERIODIC, W.PERIODIC], W.DISS_FULL, 8),
+    ([5, 4, 6], [W.PERIODIC, W.PERIODIC, W.PERIODIC], W.CONSERVATIVE, 0),
+    ([6, 5, 7], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], W.CONSERVATIVE, 0),
+    ([4, 9, 5], [W.NEUMANN, W.DIRICHLET, W.DIRICHLET], W.CONSERVATIVE, 0),
+    ([9, 3, 4], [W.PERIODIC, W.DIRICHLET, W.NEUMANN], W.CONSERVATIVE, 0),
 ]
 
 
@@ -458,7 +484,8 @@ COMPOSED_CASES = [(n, bc, W.DISS_FULL, 0) for n, bc in TILED_CASES] + [
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_composed_3d_m3_matches_oracle(n, bc, meth, stages, prec):
     """The composed-map 3-D m = 3 kernel (ragged tiles, every wall type, both half-step
-    directions, anisotropic h, both variants, truncated series) against the oracle."""
+    directions, anisotropic h, both dissipative variants, truncated series, and the
+    conservative method) against the oracle."""
     B = _B()
     _log(f"[composed] n={n} bc={bc} meth={meth} st={stages} {prec}")
     spec = W.make_spec(3, 3, n, 0.0, [1.0, 0.8, 0.9], 1.2, cfl=0.85, bc=bc, method=meth,

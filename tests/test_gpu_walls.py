@@ -2,7 +2,7 @@
 (eq. (wavequ)) through the library's hw_half_step_ext, against the oracle.
 
 Every kernel path is exercised: the problem's own fast kernel (dense in 2-D, composed
-map in 3-D m = 3) with homogeneous walls followed by the wall-data correction launch
+map in 3-D m = 3, both methods) with homogeneous walls followed by the wall-data correction launch
 over the wall cells, the generic kernel with the same correction, and the generic
 kernel carrying forcing and wall data in one launch.  Random data and random wall
 records (the oracle applies the same ghost rule to any records), both precisions:
@@ -41,6 +41,7 @@ CASES = [
     (3, 3, [5, 4, 6], [W.DIRICHLET, W.NEUMANN, W.DIRICHLET], W.DISS_FULL),
     (3, 3, [4, 5, 4], [W.PERIODIC, W.DIRICHLET, W.NEUMANN], W.DISS_SIMPLE),
     (3, 2, [4, 3, 5], [W.NEUMANN, W.PERIODIC, W.DIRICHLET], W.CONSERVATIVE),
+    (3, 3, [5, 4, 6], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], W.CONSERVATIVE),
 ]
 
 
