@@ -40,7 +40,7 @@ EXECUTED_FLOPS_PER_CELL = 2 * 11776 + 1460
 # matrix-core busy fraction of the same kernel from its counters (SQ_BUSY_CYCLES /
 # SQ_VALU_MFMA_BUSY_CYCLES pass), tied to the source it was measured on like the traffic
 MFMA_BUSY_RECORD = {
-    "source_sha256": "3f9b0996c5a38893020f5f8862a55bc5d57a4bbbdb0ca9e9f4f3961a3fbe97f8",
+    "source_sha256": "1ce499181a4509c3c764cbb3cb52e845ed978619014ff18a43b2f0a3a8f5e6b0",
     "busy_frac": 0.43,
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-sq_counters.md",
 }
@@ -53,9 +53,9 @@ MFMA_BUSY_RECORD = {
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "3f9b0996c5a38893020f5f8862a55bc5d57a4bbbdb0ca9e9f4f3961a3fbe97f8",
-    "fetch_bytes": 8690992039,  # FETCH_SIZE 4243769.5 KiB x 1048576/524303.0 (copy: 1 GiB read)
-    "write_bytes": 6174015685,  # WRITE_SIZE 6029312.2 KiB x 1048576/1048576.0 (copy: 1 GiB written)
+    "source_sha256": "1ce499181a4509c3c764cbb3cb52e845ed978619014ff18a43b2f0a3a8f5e6b0",
+    "fetch_bytes": 8693021732,  # FETCH_SIZE 4244760.1 KiB x 1048576/524302.9 (copy: 1 GiB read)
+    "write_bytes": 6174015541,  # WRITE_SIZE 6029312.1 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-hbm_bytes.md",
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_cmap3d.hip")
