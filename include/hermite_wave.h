@@ -259,8 +259,10 @@ const char* hw_last_error(void);
  * turns this off; HW_TUNE_CACHE=<file> keeps the choices across processes;
  * HW_TUNE_FORCE=<kernel>=<choice>[,...] imposes a choice, e.g. "dense=-64,dense_list=16").
  * For the 2-D dense kernels ("dense", "dense_list") a choice c > 0 is the per-lane gather
- * form with tiles of c x (256 / c) cells, c < 0 the LDS-staged form with tiles of
- * |c| x (256 / |c|) cells (|c| = 32 or 64).  The text is
+ * form with tiles of c x (256 / c) cells, c = -32 or -64 the LDS-staged form (whole node
+ * records in LDS) with tiles of |c| x (256 / |c|) cells, c = -1032 or -1064 the row-chunked
+ * staged form (one coefficient row of the tile's nodes in LDS at a time) with tiles 32 or
+ * 64 cells wide.  The text is
  * thread-local and valid until the next call from the same thread.  This is about the
  * implementation's launch configuration, not the method of the paper. */
 const char* hw_tuning_report(void);

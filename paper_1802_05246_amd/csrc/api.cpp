@@ -277,24 +277,30 @@ hw_status check_solver(const hw_solver* s)
 
 DenseArgs dense_args(const hw_solver* s, int k, int i);
 
-// A 2-D dense kernel variant as one tile code: tx > 0 is the per-lane gather form with
-// tiles of tx x (256 / tx) cells, tx < 0 the LDS-staged form with tiles of |tx| x (256 / |tx|)
+// A 2-D dense kernel variant as one tile code: c > 0 is the per-lane gather form with
+// tiles of c x (256 / c) cells, c = -32 / -64 the LDS-staged form (whole node records) with
+// tiles of |c| x (256 / |c|), c = -1032 / -1064 the row-chunked staged form with tiles
+// (|c| - 1000) wide
+int tile_width(int code) { return code > 0 ? code : (-code) % 1000; }
+int staged_form(int code) { return code > 0 ? 0 : (-code) / 1000 + 1; }
 void set_tile(DenseArgs& a, int code)
 {
-    a.tile_x = code < 0 ? -code : code;
-    a.staged = code < 0 ? 1 : 0;
+    a.tile_x = tile_width(code);
+    a.staged = staged_form(code);
 }
+// the list launch's variant argument (0, 32 / 64, 1032 / 1064)
 int staged_width(int code) { return code < 0 ? -code : 0; }
 
 // a tile code the dense kernels can launch (a choice imposed through HW_TUNE_FORCE may not be)
 hw_status check_tile(int code, int m, bool cons, bool fp64)
 {
     if (code > 0 && code <= 256 && 256 % code == 0) return HW_OK;
-    if ((code == -32 || code == -64) && hw_dense_staged_fits(m, cons, fp64, -code)) return HW_OK;
+    if (code < 0 && -code < 2000 && (tile_width(code) == 32 || tile_width(code) == 64) &&
+        hw_dense_staged_fits(m, cons, fp64, tile_width(code), staged_form(code)))
+        return HW_OK;
     return fail(HW_EUNSUPPORTED, "dense tile choice %d not available for m=%d method=%s %s", code, m,
                 cons ? "conservative" : "dissipative", fp64 ? "fp64" : "fp32");
 }
-int tile_width(int code) { return code < 0 ? -code : code; }
 
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
 {
@@ -380,15 +386,15 @@ DenseArgs dense_args(const hw_solver* s, int k, int i)
     return a;
 }
 
-// Tiles of tx x (256 / tx) cells covering the grid written in `phase` by the members of
-// a class (member j is problem probs[j]).
-void class_tiles(const hw_solver* s, int phase, const std::vector<int>& probs, int tx, std::vector<int4>& tiles)
+// Tiles of the variant `code` (tile_width x 256 / tile_width cells) covering the grid
+// written in `phase` by the members of a class (member j is problem probs[j]).
+void class_tiles(const hw_solver* s, int phase, const std::vector<int>& probs, int code, std::vector<int4>& tiles)
 {
     const int np = (int)s->probs.size();
+    const int tx = tile_width(code), h = 256 / tx;
     tiles.clear();
     for (int j = 0; j < (int)probs.size(); ++j) {
         const ProblemDesc& D = s->h_descs[(size_t)(phase * 2) * np + probs[j]];
-        const int h = 256 / tx;
         for (int y = 0; y < D.ext_to[1]; y += h)
             for (int x = 0; x < D.ext_to[0]; x += tx) tiles.push_back(make_int4(j, x, y, 0));
     }
@@ -426,7 +432,7 @@ void zero_state(hw_solver* s, int i)
     }
 }
 
-const std::vector<int> kTileCandidates = {16, 32, 64, 128, -32, -64};
+const std::vector<int> kTileCandidates = {16, 32, 64, 128, -32, -64, -1032, -1064};
 
 // Tile width of the single-problem dense kernel for 2-D problem i (autotuned).
 hw_status tune_dense_single(hw_solver* s, int i)
@@ -482,7 +488,7 @@ hw_status setup_batch_classes(hw_solver* s)
             int4* dt = nullptr;
             auto time_us = [&](int cand) -> double {
                 std::vector<int4> tl;
-                class_tiles(s, 0, std::vector<int>{C.probs[rep]}, tile_width(cand), tl);
+                class_tiles(s, 0, std::vector<int>{C.probs[rep]}, cand, tl);
                 for (auto& t : tl) t.x = rep;  // the list names the member's own descriptor
                 if (upload_args(cand) != hipSuccess) return -1.0;
                 if (dt) (void)hipFree(dt);
@@ -505,7 +511,7 @@ hw_status setup_batch_classes(hw_solver* s)
         if (upload_args(C.tx) != hipSuccess) return fail(HW_EHIP, "batch descriptor upload failed");
         for (int ph = 0; ph < 2; ++ph) {
             std::vector<int4> tl;
-            class_tiles(s, ph, C.probs, tile_width(C.tx), tl);
+            class_tiles(s, ph, C.probs, C.tx, tl);
             C.ntiles[ph] = (int)tl.size();
             if (hipMalloc((void**)&C.tiles[ph], std::max<size_t>(tl.size(), 1) * sizeof(int4)) != hipSuccess)
                 return fail(HW_ENOMEM, "batch work list allocation failed");

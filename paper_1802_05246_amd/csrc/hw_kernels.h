@@ -56,7 +56,8 @@ struct DenseArgs {
     const void* G;     // rows of corner 0 of the cell matrix: [n_in / 2^d][n_out], input-major
     int64_t n_cells;
     int tile_x = 64;   // 2-D: cells along x of a workgroup's tile of 256 (a divisor of 256)
-    int staged = 0;    // 2-D: 1 = the LDS-staged form (tile_x 32 or 64), 0 = per-lane gathers
+    int staged = 0;    // 2-D: 0 = per-lane gathers; LDS-staged forms (tile_x 32 or 64): 1 = whole
+                       // node records, 2 = one coefficient row of every node at a time
 };
 bool hw_dense_supported(int d, int m, int method, int precision);
 
@@ -68,12 +69,14 @@ void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
 // Persistent launch over the tiles of many 2-D problems of one (m, method): probs[i] are
 // their descriptors, tiles {problem i, x0, y0, 0} of tile_x x (256 / tile_x) cells;
-// staged_tx = 32 or 64 selects the LDS-staged form with tiles of that width, 0 the
+// staged_tx = 32 or 64 selects the LDS-staged form (whole node records) with tiles of
+// that width, 1032 or 1064 the row-chunked staged form with tiles 32 or 64 wide, 0 the
 // per-lane gather form.
 hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
                                 bool fp64, int staged_tx, hipStream_t st);
-// whether the LDS-staged form with tiles tx cells wide fits a CU's LDS for (m, method, precision)
-bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx);
+// whether staged form `form` (1 or 2) with tiles tx cells wide fits a CU's LDS for
+// (m, method, precision)
+bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form);
 
 // Composed-map MFMA kernel for the 3-D dissipative and conservative methods, m = 3 (kernel_cmap3d.hip):
 // the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are

@@ -11,6 +11,8 @@
 // and u_new = 2 S - u_old.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "hw_kernels.h"
 
 namespace {
@@ -411,16 +413,176 @@ __device__ void dense_tile_staged(const DenseArgs& a, int x0, int y0, T* __restr
             std::integral_constant<int, NV>{});
 }
 
+// Row-chunked staged form (for large nodes, whose whole records would not fit in LDS): the
+// tile's nodes are staged one coefficient row at a time (the MD values l_x = 0..MD-1 of
+// one l_y of the u or v block: contiguous in the node record), double-buffered, each
+// chunk's loads issued before the previous chunk is computed; the lanes accumulate every
+// output over all chunks in registers and store their cell's outputs directly.
+template <typename T, int MU, bool CONS>
+struct ChunkShape {
+    static constexpr int MV = CONS ? 0 : MU - 1;
+    static constexpr int CW = MU | 1; // odd node stride of a chunk row in LDS
+    static constexpr size_t lds_words(int tx) { return (size_t)2 * (tx + 1) * (DENSE_BLOCK / tx + 1) * CW; }
+};
+
 template <typename T, int MU, bool CONS, int TX>
+__device__ void dense_tile_chunked(const DenseArgs& a, int x0, int y0, T* __restrict__ sm)
+{
+    using CS = ChunkShape<T, MU, CONS>;
+    constexpr int TY = DENSE_BLOCK / TX, NXT = TX + 1, NYT = TY + 1, CW = CS::CW;
+    constexpr int MV = CS::MV, NU = MU * MU, NV = MV * MV, NO = NU + NV, BUF = NYT * NXT * CW;
+    constexpr int SU = (NXT * MU + DENSE_BLOCK - 1) / DENSE_BLOCK;         // slots per row, u chunks
+    constexpr int SV = MV > 0 ? (NXT * MV + DENSE_BLOCK - 1) / DENSE_BLOCK : 1; // v chunks
+    constexpr int SL = SU > SV ? SU : SV;
+    typedef const __attribute__((address_space(1))) T* GIn;
+    typedef __attribute__((address_space(1))) T* GOut;
+    typedef const __attribute__((address_space(4))) T* ConstPtr;
+    const int tid = threadIdx.x;
+    const int off = a.to_grid == 1 ? 0 : -1;
+    const int ex0 = a.ext_from[0], ex1 = a.ext_from[1];
+    const GIn uin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
+    const GIn vin = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
+
+    // node rows of the tile (shared by every chunk) and, per block, the thread's slots
+    int rowbase[NYT];
+    bool rowghost[NYT];
+#pragma unroll
+    for (int r = 0; r < NYT; ++r) {
+        bool g;
+        rowbase[r] = wrap_node(y0 + r + off, ex1, a.bc[1], g) * ex0;
+        rowghost[r] = g;
+    }
+    struct Slots {
+        int node[SL], dst[SL], lx[SL];
+        bool on[SL], negx[SL];
+    };
+    auto slots_of = [&](auto md_tag) {
+        constexpr int MD = decltype(md_tag)::value, PER_ROW = NXT * MD;
+        Slots sl;
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            const int e = tid + k * DENSE_BLOCK;
+            const int xx = e / MD, lx = e - xx * MD;
+            bool gxg;
+            sl.node[k] = wrap_node(x0 + xx + off, ex0, a.bc[0], gxg);
+            sl.dst[k] = xx * CW + lx;
+            sl.lx[k] = lx;
+            sl.on[k] = e < PER_ROW;
+            sl.negx[k] = gxg && flips(a.bc[0], lx);
+        }
+        return sl;
+    };
+    const Slots su = slots_of(std::integral_constant<int, MU>{});
+    const Slots sv = slots_of(std::integral_constant<int, (MV > 0 ? MV : 1)>{});
+
+    T v[NYT][SL];
+    // chunk loads into registers (row ly of the u or v block)
+    auto load = [&](bool ublk, int ly) {
+        const GIn src = ublk ? uin : vin;
+        const int md = ublk ? MU : MV, nb = ublk ? NU : NV;
+        const Slots& sl = ublk ? su : sv;
+#pragma unroll
+        for (int r = 0; r < NYT; ++r)
+#pragma unroll
+            for (int k = 0; k < SL; ++k)
+                if (sl.on[k]) v[r][k] = src[((int64_t)rowbase[r] + sl.node[k]) * nb + ly * md + sl.lx[k]];
+    };
+    auto put = [&](bool ublk, int ly, T* buf) {
+        const Slots& sl = ublk ? su : sv;
+        const bool yflip = flips(a.bc[1], ly);
+#pragma unroll
+        for (int r = 0; r < NYT; ++r)
+#pragma unroll
+            for (int k = 0; k < SL; ++k)
+                if (sl.on[k]) {
+                    const bool neg = sl.negx[k] != (rowghost[r] && yflip);
+                    buf[r * NXT * CW + sl.dst[k]] = neg ? -v[r][k] : v[r][k];
+                }
+    };
+
+    const int tx = tid % TX, ty = tid / TX;
+    const ConstPtr G = reinterpret_cast<ConstPtr>(reinterpret_cast<uintptr_t>(a.G));
+    T acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = T(0);
+    auto opar = [](int o, int i) {
+        const int md = o < NU ? MU : MV, oo = o < NU ? o : o - NU;
+        return (i == 0 ? oo % md : (oo / md) % md) & 1;
+    };
+    // products of one chunk: inputs l = in0 + MD ly + l_x
+    auto compute = [&](auto md_tag, int in0, int ly, const T* buf) {
+        constexpr int MD = decltype(md_tag)::value;
+        const T* __restrict__ n00 = buf + (ty * NXT + tx) * CW;
+        const bool ly_odd = (ly & 1) != 0;
+#pragma unroll
+        for (int lx = 0; lx < MD; ++lx) {
+            const T x00 = n00[lx], x10 = n00[CW + lx], x01 = n00[NXT * CW + lx], x11 = n00[(NXT + 1) * CW + lx];
+            const T p = x00 + x10, q = x00 - x10, r = x01 + x11, t = x01 - x11;
+            T Sv[4];
+            Sv[0] = ly_odd ? p - r : p + r;
+            Sv[1] = ly_odd ? q - t : q + t;
+            Sv[2] = ly_odd ? p + r : p - r;
+            Sv[3] = ly_odd ? q + t : q - t;
+            const ConstPtr g = G + (int64_t)(in0 + MD * ly + lx) * NO;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) acc[o] += g[o] * Sv[((opar(o, 0) + lx) & 1) + 2 * opar(o, 1)];
+        }
+    };
+
+    // chunks 0 .. MU-1: u rows, MU .. MU+MV-1: v rows; buffer c & 1
+    constexpr int NCH = MU + MV;
+    load(true, 0);
+#pragma unroll 1
+    for (int c = 0; c < NCH; ++c) {
+        T* buf = sm + (c & 1) * BUF;
+        const bool ublk = c < MU;
+        const int ly = ublk ? c : c - MU;
+        put(ublk, ly, buf);
+        if (c + 1 < NCH) load(c + 1 < MU, c + 1 < MU ? c + 1 : c + 1 - MU);
+        __syncthreads();
+        if (ublk) compute(std::integral_constant<int, MU>{}, 0, ly, buf);
+        else if constexpr (MV > 0) compute(std::integral_constant<int, (MV > 0 ? MV : 1)>{}, NU, ly, buf);
+    }
+
+    // outputs: each lane stores its cell's (conservative: old level read in chunks of 16
+    // before their stores)
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) return;
+    const int64_t cell = (int64_t)gy * a.ext_to[0] + gx;
+    const GOut __restrict__ uo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + cell * NU;
+    if constexpr (CONS) {
+        const GIn __restrict__ old = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old)) + cell * NU;
+        constexpr int CH = 16;
+#pragma unroll
+        for (int o0 = 0; o0 < NU; o0 += CH) {
+            T ov[CH];
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (o0 + j < NU) ov[j] = old[o0 + j];
+#pragma unroll
+            for (int j = 0; j < CH; ++j)
+                if (o0 + j < NU) uo[o0 + j] = T(2) * acc[o0 + j] - ov[j];
+        }
+    } else {
+        const GOut __restrict__ vo = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + cell * NV;
+#pragma unroll
+        for (int o = 0; o < NU; ++o) uo[o] = acc[o];
+#pragma unroll
+        for (int o = 0; o < NV; ++o) vo[o] = acc[NU + o];
+    }
+}
+
+template <typename T, int MU, bool CONS, int TX, int FORM>
 __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged(DenseArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tiles_x = (a.ext_to[0] + TX - 1) / TX;
     const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * (DENSE_BLOCK / TX);
-    dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+    if constexpr (FORM == 1) dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+    else dense_tile_chunked<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
 }
 
-template <typename T, int MU, bool CONS, int TX>
+template <typename T, int MU, bool CONS, int TX, int FORM>
 __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged_list(const DenseArgs* __restrict__ probs,
                                                                    const int4* __restrict__ tiles, int n_tiles)
 {
@@ -436,7 +598,8 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged_list(const DenseAr
         const int pi = __builtin_amdgcn_readfirstlane(tl.x);
         const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
         const DenseArgs a = probs[pi];
-        dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+        if constexpr (FORM == 1) dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+        else dense_tile_chunked<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
         __syncthreads(); // the next tile's staging overwrites the LDS
     }
 }
@@ -473,12 +636,18 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_list(const DenseArgs* __r
 // the staged form's LDS: at most the 160 KB of a CU
 constexpr size_t kMaxLds = 160 * 1024;
 
-template <typename T, int MU, bool CONS, int TX>
+template <typename T, int MU, bool CONS, int FORM>
+size_t staged_lds(int tx)
+{
+    return (FORM == 1 ? StagedShape<T, MU, CONS>::lds_words(tx) : ChunkShape<T, MU, CONS>::lds_words(tx)) * sizeof(T);
+}
+
+template <typename T, int MU, bool CONS, int TX, int FORM>
 hipError_t launch_staged(const DenseArgs& a, hipStream_t st)
 {
-    const size_t lds = StagedShape<T, MU, CONS>::lds_words(TX) * sizeof(T);
+    const size_t lds = staged_lds<T, MU, CONS, FORM>(TX);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = k_dense_staged<T, MU, CONS, TX>;
+    auto kern = k_dense_staged<T, MU, CONS, TX, FORM>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int blocks = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + DENSE_BLOCK / TX - 1) / (DENSE_BLOCK / TX));
@@ -490,9 +659,14 @@ template <typename T, int D, int MU, bool CONS>
 hipError_t launch(const DenseArgs& a, hipStream_t st)
 {
     if constexpr (D == 2) {
-        if (a.staged) {
-            if (a.tile_x == 32) return launch_staged<T, MU, CONS, 32>(a, st);
-            if (a.tile_x == 64) return launch_staged<T, MU, CONS, 64>(a, st);
+        if (a.staged == 1) {
+            if (a.tile_x == 32) return launch_staged<T, MU, CONS, 32, 1>(a, st);
+            if (a.tile_x == 64) return launch_staged<T, MU, CONS, 64, 1>(a, st);
+            return hipErrorInvalidValue;
+        }
+        if (a.staged == 2) {
+            if (a.tile_x == 32) return launch_staged<T, MU, CONS, 32, 2>(a, st);
+            if (a.tile_x == 64) return launch_staged<T, MU, CONS, 64, 2>(a, st);
             return hipErrorInvalidValue;
         }
     }
@@ -504,12 +678,12 @@ hipError_t launch(const DenseArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int MU, bool CONS, int TX>
+template <typename T, int MU, bool CONS, int TX, int FORM>
 hipError_t launch_staged_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, hipStream_t st)
 {
-    const size_t lds = StagedShape<T, MU, CONS>::lds_words(TX) * sizeof(T);
+    const size_t lds = staged_lds<T, MU, CONS, FORM>(TX);
     if (lds > kMaxLds) return hipErrorInvalidValue;
-    auto kern = k_dense_staged_list<T, MU, CONS, TX>;
+    auto kern = k_dense_staged_list<T, MU, CONS, TX, FORM>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(DENSE_BLOCK), lds, st, probs, tiles, n_tiles);
@@ -520,9 +694,14 @@ template <typename T, int MU, bool CONS>
 hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int staged_tx,
                        hipStream_t st)
 {
-    if (staged_tx == 32) return launch_staged_list<T, MU, CONS, 32>(probs, tiles, n_tiles, grid, st);
-    if (staged_tx == 64) return launch_staged_list<T, MU, CONS, 64>(probs, tiles, n_tiles, grid, st);
-    if (staged_tx != 0) return hipErrorInvalidValue;
+    switch (staged_tx) {
+    case 0: break;
+    case 32: return launch_staged_list<T, MU, CONS, 32, 1>(probs, tiles, n_tiles, grid, st);
+    case 64: return launch_staged_list<T, MU, CONS, 64, 1>(probs, tiles, n_tiles, grid, st);
+    case 1032: return launch_staged_list<T, MU, CONS, 32, 2>(probs, tiles, n_tiles, grid, st);
+    case 1064: return launch_staged_list<T, MU, CONS, 64, 2>(probs, tiles, n_tiles, grid, st);
+    default: return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((k_dense_list<T, MU, CONS>), dim3(grid), dim3(DENSE_BLOCK), 0, st, probs, tiles, n_tiles);
     return hipGetLastError();
 }
@@ -604,13 +783,19 @@ hipError_t dispatch(const DenseArgs& a, int d, int m, bool cons, hipStream_t st)
 
 } // namespace
 
-bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx)
+bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form)
 {
-    if (m < 0 || m > 6 || (!cons && m < 1) || (tx != 32 && tx != 64)) return false;
+    if (m < 0 || m > 6 || (!cons && m < 1) || (tx != 32 && tx != 64) || form < 1 || form > 2) return false;
     const int mu = m + 1, mv = cons ? 0 : m;
-    const size_t nip = (size_t)(mu * mu + mv * mv) | 1;
-    const size_t in = (size_t)(tx + 1) * (DENSE_BLOCK / tx + 1) * nip, out = (size_t)DENSE_BLOCK * nip;
-    return (in > out ? in : out) * (fp64 ? 8 : 4) <= kMaxLds;
+    const size_t nodes = (size_t)(tx + 1) * (DENSE_BLOCK / tx + 1);
+    size_t words;
+    if (form == 1) {
+        const size_t nip = (size_t)(mu * mu + mv * mv) | 1;
+        words = std::max(nodes * nip, (size_t)DENSE_BLOCK * nip);
+    } else {
+        words = 2 * nodes * (size_t)(mu | 1);
+    }
+    return words * (fp64 ? 8 : 4) <= kMaxLds;
 }
 
 hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
@@ -626,7 +811,8 @@ hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp6
 {
     if (!a.G || a.n_cells < 0) return hipErrorInvalidValue;
     if (d == 2 && (a.tile_x < 1 || a.tile_x > DENSE_BLOCK || DENSE_BLOCK % a.tile_x)) return hipErrorInvalidValue;
-    if (a.staged && (d != 2 || (a.tile_x != 32 && a.tile_x != 64))) return hipErrorInvalidValue;
+    if (a.staged && (d != 2 || a.staged < 1 || a.staged > 2 || (a.tile_x != 32 && a.tile_x != 64)))
+        return hipErrorInvalidValue;
     if (a.n_cells == 0) return hipSuccess;
     for (int i = 0; i < d; ++i)
         if (a.ext_to[i] < 1 || a.ext_from[i] < 1) return hipErrorInvalidValue;

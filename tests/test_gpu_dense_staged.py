@@ -1,7 +1,9 @@
 """The 2-D dense kernels in every launch variant the autotuner may choose, against the
-oracle: the per-lane gather form (tiles 16 and 128 cells wide) and the LDS-staged form
+oracle: the per-lane gather form (tiles 16 and 128 cells wide), the LDS-staged form
 (tiles 32 and 64 wide, corner nodes copied to LDS with coalesced loads, ghost nodes
-mirrored there, outputs stored through LDS).  The variant is imposed with HW_TUNE_FORCE,
+mirrored there, outputs stored through LDS; codes -32, -64) and the row-chunked staged
+form (one coefficient row of every node of the tile in LDS at a time, double-buffered;
+codes -1032, -1064).  The variant is imposed with HW_TUNE_FORCE,
 for the single-problem kernel ("dense") and the batched persistent kernel
 ("dense_list").  Grids span several tiles with ragged edges; every wall type, both
 methods, m = 1..6; same bars as the other parity tests."""
@@ -16,7 +18,7 @@ from test_gpu_parity import _log, _state, state_err
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-CODES = [16, 128, -32, -64]
+CODES = [16, 128, -32, -64, -1032, -1064]
 
 SINGLE = [
     # m, method, n, bc
@@ -35,12 +37,18 @@ def _id(c):
     return f"m{m}-meth{meth}-n{n[0]}x{n[1]}-bc{bc[0]}{bc[1]}"
 
 
-def _staged_fits(m, meth, prec, tx):
-    """Whether the staged form's LDS (node tile or output staging, odd strides) fits the
-    160 KB of a CU; the library refuses the other choices."""
+def _staged_fits(m, meth, prec, code):
+    """Whether a staged form's LDS fits the 160 KB of a CU (whole records: node tile or
+    output staging, odd strides; row chunks: two buffers of one odd-padded row per node);
+    the library refuses the other choices."""
+    tx = (-code) % 1000
     mu, mv = m + 1, (0 if meth == W.CONSERVATIVE else m)
-    nip = (mu * mu + mv * mv) | 1
-    words = max((tx + 1) * (256 // tx + 1) * nip, 256 * nip)
+    nodes = (tx + 1) * (256 // tx + 1)
+    if -code >= 1000:
+        words = 2 * nodes * (mu | 1)
+    else:
+        nip = (mu * mu + mv * mv) | 1
+        words = max(nodes * nip, 256 * nip)
     return words * (8 if prec == "fp64" else 4) <= 160 * 1024
 
 
@@ -65,7 +73,7 @@ def test_dense_variant_matches_oracle(case, code, prec, monkeypatch):
     monkeypatch.setenv("HW_TUNE_FORCE", f"dense={code}")
     spec = W.make_spec(2, m, n, 0.0, [1.0, 0.9], 1.1, cfl=0.9, bc=bc, method=meth)
     _log(f"[dense variant {code}] {_id(case)} {prec}")
-    if code < 0 and not _staged_fits(m, meth, prec, -code):
+    if code < 0 and not _staged_fits(m, meth, prec, code):
         with pytest.raises(B.HwError):
             B.Solver(spec, precision=B.HW_FP64 if prec == "fp64" else B.HW_FP32, kernel=B.HW_KERNEL_DENSE)
         _log("    refused (LDS)")
@@ -87,7 +95,7 @@ def test_batch_variant_matches_oracle(case, code, prec, monkeypatch):
     monkeypatch.setenv("HW_TUNE_FORCE", f"dense_list={code}")
     spec = W.make_spec(2, m, n, 0.0, [1.0, 0.9], 1.1, cfl=0.9, bc=bc, method=meth)
     _log(f"[batch variant {code}] {_id(case)} {prec}")
-    if code < 0 and not _staged_fits(m, meth, prec, -code):
+    if code < 0 and not _staged_fits(m, meth, prec, code):
         with pytest.raises(B.HwError):
             B.Solver(spec, precision=B.HW_FP64 if prec == "fp64" else B.HW_FP32, kernel=B.HW_KERNEL_BATCH)
         _log("    refused (LDS)")
@@ -97,7 +105,7 @@ def test_batch_variant_matches_oracle(case, code, prec, monkeypatch):
     assert err <= tol
 
 
-@pytest.mark.parametrize("code", [-32, -64])
+@pytest.mark.parametrize("code", [-32, -64, -1032, -1064])
 def test_staged_batch_of_mixed_problems_matches_gather_form(code, monkeypatch):
     """A mixed batch (several problems per (m, method) class, ragged sizes) through the
     staged persistent kernel equals the gather form to FP64 rounding."""
