@@ -262,7 +262,10 @@ const char* hw_last_error(void);
  * form with tiles of c x (256 / c) cells, c = -32 or -64 the LDS-staged form (whole node
  * records in LDS) with tiles of |c| x (256 / |c|) cells, c = -1032 or -1064 the row-chunked
  * staged form (one coefficient row of the tile's nodes in LDS at a time) with tiles 32 or
- * 64 cells wide.  The text is
+ * 64 cells wide, c = -2016 (m = 3..6 only) the composed-map form on the matrix cores
+ * (strips of 16 cells walking their cell rows; the four corner sums of each cell formed
+ * in LDS, the cell matrix applied as 16x16x4 products).  HW_TUNE_LOG=1 prints every
+ * candidate's time to stderr while it is measured.  The text is
  * thread-local and valid until the next call from the same thread.  This is about the
  * implementation's launch configuration, not the method of the paper. */
 const char* hw_tuning_report(void);

@@ -111,6 +111,7 @@ struct hw_solver {
     std::vector<char> dense;      // per problem: served by the per-lane dense kernel (d <= 2)
     std::vector<const void*> dense_G;  // per problem: its cell matrix in the state precision
     std::vector<void*> dense_alloc;    // the distinct cell matrices (problems with equal maps share)
+    std::vector<const void*> cm2_tabs; // per problem: tables of the 2-D composed-map form (or null)
     int64_t* gen_prefix = nullptr;     // prefix sums of the generic kernel's cells (dense problems: 0)
     int64_t gen_total[2]{};
     bool any_generic = true;
@@ -280,7 +281,8 @@ DenseArgs dense_args(const hw_solver* s, int k, int i);
 // A 2-D dense kernel variant as one tile code: c > 0 is the per-lane gather form with
 // tiles of c x (256 / c) cells, c = -32 / -64 the LDS-staged form (whole node records) with
 // tiles of |c| x (256 / |c|), c = -1032 / -1064 the row-chunked staged form with tiles
-// (|c| - 1000) wide
+// (|c| - 1000) wide, c = -2016 the composed-map form on the matrix cores (strips of 16
+// cells walking rows)
 int tile_width(int code) { return code > 0 ? code : (-code) % 1000; }
 int staged_form(int code) { return code > 0 ? 0 : (-code) / 1000 + 1; }
 void set_tile(DenseArgs& a, int code)
@@ -298,8 +300,34 @@ hw_status check_tile(int code, int m, bool cons, bool fp64)
     if (code < 0 && -code < 2000 && (tile_width(code) == 32 || tile_width(code) == 64) &&
         hw_dense_staged_fits(m, cons, fp64, tile_width(code), staged_form(code)))
         return HW_OK;
+    if (code == -2016 && hw_cmap2d_supported(m)) return HW_OK;
     return fail(HW_EUNSUPPORTED, "dense tile choice %d not available for m=%d method=%s %s", code, m,
                 cons ? "conservative" : "dissipative", fp64 ? "fp64" : "fp32");
+}
+
+// rows per strip of the composed-map form on one problem: long chunks (each re-reads one
+// node row) while the launch keeps at least 2048 workgroups
+int cmap2d_rows(const DenseArgs& a)
+{
+    const int strips = (a.ext_to[0] + 15) / 16;
+    int ry = 256;
+    while (ry > 16 && (int64_t)strips * ((a.ext_to[1] + ry - 1) / ry) < 2048) ry /= 2;
+    return ry;
+}
+
+// one 2-D dense launch in the form the descriptor names
+hipError_t launch_dense_any(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
+{
+    if (a.staged == 3) return hw_launch_cmap2d(a, m, cons, fp64, cmap2d_rows(a), st);
+    return hw_launch_dense(a, d, m, cons, fp64, st);
+}
+
+// one batched launch over a class's work list in the form its tile code names
+hipError_t launch_list_any(const DenseArgs* args, const int4* items, int n, int grid, int m, bool cons, bool fp64,
+                           int code, hipStream_t st)
+{
+    if (staged_form(code) == 3) return hw_launch_cmap2d_list(args, items, n, grid, m, cons, fp64, st);
+    return hw_launch_dense_list(args, items, n, grid, m, cons, fp64, staged_width(code), st);
 }
 
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
@@ -308,8 +336,8 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
     if (s->use_batch2d) {
         for (const auto& C : s->bclasses) {
             const size_t n = C.probs.size();
-            HIP_TRY(hw_launch_dense_list(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.grid,
-                                         C.m, C.cons, s->fp64, staged_width(C.tx), st));
+            HIP_TRY(launch_list_any(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.grid,
+                                    C.m, C.cons, s->fp64, C.tx, st));
         }
         return HW_OK;
     }
@@ -342,7 +370,7 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
             if (!s->dense[i]) continue;
             const ProblemDesc& D = s->h_descs[(size_t)(phase * 2 + q) * np + i];
             const DenseArgs a = dense_args(s, phase * 2 + q, i);
-            HIP_TRY(hw_launch_dense(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
+            HIP_TRY(launch_dense_any(a, s->d, D.m, D.variant == HWV_CONS, s->fp64, st));
         }
         if (!s->any_generic) return HW_OK;
         HIP_TRY(hw_launch_generic(s->d, s->fp64, s->descs + (size_t)(phase * 2 + q) * np,
@@ -383,6 +411,7 @@ DenseArgs dense_args(const hw_solver* s, int k, int i)
     a.G = s->dense_G[i];
     a.n_cells = D.n_out;
     set_tile(a, s->dense_tx.empty() ? 64 : s->dense_tx[i]);
+    a.cm2 = s->cm2_tabs.empty() ? nullptr : s->cm2_tabs[i];
     return a;
 }
 
@@ -393,6 +422,16 @@ void class_tiles(const hw_solver* s, int phase, const std::vector<int>& probs, i
     const int np = (int)s->probs.size();
     const int tx = tile_width(code), h = 256 / tx;
     tiles.clear();
+    if (staged_form(code) == 3) {
+        // composed-map form: strips of 16 cells over chunks of at most 64 cell rows
+        for (int j = 0; j < (int)probs.size(); ++j) {
+            const ProblemDesc& D = s->h_descs[(size_t)(phase * 2) * np + probs[j]];
+            for (int y = 0; y < D.ext_to[1]; y += 64)
+                for (int x = 0; x < D.ext_to[0]; x += 16)
+                    tiles.push_back(make_int4(j, x, y, std::min(y + 64, D.ext_to[1])));
+        }
+        return;
+    }
     for (int j = 0; j < (int)probs.size(); ++j) {
         const ProblemDesc& D = s->h_descs[(size_t)(phase * 2) * np + probs[j]];
         for (int y = 0; y < D.ext_to[1]; y += h)
@@ -432,7 +471,7 @@ void zero_state(hw_solver* s, int i)
     }
 }
 
-const std::vector<int> kTileCandidates = {16, 32, 64, 128, -32, -64, -1032, -1064};
+const std::vector<int> kTileCandidates = {16, 32, 64, 128, -32, -64, -1032, -1064, -2016};
 
 // Tile width of the single-problem dense kernel for 2-D problem i (autotuned).
 hw_status tune_dense_single(hw_solver* s, int i)
@@ -444,7 +483,7 @@ hw_status tune_dense_single(hw_solver* s, int i)
     auto time_us = [&](int cand) {
         DenseArgs a = dense_args(s, 0, i);
         set_tile(a, cand);
-        return time_launches([&](hipStream_t ts) { return hw_launch_dense(a, 2, P.p.m, cons, s->fp64, ts); });
+        return time_launches([&](hipStream_t ts) { return launch_dense_any(a, 2, P.p.m, cons, s->fp64, ts); });
     };
     s->dense_tx[i] = hw_tune_choose("dense", 2, P.p.m, P.p.method, s->fp64, hw_tune_size_class(P.nodes[1]),
                                     kTileCandidates, time_us);
@@ -498,8 +537,7 @@ hw_status setup_batch_classes(hw_solver* s)
                     return -1.0;
                 const int grid = (int)std::min<size_t>(tl.size(), 2048);
                 return time_launches([&](hipStream_t ts) {
-                    return hw_launch_dense_list(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64,
-                                                staged_width(cand), ts);
+                    return launch_list_any(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64, cand, ts);
                 });
             };
             C.tx = hw_tune_choose("dense_list", 2, C.m, C.cons ? HW_CONSERVATIVE : HW_DISS_FULL, s->fp64,
@@ -741,8 +779,9 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     if (!s->dense.empty()) {
         // cell matrices (problems with identical maps share one), and the generic kernel's
         // work list without the dense problems
-        std::map<std::vector<double>, void*> made;
+        std::map<std::vector<double>, void*> made, made2;
         s->dense_G.assign(count, nullptr);
+        s->cm2_tabs.assign(count, nullptr);
         for (int i = 0; i < count; ++i) {
             if (!s->dense[i]) continue;
             std::vector<double> G;
@@ -750,6 +789,21 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             hw_cell_map(s->h_descs[i], G, n_in, n_out);
             // the kernel uses corner 0's rows; the others follow by reflection symmetry
             G.resize((size_t)(n_in >> s->d) * n_out);
+            if (s->d == 2 && hw_cmap2d_supported(s->probs[i].p.m)) {
+                // tables of the composed-map form (its autotuner candidate)
+                auto it2 = made2.find(G);
+                if (it2 != made2.end()) {
+                    s->cm2_tabs[i] = it2->second;
+                } else {
+                    void* tabs = nullptr;
+                    if (hw_cmap2d_tables_create(G, s->probs[i].p.m, s->probs[i].p.method == HW_CONSERVATIVE, s->fp64,
+                                                &tabs) != hipSuccess)
+                        return cleanup(fail(HW_EHIP, "composed-map table setup failed"));
+                    s->dense_alloc.push_back(tabs);
+                    s->cm2_tabs[i] = tabs;
+                    made2.emplace(G, tabs);
+                }
+            }
             auto it = made.find(G);
             if (it != made.end()) {
                 s->dense_G[i] = it->second;

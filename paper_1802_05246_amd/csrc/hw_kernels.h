@@ -57,7 +57,9 @@ struct DenseArgs {
     int64_t n_cells;
     int tile_x = 64;   // 2-D: cells along x of a workgroup's tile of 256 (a divisor of 256)
     int staged = 0;    // 2-D: 0 = per-lane gathers; LDS-staged forms (tile_x 32 or 64): 1 = whole
-                       // node records, 2 = one coefficient row of every node at a time
+                       // node records, 2 = one coefficient row of every node at a time;
+                       // 3 = the composed-map form on the matrix cores (kernel_cmap2d.hip)
+    const void* cm2 = nullptr; // tables of the composed-map form (hw_cmap2d_tables_create)
 };
 bool hw_dense_supported(int d, int m, int method, int precision);
 
@@ -77,6 +79,17 @@ hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n
 // whether staged form `form` (1 or 2) with tiles tx cells wide fits a CU's LDS for
 // (m, method, precision)
 bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form);
+
+// Composed-map MFMA kernel for 2-D problems, m = 3..6, both methods (kernel_cmap2d.hip):
+// tables from corner 0's rows of the cell matrix (G0: [NI][NI], input-major, FP64); single
+// problems in strips of 16 cells walking chunks of ry cell rows, or a persistent launch
+// over a work list of strips {problem, x0, cy0, cy1} of many problems of one (m, method)
+// (the descriptors' cm2 fields name each problem's tables).
+bool hw_cmap2d_supported(int m);
+hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool cons, bool fp64, void** out);
+hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int ry, hipStream_t st);
+hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int grid, int m, bool cons,
+                                 bool fp64, hipStream_t st);
 
 // Composed-map MFMA kernel for the 3-D dissipative and conservative methods, m = 3 (kernel_cmap3d.hip):
 // the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are

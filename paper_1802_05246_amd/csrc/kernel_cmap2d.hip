@@ -1,0 +1,565 @@
+// Composed-map half-step kernel for 2-D problems on the matrix cores, nodal degree
+// m = 3..6, both methods (dissipative: u and v; conservative, Sec. 4.1: the even time sum
+// S of the other grid's u, u_new = 2 S - u_old), element type T = float or double.
+//
+// The half step of a cell is a linear map of its 4 corner nodes (NI = n_u [+ n_v]
+// coefficients each) to its output node, composed on the host (cellmap.cpp).  By the
+// reflection symmetry of the Hermite operators about the cell centre (kept by the time
+// sums), corner s = (s_x, s_y) enters output a with (-1)^(sum_i s_i (a_i + l_i)) times
+// corner 0's entry, so the corners are combined into the four sums
+// S_p[l] = sum_s (-1)^(p . s) x_s[l] (p = p_x + 2 p_y), and output a needs, for each input
+// l, only S_{pi(a) xor pi(l)}[l] (pi: the parity vector).  Grouped by the output parity
+// class q = pi(a), each class is a dense (rows of the class) x NI product with the
+// class's column of selected sums; its rows are cut into tiles of 16 ("chains"), each
+// applied to 16 cells at a time as a chain of 16x16x4 products.
+//
+// A workgroup (one wave per chain) owns a strip of 16 cells along x and walks a chunk of
+// its cell rows upwards in y, one node row of the input grid at a time:
+//   1. the row's 17 nodes, loaded into registers during the previous row, are stashed in
+//      LDS (ghost nodes outside non-periodic walls mirrored with the odd / even signs of
+//      Sec. 3.1.3); the cell row finished two rows ago is stored and the loads of the
+//      next node row are issued;
+//   2. butterflies: per cell and input l, T_px[l] = x(left)[l] +- x(right)[l] of this
+//      row, combined with those of the row below (kept in registers since the previous
+//      pass) into S_{px + 2 py}[l] = T_px(lower)[l] +- T_px(upper)[l], written to LDS;
+//   3. the chains' products (A: the chain's rows of the composed map, registers; B: the
+//      selected sums read from LDS), outputs staged in LDS for the coalesced stores.
+// LDS strides follow the 32 banks of 4 bytes served 32 lanes (b32) or 16 lanes (b64) at a
+// time: node stride = 2 (mod 32) in FP32 (the 16 cells of a butterfly pass on the 16 even
+// banks, the pass's second K position -- whose input index has the other parity -- on the
+// odd ones), 1 (mod 16) in FP64; sums' cell stride = 2 (mod 32) in FP32, odd in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "hw_kernels.h"
+
+namespace {
+
+constexpr int CX = 16;      // cells of a strip
+constexpr int NXN = CX + 1; // nodes of a row of a strip
+constexpr int MAXCH = 8;    // chains (row tiles over the 4 classes) at most
+
+// smallest v >= x with v = r (mod m)
+constexpr int up_to_residue(int x, int m, int r) { return x + ((r - x % m) % m + m) % m; }
+
+template <typename T, int MU, bool CONS>
+struct Shape2 {
+    static constexpr int MV = CONS ? 0 : MU - 1;
+    static constexpr int NU = MU * MU, NV = MV * MV, NI = NU + NV; // inputs = outputs per node
+    static constexpr int TL = (NI + 3) / 4 * 4;                    // K positions (padded)
+    static constexpr int KS = TL / 4;                              // K-steps of 4
+    static constexpr bool PAD = TL > NI;                           // padding reads slot NI or NI+1 (zero)
+    static constexpr int SX0 = NI + (PAD ? 2 : 0);                 // minimum node stride
+    static constexpr int SX = sizeof(T) == 4 ? up_to_residue(SX0, 32, 2) : up_to_residue(SX0, 16, 1);
+    static constexpr int TSZ0 = 4 * TL;
+    static constexpr int TSZ = sizeof(T) == 4 ? up_to_residue(TSZ0, 32, 2) : (TSZ0 | 1);
+    static constexpr int OS = (NI + 1) | 1; // cell stride of the staged outputs (slot NI: unused rows)
+    static_assert(SX >= SX0 && TSZ >= TSZ0 && OS > NI, "strides");
+    static_assert(sizeof(T) == 8 || (SX % 32 == 2 && TSZ % 32 == 2), "FP32 strides");
+    static_assert(sizeof(T) == 4 || (SX % 16 == 1 && TSZ % 2 == 1), "FP64 strides");
+};
+
+template <typename T>
+struct Mf2;
+template <>
+struct Mf2<float> {
+    typedef float vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(float a, float b, vec c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __host__ __device__ inline int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mf2<double> {
+    typedef double vec __attribute__((ext_vector_type(4)));
+    static __device__ inline vec mac(double a, double b, vec c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __host__ __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Tables of one problem:
+//   ta[ch][KS][64]  A operand of chain ch: entry (row i = lane % 16 of the chain's tile,
+//                   K position 4 ks + lane / 16)
+//   tb[ch][KS][4]   offset of the selected sum in a cell's block for (K-step, lane / 16):
+//                   p * TL + k, p = p_x + 2 p_y of the class and the input at K position k
+//   tr[ch][16]      output of the chain's row (index into the node's u | v block), -1 unused
+//   kl[TL]          input at K position k (padding positions: the zero slots NI, NI + 1,
+//                   whichever index parity keeps the butterfly pairs below complete)
+//   bk[TL]          K positions of the butterfly passes, pairs (even, odd) whose inputs have
+//                   indices of opposite parity
+//   nch             chains
+template <typename T, int MU, bool CONS>
+struct C2Tables {
+    using S = Shape2<T, MU, CONS>;
+    T ta[MAXCH][S::KS][64];
+    int tb[MAXCH][S::KS][4];
+    int tr[MAXCH][16];
+    int kl[S::TL];
+    int bk[S::TL];
+    int nch;
+};
+
+template <typename T, int MU, bool CONS>
+struct C2Shared {
+    using S = Shape2<T, MU, CONS>;
+    alignas(16) T tsum[CX * S::TSZ];
+    alignas(16) T out[CX * S::OS];
+    T nd[NXN * S::SX];
+};
+
+struct Map1 {
+    int j, ghost;
+};
+
+__device__ inline Map1 map_node(int gi, int ext, int bc)
+{
+    Map1 m;
+    m.ghost = 0;
+    if (bc == 0) {
+        int j = gi % ext;
+        if (j < 0) j += ext;
+        m.j = j;
+    } else if (gi < 0) {
+        m.j = 0;
+        m.ghost = 1;
+    } else if (gi >= ext) {
+        m.j = ext - 1;
+        m.ghost = 1;
+    } else {
+        m.j = gi;
+    }
+    return m;
+}
+
+// sign of coefficient l of a node mirrored across a wall of type bc (1: Dirichlet, odd
+// extension: (-1)^(l+1); 2: Neumann, even extension: (-1)^l)
+__host__ __device__ inline bool flips(int bc, int l) { return (bc == 1) ? ((l & 1) == 0) : ((l & 1) == 1); }
+
+// (l_x, l_y) of input c of a node (u block: MU x MU, then v block: MV x MV)
+template <int MU>
+__host__ __device__ inline void coef2(int c, int& lx, int& ly)
+{
+    if (c < MU * MU) {
+        lx = c % MU;
+        ly = c / MU;
+    } else {
+        const int v = c - MU * MU;
+        lx = v % (MU - 1);
+        ly = v / (MU - 1);
+    }
+}
+
+// One strip of 16 cells (x0 .. x0 + 15) over cell rows cy0 .. cy1 - 1 of problem a.
+template <typename T, int MU, bool CONS, int NT>
+__device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restrict__ tabs, int x0, int cy0, int cy1,
+                      unsigned char* smem_raw)
+{
+    using S = Shape2<T, MU, CONS>;
+    using SH = C2Shared<T, MU, CONS>;
+    using MF = Mf2<T>;
+    constexpr int NI = S::NI, NU = S::NU, NV = S::NV, KS = S::KS, TL = S::TL;
+    constexpr int SX = S::SX, TSZ = S::TSZ, OS = S::OS;
+    constexpr int NLOAD = (NXN * NI + NT - 1) / NT;
+    constexpr int NBF = (CX * TL + NT - 1) / NT;
+    SH& sh = *reinterpret_cast<SH*>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int off = a.to_grid == 1 ? 0 : -1; // input node of corner s = cell + off + s
+    typedef const __attribute__((address_space(1))) T* GIn;
+    typedef __attribute__((address_space(1))) T* GOut;
+    const GIn gu = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
+    const GIn gv = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
+
+    // the zero slots NI, NI + 1 of every node (padding inputs); never written by the stash
+    if constexpr (S::PAD)
+        for (int i = tid; i < 2 * NXN; i += NT) sh.nd[(i >> 1) * SX + NI + (i & 1)] = T(0);
+
+    // the wave's chain: A operands, B offsets, output targets
+    const int nch = tabs->nch;
+    const bool active = wave < nch;
+    const int ch = active ? wave : 0;
+    T ta[KS];
+    int tb[KS], rdst[4];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        ta[ks] = tabs->ta[ch][ks][lane];
+        tb[ks] = tabs->tb[ch][ks][lane >> 4];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = tabs->tr[ch][MF::row(lane, r)];
+        rdst[r] = o < 0 ? NI : o; // unused rows write the spare slot NI of the cell
+    }
+
+    // node loads: slot i = element tid + i NT of the row's 17 x NI block; the x part and
+    // the x ghost sign are fixed per strip
+    const int ex0 = a.ext_from[0], ex1 = a.ext_from[1];
+    int ld_off[NLOAD], ld_msk[NLOAD];
+    T rl[NLOAD];
+#pragma unroll
+    for (int i = 0; i < NLOAD; ++i) {
+        const int e = tid + i * NT;
+        ld_off[i] = 0;
+        ld_msk[i] = 4; // idle slot: reads u of node 0 of the row, never stashed
+        if (e >= NXN * NI) continue;
+        const int node = e / NI, c = e % NI;
+        int lx, ly;
+        coef2<MU>(c, lx, ly);
+        const Map1 mx = map_node(x0 + off + node, ex0, a.bc[0]);
+        ld_off[i] = c < NU ? mx.j * NU + c : mx.j * NV + (c - NU);
+        const bool neg = mx.ghost && flips(a.bc[0], lx);
+        ld_msk[i] = 1 | (neg ? 2 : 0) | (c < NU ? 4 : 0) | ((ly & 1) << 3);
+    }
+    int yghost = 0;
+    auto fetch = [&](int gy) {
+        const Map1 my = map_node(gy, ex1, a.bc[1]);
+        yghost = my.ghost;
+        const int64_t rn = (int64_t)ex0 * my.j;
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const GIn src = (CONS || (ld_msk[i] & 4)) ? gu + rn * NU : gv + rn * NV;
+            rl[i] = src[ld_off[i]];
+        }
+    };
+    auto stash = [&]() {
+        // the y flip of a ghost row: Dirichlet flips even l_y, Neumann odd l_y
+        const bool yflip_odd = a.bc[1] != 1;
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            const int e = tid + i * NT;
+            if (e >= NXN * NI) break;
+            const int m = ld_msk[i];
+            bool neg = (m & 2) != 0;
+            if (yghost && (((m >> 3) & 1) != 0) == yflip_odd) neg = !neg;
+            sh.nd[(e / NI) * SX + e % NI] = neg ? -rl[i] : rl[i];
+        }
+    };
+
+    // staged outputs of a cell row, stored coalesced (a strip's row of cells is contiguous)
+    const int nrows = cy1 - cy0 + 1; // node rows
+    constexpr int NSU = (CX * NU + NT - 1) / NT;
+    T ov[CONS ? NSU : 1];
+    int64_t ogi[CONS ? NSU : 1];
+    auto old_fetch = [&](int cy) {
+        if constexpr (CONS) {
+            const GIn old_u = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old));
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) {
+                const int i = tid + k * NT, c = i / NU, o = i % NU;
+                ogi[k] = -1;
+                if (i >= CX * NU || x0 + c >= a.ext_to[0]) continue;
+                ogi[k] = ((int64_t)a.ext_to[0] * cy + x0 + c) * NU + o;
+                ov[k] = old_u[ogi[k]];
+            }
+        }
+    };
+    auto store_row = [&](int cy) {
+        const GOut out_u = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out));
+        if constexpr (CONS) {
+            (void)cy;
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) {
+                const int i = tid + k * NT, c = i / NU, o = i % NU;
+                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * sh.out[c * OS + o] - ov[k];
+            }
+        } else {
+            const GOut out_v = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out));
+            const int64_t rb = (int64_t)a.ext_to[0] * cy + x0;
+            for (int i = tid; i < CX * NU; i += NT) {
+                const int c = i / NU, o = i % NU;
+                if (x0 + c < a.ext_to[0]) out_u[(rb + c) * NU + o] = sh.out[c * OS + o];
+            }
+            for (int i = tid; i < CX * NV; i += NT) {
+                const int c = i / NV, o = i % NV;
+                if (x0 + c < a.ext_to[0]) out_v[(rb + c) * NV + o] = sh.out[c * OS + NU + o];
+            }
+        }
+    };
+
+    // butterfly slots: 32 lanes cover 16 cells x a pair of K positions; a thread keeps the
+    // same (cell, kp) slots in every pass
+    T prev[NBF][2];
+    int bkp[NBF], bl[NBF];
+#pragma unroll
+    for (int k = 0; k < NBF; ++k) {
+        const int t = tid + k * NT;
+        bkp[k] = t < CX * TL ? tabs->bk[2 * (t >> 5) + ((t >> 4) & 1)] : 0;
+        bl[k] = tabs->kl[bkp[k]];
+    }
+
+    fetch(cy0 + off);
+    for (int step = 0; step < nrows; ++step) {
+        stash();
+        __syncthreads();
+        if (step >= 2) store_row(cy0 + step - 2);
+        if (step + 1 < nrows) fetch(cy0 + off + step + 1);
+        if (step >= 1) old_fetch(cy0 + step - 1); // the cell row computed in this pass
+
+        // butterflies of node row `step`: T_px of this row, combined with the lower row's
+        // into S_{px + 2 py} of cell row step - 1
+#pragma unroll
+        for (int k = 0; k < NBF; ++k) {
+            const int t = tid + k * NT;
+            if (t >= CX * TL) break;
+            const int cell = t & 15, kp = bkp[k], l = bl[k];
+            const T xl = sh.nd[cell * SX + l], xr = sh.nd[(cell + 1) * SX + l];
+            const T cur[2] = {xl + xr, xl - xr};
+            if (step > 0) {
+                T* dst = sh.tsum + cell * TSZ + kp;
+                dst[0] = prev[k][0] + cur[0];
+                dst[TL] = prev[k][1] + cur[1];
+                dst[2 * TL] = prev[k][0] - cur[0];
+                dst[3 * TL] = prev[k][1] - cur[1];
+            }
+            prev[k][0] = cur[0];
+            prev[k][1] = cur[1];
+        }
+        __syncthreads();
+        if (step == 0 || !active) continue;
+
+        // the chain's products for cell row step - 1, outputs staged for the next pass
+        T bv[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = sh.tsum[(lane & 15) * TSZ + tb[ks]];
+        typename MF::vec acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc = MF::mac(ta[ks], bv[ks], acc);
+        const int cell = lane & 15;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh.out[cell * OS + rdst[r]] = acc[r];
+    }
+    __syncthreads();
+    store_row(cy0 + nrows - 2);
+}
+
+template <typename T, int MU, bool CONS, int NT>
+__global__ void __launch_bounds__(NT) k_cmap2d(DenseArgs a, int ry)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int x0 = blockIdx.x * CX, cy0 = blockIdx.y * ry, cy1 = min(cy0 + ry, a.ext_to[1]);
+    strip<T, MU, CONS, NT>(a, static_cast<const C2Tables<T, MU, CONS>*>(a.cm2), x0, cy0, cy1, smem_raw);
+}
+
+// many problems of one (m, method): a persistent grid walks a work list of strips
+// {problem, x0, cy0, cy1}; workgroup b runs on XCD b mod 8 and takes a contiguous part
+template <typename T, int MU, bool CONS, int NT>
+__global__ void __launch_bounds__(NT) k_cmap2d_list(const DenseArgs* __restrict__ probs, const int4* __restrict__ items,
+                                                    int n_items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int nx = nb < 8 ? nb : 8;
+    const int xcd = b % nx, slot = b / nx;
+    const int per_xcd = (nb + nx - 1 - xcd) / nx;
+    const int chunk = (n_items + nx - 1) / nx;
+    const int t0 = xcd * chunk, t1 = min(n_items, t0 + chunk);
+    for (int t = t0 + slot; t < t1; t += per_xcd) {
+        const int4 it = items[t];
+        const int pi = __builtin_amdgcn_readfirstlane(it.x);
+        const int x0 = __builtin_amdgcn_readfirstlane(it.y);
+        const int cy0 = __builtin_amdgcn_readfirstlane(it.z), cy1 = __builtin_amdgcn_readfirstlane(it.w);
+        const DenseArgs a = probs[pi];
+        strip<T, MU, CONS, NT>(a, static_cast<const C2Tables<T, MU, CONS>*>(a.cm2), x0, cy0, cy1, smem_raw);
+        __syncthreads(); // the next strip's stash overwrites the LDS
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host
+// ---------------------------------------------------------------------------
+template <typename T, int MU, bool CONS>
+hipError_t create(const std::vector<double>& G0, void** out)
+{
+    using S = Shape2<T, MU, CONS>;
+    using Tab = C2Tables<T, MU, CONS>;
+    constexpr int NI = S::NI, NU = S::NU, KS = S::KS, TL = S::TL, MV = S::MV;
+    if (G0.size() != (size_t)NI * NI) return hipErrorInvalidValue;
+    Tab* h = new Tab();
+    std::memset(h, 0, sizeof *h);
+    // K order: the natural input order, padding positions last.  The butterfly passes pair
+    // an even K position with an odd one whose inputs have indices of opposite parity (their
+    // LDS reads and writes then fall on the even and the odd banks); the padding positions
+    // read the zero slot NI or NI + 1, chosen to keep the four (position, input) parity
+    // classes balanced so that every position finds its partner.
+    {
+        int cnt[4] = {0, 0, 0, 0}; // [2 * position parity + input parity]
+        for (int k = 0; k < NI; ++k) {
+            h->kl[k] = k;
+            ++cnt[2 * (k & 1) + (k & 1)];
+        }
+        for (int k = NI; k < TL; ++k) {
+            const int pk = k & 1;
+            // even position: (0, even input) pairs with (1, odd), (0, odd) with (1, even)
+            const int want_in = pk == 0 ? (cnt[0] < cnt[3] ? 0 : 1) : (cnt[3] < cnt[0] ? 1 : 0);
+            h->kl[k] = (NI & 1) == want_in ? NI : NI + 1;
+            ++cnt[2 * pk + want_in];
+        }
+        std::vector<int> cls[4]; // [position parity][input parity]
+        for (int k = 0; k < TL; ++k) cls[2 * (k & 1) + (h->kl[k] & 1)].push_back(k);
+        // complete pairs first, then whatever remains (correct either way, only slower)
+        std::vector<int> ev, od;
+        int j = 0;
+        const size_t n03 = std::min(cls[0].size(), cls[3].size()), n12 = std::min(cls[1].size(), cls[2].size());
+        for (size_t i = 0; i < n03; ++i, ++j) {
+            h->bk[2 * j] = cls[0][i];
+            h->bk[2 * j + 1] = cls[3][i];
+        }
+        for (size_t i = 0; i < n12; ++i, ++j) {
+            h->bk[2 * j] = cls[1][i];
+            h->bk[2 * j + 1] = cls[2][i];
+        }
+        for (size_t i = n03; i < cls[0].size(); ++i) ev.push_back(cls[0][i]);
+        for (size_t i = n12; i < cls[1].size(); ++i) ev.push_back(cls[1][i]);
+        for (size_t i = n12; i < cls[2].size(); ++i) od.push_back(cls[2][i]);
+        for (size_t i = n03; i < cls[3].size(); ++i) od.push_back(cls[3][i]);
+        for (size_t i = 0; i < ev.size(); ++i, ++j) {
+            h->bk[2 * j] = ev[i];
+            h->bk[2 * j + 1] = od[i];
+        }
+        if (2 * j != TL) {
+            delete h;
+            return hipErrorInvalidValue;
+        }
+    }
+    int nch = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        std::vector<int> rows; // outputs of the class: u block, then v block
+        for (int ay = qy; ay < MU; ay += 2)
+            for (int ax = qx; ax < MU; ax += 2) rows.push_back(ax + MU * ay);
+        if (!CONS)
+            for (int ay = qy; ay < MV; ay += 2)
+                for (int ax = qx; ax < MV; ax += 2) rows.push_back(NU + ax + MV * ay);
+        for (size_t r0 = 0; r0 < rows.size(); r0 += 16, ++nch) {
+            if (nch >= MAXCH) {
+                delete h;
+                return hipErrorInvalidValue;
+            }
+            const int nr = (int)std::min<size_t>(16, rows.size() - r0);
+            for (int i = 0; i < 16; ++i) h->tr[nch][i] = i < nr ? rows[r0 + i] : -1;
+            for (int ks = 0; ks < KS; ++ks) {
+                for (int g = 0; g < 4; ++g) {
+                    const int k = 4 * ks + g, l = h->kl[k];
+                    int p = 0; // padding: the (zero) sums of p = 0
+                    if (l < NI) {
+                        int lx, ly;
+                        coef2<MU>(l, lx, ly);
+                        p = ((qx + lx) & 1) + 2 * ((qy + ly) & 1);
+                    }
+                    h->tb[nch][ks][g] = p * TL + k;
+                }
+                for (int lanei = 0; lanei < 64; ++lanei) {
+                    const int i = lanei & 15, k = 4 * ks + (lanei >> 4), l = h->kl[k];
+                    h->ta[nch][ks][lanei] = (i < nr && l < NI) ? (T)G0[(size_t)l * NI + rows[r0 + i]] : T(0);
+                }
+            }
+        }
+    }
+    h->nch = nch;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(Tab));
+    if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(Tab), hipMemcpyHostToDevice);
+    delete h;
+    if (e != hipSuccess) {
+        if (p) (void)hipFree(p);
+        return e;
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+template <typename T, int MU, bool CONS>
+constexpr int threads()
+{
+    using S = Shape2<T, MU, CONS>;
+    // chains: per class ceil(rows / 16); at most 8
+    int n = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int qx = q & 1, qy = q >> 1;
+        const int ru = ((MU - qx + 1) / 2) * ((MU - qy + 1) / 2);
+        const int rv = CONS ? 0 : ((S::MV - qx + 1) / 2) * ((S::MV - qy + 1) / 2);
+        n += (ru + rv + 15) / 16;
+    }
+    return n <= 4 ? 256 : 512;
+}
+
+template <typename T, int MU, bool CONS>
+hipError_t launch1(const DenseArgs& a, int ry, hipStream_t st)
+{
+    constexpr int NT = threads<T, MU, CONS>();
+    const size_t lds = sizeof(C2Shared<T, MU, CONS>);
+    auto kern = k_cmap2d<T, MU, CONS, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((a.ext_to[0] + CX - 1) / CX, (a.ext_to[1] + ry - 1) / ry);
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, a, ry);
+    return hipGetLastError();
+}
+
+template <typename T, int MU, bool CONS>
+hipError_t launch_list(const DenseArgs* probs, const int4* items, int n_items, int grid, hipStream_t st)
+{
+    constexpr int NT = threads<T, MU, CONS>();
+    const size_t lds = sizeof(C2Shared<T, MU, CONS>);
+    auto kern = k_cmap2d_list<T, MU, CONS, NT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, probs, items, n_items);
+    return hipGetLastError();
+}
+
+template <typename T, bool CONS, typename F>
+hipError_t by_m(int m, F f)
+{
+    switch (m) {
+    case 3: return f(std::integral_constant<int, 4>{});
+    case 4: return f(std::integral_constant<int, 5>{});
+    case 5: return f(std::integral_constant<int, 6>{});
+    case 6: return f(std::integral_constant<int, 7>{});
+    }
+    return hipErrorInvalidValue;
+}
+
+} // namespace
+
+bool hw_cmap2d_supported(int m) { return m >= 3 && m <= 6; }
+
+hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool cons, bool fp64, void** out)
+{
+    *out = nullptr;
+    if (!hw_cmap2d_supported(m)) return hipErrorInvalidValue;
+    auto mk = [&](auto T_tag, auto c_tag) {
+        using T = decltype(T_tag);
+        constexpr bool C = decltype(c_tag)::value;
+        return by_m<T, C>(m, [&](auto mu) { return create<T, decltype(mu)::value, C>(G0, out); });
+    };
+    if (fp64)
+        return cons ? mk(double(), std::true_type{}) : mk(double(), std::false_type{});
+    return cons ? mk(float(), std::true_type{}) : mk(float(), std::false_type{});
+}
+
+hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int ry, hipStream_t st)
+{
+    if (!a.cm2 || ry < 1) return hipErrorInvalidValue;
+    if (a.ext_to[0] < 1 || a.ext_to[1] < 1 || a.ext_from[0] < 1 || a.ext_from[1] < 1) return hipErrorInvalidValue;
+    auto go = [&](auto T_tag, auto c_tag) {
+        using T = decltype(T_tag);
+        constexpr bool C = decltype(c_tag)::value;
+        return by_m<T, C>(m, [&](auto mu) { return launch1<T, decltype(mu)::value, C>(a, ry, st); });
+    };
+    if (fp64) return cons ? go(double(), std::true_type{}) : go(double(), std::false_type{});
+    return cons ? go(float(), std::true_type{}) : go(float(), std::false_type{});
+}
+
+hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int grid, int m, bool cons,
+                                 bool fp64, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (grid < 1) grid = 1;
+    auto go = [&](auto T_tag, auto c_tag) {
+        using T = decltype(T_tag);
+        constexpr bool C = decltype(c_tag)::value;
+        return by_m<T, C>(m, [&](auto mu) { return launch_list<T, decltype(mu)::value, C>(probs, items, n_items, grid, st); });
+    };
+    if (fp64) return cons ? go(double(), std::true_type{}) : go(double(), std::false_type{});
+    return cons ? go(float(), std::true_type{}) : go(float(), std::false_type{});
+}

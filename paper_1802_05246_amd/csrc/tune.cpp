@@ -4,7 +4,8 @@
 // from and appended to that text file (one "kernel d m method fp64 size choice us" line
 // per key), so later processes reuse the choices; HW_AUTOTUNE=0 turns the timing off
 // (every kernel then takes its default shape); HW_TUNE_FORCE="kernel=choice,..." imposes
-// a choice for the named kernels (tests use it to run every variant).
+// a choice for the named kernels (tests use it to run every variant); HW_TUNE_LOG=1 prints
+// every candidate's time to stderr as it is measured.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -106,8 +107,13 @@ int hw_tune_choose(const char* kernel, int d, int m, int method, bool fp64, int 
     }
     int best = candidates.empty() ? 0 : candidates[0];
     double best_us = 1e300;
+    const char* lg = std::getenv("HW_TUNE_LOG");
+    const bool log = lg && std::strcmp(lg, "0") != 0;
     for (int c : candidates) {
         const double t = time_us(c);
+        if (log)
+            std::fprintf(stderr, "[tune] %s d=%d m=%d method=%d fp64=%d size=%d choice %d: %.3f us\n", kernel, d, m,
+                         method, fp64 ? 1 : 0, size_class, c, t);
         if (t > 0.0 && t < best_us) {
             best_us = t;
             best = c;

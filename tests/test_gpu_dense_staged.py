@@ -3,7 +3,9 @@ oracle: the per-lane gather form (tiles 16 and 128 cells wide), the LDS-staged f
 (tiles 32 and 64 wide, corner nodes copied to LDS with coalesced loads, ghost nodes
 mirrored there, outputs stored through LDS; codes -32, -64) and the row-chunked staged
 form (one coefficient row of every node of the tile in LDS at a time, double-buffered;
-codes -1032, -1064).  The variant is imposed with HW_TUNE_FORCE,
+codes -1032, -1064) and the composed-map form on the matrix cores (strips of 16 cells
+walking their cell rows, corner sums formed in LDS, m = 3..6 only; code -2016).  The
+variant is imposed with HW_TUNE_FORCE,
 for the single-problem kernel ("dense") and the batched persistent kernel
 ("dense_list").  Grids span several tiles with ragged edges; every wall type, both
 methods, m = 1..6; same bars as the other parity tests."""
@@ -18,7 +20,7 @@ from test_gpu_parity import _log, _state, state_err
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-CODES = [16, 128, -32, -64, -1032, -1064]
+CODES = [16, 128, -32, -64, -1032, -1064, -2016]
 
 SINGLE = [
     # m, method, n, bc
@@ -40,7 +42,9 @@ def _id(c):
 def _staged_fits(m, meth, prec, code):
     """Whether a staged form's LDS fits the 160 KB of a CU (whole records: node tile or
     output staging, odd strides; row chunks: two buffers of one odd-padded row per node);
-    the library refuses the other choices."""
+    the library refuses the other choices.  The composed-map form serves m = 3..6."""
+    if code == -2016:
+        return 3 <= m <= 6
     tx = (-code) % 1000
     mu, mv = m + 1, (0 if meth == W.CONSERVATIVE else m)
     nodes = (tx + 1) * (256 // tx + 1)
@@ -76,7 +80,7 @@ def test_dense_variant_matches_oracle(case, code, prec, monkeypatch):
     if code < 0 and not _staged_fits(m, meth, prec, code):
         with pytest.raises(B.HwError):
             B.Solver(spec, precision=B.HW_FP64 if prec == "fp64" else B.HW_FP32, kernel=B.HW_KERNEL_DENSE)
-        _log("    refused (LDS)")
+        _log("    refused")
         return
     err, tol = _run(B, spec, B.HW_KERNEL_DENSE, 700 + m, prec)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
@@ -98,22 +102,24 @@ def test_batch_variant_matches_oracle(case, code, prec, monkeypatch):
     if code < 0 and not _staged_fits(m, meth, prec, code):
         with pytest.raises(B.HwError):
             B.Solver(spec, precision=B.HW_FP64 if prec == "fp64" else B.HW_FP32, kernel=B.HW_KERNEL_BATCH)
-        _log("    refused (LDS)")
+        _log("    refused")
         return
     err, tol = _run(B, spec, B.HW_KERNEL_BATCH, 800 + m, prec)
     _log(f"    rel-L2 = {err:.3e} (tol {tol:g})")
     assert err <= tol
 
 
-@pytest.mark.parametrize("code", [-32, -64, -1032, -1064])
+@pytest.mark.parametrize("code", [-32, -64, -1032, -1064, -2016])
 def test_staged_batch_of_mixed_problems_matches_gather_form(code, monkeypatch):
-    """A mixed batch (several problems per (m, method) class, ragged sizes) through the
-    staged persistent kernel equals the gather form to FP64 rounding."""
+    """A mixed batch (several problems per (m, method) class, ragged sizes, strips longer
+    than one 64-row chunk) through the staged persistent kernels equals the gather form to
+    FP64 rounding."""
     from paper_1802_05246_amd import binding as B
-    specs = [W.make_spec(2, m, [29 + 11 * i, 7 + 5 * i], 0.0, 1.0, 0.7 + 0.1 * i, cfl=0.8,
+    ms = [3, 6, 3, 4, 5, 5, 4, 3] if code == -2016 else [2, 3, 3, 4, 2, 5, 4, 3]
+    specs = [W.make_spec(2, m, [29 + 11 * i, 7 + 17 * i], 0.0, 1.0, 0.7 + 0.1 * i, cfl=0.8,
                          bc=[W.PERIODIC, W.DIRICHLET, W.NEUMANN][i % 3],
                          method=[W.DISS_FULL, W.CONSERVATIVE][(m + i) % 2])
-             for i, m in enumerate([2, 3, 3, 4, 2, 5, 4, 3])]
+             for i, m in enumerate(ms)]
     states = [_state(sp, 900 + i) for i, sp in enumerate(specs)]
     out = {}
     for c in (code, 64):
