@@ -10,20 +10,27 @@
 // S_p[l] = sum_s (-1)^(p . s) x_s[l] (p = p_x + 2 p_y), and output a needs, for each input
 // l, only S_{pi(a) xor pi(l)}[l] (pi: the parity vector).  Grouped by the output parity
 // class q = pi(a), each class is a dense (rows of the class) x NI product with the
-// class's column of selected sums; its rows are cut into tiles of 16 ("chains"), each
-// applied to 16 cells at a time as a chain of 16x16x4 products.
+// class's column of selected sums; its rows are cut into tiles of 16 ("chains", one or
+// two per class), each applied to 16 cells at a time as a chain of 16x16x4 products.
 //
-// A workgroup (one wave per chain) owns a strip of 16 cells along x and walks a chunk of
-// its cell rows upwards in y, one node row of the input grid at a time:
+// A workgroup of 8 waves owns a strip of 16 cells along x and walks a chunk of its cell
+// rows upwards in y, one node row of the input grid at a time; wave 2 q + h runs every
+// chain of class q over half h of the K range (the two halves' partial outputs are added
+// when the row is stored, so that the waves of a class share their B operands and the
+// chains are half as long):
 //   1. the row's 17 nodes, loaded into registers during the previous row, are stashed in
 //      LDS (ghost nodes outside non-periodic walls mirrored with the odd / even signs of
 //      Sec. 3.1.3); the cell row finished two rows ago is stored and the loads of the
 //      next node row are issued;
 //   2. butterflies: per cell and input l, T_px[l] = x(left)[l] +- x(right)[l] of this
 //      row, combined with those of the row below (kept in registers since the previous
-//      pass) into S_{px + 2 py}[l] = T_px(lower)[l] +- T_px(upper)[l], written to LDS;
-//   3. the chains' products (A: the chain's rows of the composed map, registers; B: the
-//      selected sums read from LDS), outputs staged in LDS for the coalesced stores.
+//      pass) into S_{px + 2 py}[l] = T_px(lower)[l] +- T_px(upper)[l], written to LDS in
+//      class order: the cell's block holds, for class q and K position k, the sum that
+//      class selects for input l_k, S_{q xor pi(l_k)}[l_k], so that a wave's B operands
+//      are read at affine offsets;
+//   3. the chains' products (A: the chains' rows of the composed map, registers; B: the
+//      selected sums read from LDS), partial outputs staged in LDS for the coalesced
+//      stores.
 // LDS strides follow the 32 banks of 4 bytes served 32 lanes (b32) or 16 lanes (b64) at a
 // time: node stride = 2 (mod 32) in FP32 (the 16 cells of a butterfly pass on the 16 even
 // banks, the pass's second K position -- whose input index has the other parity -- on the
@@ -32,6 +39,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "hw_kernels.h"
@@ -40,7 +48,7 @@ namespace {
 
 constexpr int CX = 16;      // cells of a strip
 constexpr int NXN = CX + 1; // nodes of a row of a strip
-constexpr int MAXCH = 8;    // chains (row tiles over the 4 classes) at most
+constexpr int NT2 = 512;    // threads of a workgroup: 4 classes x 2 K halves
 
 // smallest v >= x with v = r (mod m)
 constexpr int up_to_residue(int x, int m, int r) { return x + ((r - x % m) % m + m) % m; }
@@ -51,13 +59,19 @@ struct Shape2 {
     static constexpr int NU = MU * MU, NV = MV * MV, NI = NU + NV; // inputs = outputs per node
     static constexpr int TL = (NI + 3) / 4 * 4;                    // K positions (padded)
     static constexpr int KS = TL / 4;                              // K-steps of 4
+    static constexpr int KH = (KS + 1) / 2;                        // K-steps of the first half
     static constexpr bool PAD = TL > NI;                           // padding reads slot NI or NI+1 (zero)
     static constexpr int SX0 = NI + (PAD ? 2 : 0);                 // minimum node stride
     static constexpr int SX = sizeof(T) == 4 ? up_to_residue(SX0, 32, 2) : up_to_residue(SX0, 16, 1);
     static constexpr int TSZ0 = 4 * TL;
     static constexpr int TSZ = sizeof(T) == 4 ? up_to_residue(TSZ0, 32, 2) : (TSZ0 | 1);
     static constexpr int OS = (NI + 1) | 1; // cell stride of the staged outputs (slot NI: unused rows)
+    // rows of the largest parity class (u: ceil(MU/2)^2, v: ceil(MV/2)^2): one or two chains
+    static constexpr int RMAX = ((MU + 1) / 2) * ((MU + 1) / 2) + ((MV + 1) / 2) * ((MV + 1) / 2);
+    static constexpr int CPC = (RMAX + 15) / 16; // chains per class at most
+    static_assert(CPC <= 2, "at most two chains per class");
     static_assert(SX >= SX0 && TSZ >= TSZ0 && OS > NI, "strides");
+    static_assert(TL < 256 && NI + 2 < 256, "packed butterfly slots");
     static_assert(sizeof(T) == 8 || (SX % 32 == 2 && TSZ % 32 == 2), "FP32 strides");
     static_assert(sizeof(T) == 4 || (SX % 16 == 1 && TSZ % 2 == 1), "FP64 strides");
 };
@@ -78,32 +92,31 @@ struct Mf2<double> {
 };
 
 // Tables of one problem:
-//   ta[ch][KS][64]  A operand of chain ch: entry (row i = lane % 16 of the chain's tile,
-//                   K position 4 ks + lane / 16)
-//   tb[ch][KS][4]   offset of the selected sum in a cell's block for (K-step, lane / 16):
-//                   p * TL + k, p = p_x + 2 p_y of the class and the input at K position k
-//   tr[ch][16]      output of the chain's row (index into the node's u | v block), -1 unused
-//   kl[TL]          input at K position k (padding positions: the zero slots NI, NI + 1,
-//                   whichever index parity keeps the butterfly pairs below complete)
-//   bk[TL]          K positions of the butterfly passes, pairs (even, odd) whose inputs have
-//                   indices of opposite parity
-//   nch             chains
+//   ta[q][c][KS][64] A operand of chain c of class q: entry (row i = lane % 16 of the
+//                    chain's tile, K position 4 ks + lane / 16)
+//   tr[q][c][16]     output of the chain's row (index into the node's u | v block), -1 unused
+//   ncl[q]           chains of class q (1 or 2)
+//   kl[TL]           input at K position k (padding positions: the zero slots NI, NI + 1,
+//                    whichever index parity keeps the butterfly pairs below complete)
+//   pk[TL]           parity vector pi of that input (0 for the padding positions)
+//   bk[TL]           K positions of the butterfly passes, pairs (even, odd) whose inputs
+//                    have indices of opposite parity
 template <typename T, int MU, bool CONS>
 struct C2Tables {
     using S = Shape2<T, MU, CONS>;
-    T ta[MAXCH][S::KS][64];
-    int tb[MAXCH][S::KS][4];
-    int tr[MAXCH][16];
+    T ta[4][S::CPC][S::KS][64];
+    int tr[4][S::CPC][16];
+    int ncl[4];
     int kl[S::TL];
+    int pk[S::TL];
     int bk[S::TL];
-    int nch;
 };
 
 template <typename T, int MU, bool CONS>
 struct C2Shared {
     using S = Shape2<T, MU, CONS>;
     alignas(16) T tsum[CX * S::TSZ];
-    alignas(16) T out[CX * S::OS];
+    alignas(16) T out[2][CX * S::OS]; // partial outputs of the two K halves
     T nd[NXN * S::SX];
 };
 
@@ -157,12 +170,13 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
     using S = Shape2<T, MU, CONS>;
     using SH = C2Shared<T, MU, CONS>;
     using MF = Mf2<T>;
-    constexpr int NI = S::NI, NU = S::NU, NV = S::NV, KS = S::KS, TL = S::TL;
+    constexpr int NI = S::NI, NU = S::NU, NV = S::NV, KS = S::KS, KH = S::KH, TL = S::TL, CPC = S::CPC;
     constexpr int SX = S::SX, TSZ = S::TSZ, OS = S::OS;
     constexpr int NLOAD = (NXN * NI + NT - 1) / NT;
     constexpr int NBF = (CX * TL + NT - 1) / NT;
     SH& sh = *reinterpret_cast<SH*>(smem_raw);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    static_assert(NT == NT2, "one wave per (class, K half)");
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int off = a.to_grid == 1 ? 0 : -1; // input node of corner s = cell + off + s
     typedef const __attribute__((address_space(1))) T* GIn;
     typedef __attribute__((address_space(1))) T* GOut;
@@ -173,28 +187,34 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
     if constexpr (S::PAD)
         for (int i = tid; i < 2 * NXN; i += NT) sh.nd[(i >> 1) * SX + NI + (i & 1)] = T(0);
 
-    // the wave's chain: A operands, B offsets, output targets
-    const int nch = tabs->nch;
-    const bool active = wave < nch;
-    const int ch = active ? wave : 0;
-    T ta[KS];
-    int tb[KS], rdst[4];
+    // the wave's class q and K half h: A operands of the class's chains over that half
+    // (K-steps h KH ..), output targets
+    const int q = wave >> 1, h = wave & 1;
+    const int two = CPC > 1 ? tabs->ncl[q] > 1 : 0;
+    T ta[CPC][KH];
+    int rdst[CPC][4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        ta[ks] = tabs->ta[ch][ks][lane];
-        tb[ks] = tabs->tb[ch][ks][lane >> 4];
-    }
+    for (int c = 0; c < CPC; ++c) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int o = tabs->tr[ch][MF::row(lane, r)];
-        rdst[r] = o < 0 ? NI : o; // unused rows write the spare slot NI of the cell
+        for (int j = 0; j < KH; ++j) {
+            const int ks = h * KH + j;
+            ta[c][j] = ks < KS ? tabs->ta[q][c][ks][lane] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = tabs->tr[q][c][MF::row(lane, r)];
+            rdst[c][r] = o < 0 ? NI : o; // unused rows write the spare slot NI of the cell
+        }
     }
 
     // node loads: slot i = element tid + i NT of the row's 17 x NI block; the x part and
     // the x ghost sign are fixed per strip
     const int ex0 = a.ext_from[0], ex1 = a.ext_from[1];
     int ld_off[NLOAD], ld_msk[NLOAD];
-    T rl[NLOAD];
+    // node rows in flight: PD ahead of the row being stashed (two ahead, with the registers
+    // to hold them, measured no faster)
+    constexpr int PD = 1;
+    T rl[PD][NLOAD];
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
         const int e = tid + i * NT;
@@ -209,18 +229,18 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
         const bool neg = mx.ghost && flips(a.bc[0], lx);
         ld_msk[i] = 1 | (neg ? 2 : 0) | (c < NU ? 4 : 0) | ((ly & 1) << 3);
     }
-    int yghost = 0;
-    auto fetch = [&](int gy) {
+    int yghost[PD] = {};
+    auto fetch = [&](auto B, int gy) {
         const Map1 my = map_node(gy, ex1, a.bc[1]);
-        yghost = my.ghost;
+        yghost[B] = my.ghost;
         const int64_t rn = (int64_t)ex0 * my.j;
 #pragma unroll
         for (int i = 0; i < NLOAD; ++i) {
             const GIn src = (CONS || (ld_msk[i] & 4)) ? gu + rn * NU : gv + rn * NV;
-            rl[i] = src[ld_off[i]];
+            rl[B][i] = src[ld_off[i]];
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](auto B) {
         // the y flip of a ghost row: Dirichlet flips even l_y, Neumann odd l_y
         const bool yflip_odd = a.bc[1] != 1;
 #pragma unroll
@@ -229,8 +249,8 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
             if (e >= NXN * NI) break;
             const int m = ld_msk[i];
             bool neg = (m & 2) != 0;
-            if (yghost && (((m >> 3) & 1) != 0) == yflip_odd) neg = !neg;
-            sh.nd[(e / NI) * SX + e % NI] = neg ? -rl[i] : rl[i];
+            if (yghost[B] && (((m >> 3) & 1) != 0) == yflip_odd) neg = !neg;
+            sh.nd[(e / NI) * SX + e % NI] = neg ? -rl[B][i] : rl[B][i];
         }
     };
 
@@ -259,39 +279,44 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
 #pragma unroll
             for (int k = 0; k < NSU; ++k) {
                 const int i = tid + k * NT, c = i / NU, o = i % NU;
-                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * sh.out[c * OS + o] - ov[k];
+                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * (sh.out[0][c * OS + o] + sh.out[1][c * OS + o]) - ov[k];
             }
         } else {
             const GOut out_v = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out));
             const int64_t rb = (int64_t)a.ext_to[0] * cy + x0;
             for (int i = tid; i < CX * NU; i += NT) {
                 const int c = i / NU, o = i % NU;
-                if (x0 + c < a.ext_to[0]) out_u[(rb + c) * NU + o] = sh.out[c * OS + o];
+                if (x0 + c < a.ext_to[0]) out_u[(rb + c) * NU + o] = sh.out[0][c * OS + o] + sh.out[1][c * OS + o];
             }
             for (int i = tid; i < CX * NV; i += NT) {
                 const int c = i / NV, o = i % NV;
-                if (x0 + c < a.ext_to[0]) out_v[(rb + c) * NV + o] = sh.out[c * OS + NU + o];
+                if (x0 + c < a.ext_to[0])
+                    out_v[(rb + c) * NV + o] = sh.out[0][c * OS + NU + o] + sh.out[1][c * OS + NU + o];
             }
         }
     };
 
     // butterfly slots: 32 lanes cover 16 cells x a pair of K positions; a thread keeps the
     // same (cell, kp) slots in every pass
+    // slot k: K position kp, its input l and parity vector pl, packed kp | l << 8 | pl << 16
     T prev[NBF][2];
-    int bkp[NBF], bl[NBF];
+    int bslot[NBF];
 #pragma unroll
     for (int k = 0; k < NBF; ++k) {
         const int t = tid + k * NT;
-        bkp[k] = t < CX * TL ? tabs->bk[2 * (t >> 5) + ((t >> 4) & 1)] : 0;
-        bl[k] = tabs->kl[bkp[k]];
+        const int kp = t < CX * TL ? tabs->bk[2 * (t >> 5) + ((t >> 4) & 1)] : 0;
+        bslot[k] = kp | tabs->kl[kp] << 8 | tabs->pk[kp] << 16;
     }
 
-    fetch(cy0 + off);
-    for (int step = 0; step < nrows; ++step) {
-        stash();
+    // one pass per node row `step`, held in register buffer B (the buffers alternate; the
+    // row PD ahead is loaded into B once it has been stashed)
+    auto pass = [&](auto B, int step) {
+        stash(B);
         __syncthreads();
+        // (the stores go out before the next row's loads: issuing the loads first, even
+        // before the barrier, measured slower)
         if (step >= 2) store_row(cy0 + step - 2);
-        if (step + 1 < nrows) fetch(cy0 + off + step + 1);
+        if (step + PD < nrows) fetch(B, cy0 + off + step + PD);
         if (step >= 1) old_fetch(cy0 + step - 1); // the cell row computed in this pass
 
         // butterflies of node row `step`: T_px of this row, combined with the lower row's
@@ -300,67 +325,111 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
         for (int k = 0; k < NBF; ++k) {
             const int t = tid + k * NT;
             if (t >= CX * TL) break;
-            const int cell = t & 15, kp = bkp[k], l = bl[k];
+            const int cell = t & 15, kp = bslot[k] & 255, l = (bslot[k] >> 8) & 255, pl = bslot[k] >> 16;
             const T xl = sh.nd[cell * SX + l], xr = sh.nd[(cell + 1) * SX + l];
             const T cur[2] = {xl + xr, xl - xr};
             if (step > 0) {
+                // S_p goes to the block of class q = p xor pi(l)
                 T* dst = sh.tsum + cell * TSZ + kp;
-                dst[0] = prev[k][0] + cur[0];
-                dst[TL] = prev[k][1] + cur[1];
-                dst[2 * TL] = prev[k][0] - cur[0];
-                dst[3 * TL] = prev[k][1] - cur[1];
+                dst[pl * TL] = prev[k][0] + cur[0];
+                dst[(pl ^ 1) * TL] = prev[k][1] + cur[1];
+                dst[(pl ^ 2) * TL] = prev[k][0] - cur[0];
+                dst[(pl ^ 3) * TL] = prev[k][1] - cur[1];
             }
             prev[k][0] = cur[0];
             prev[k][1] = cur[1];
         }
         __syncthreads();
-        if (step == 0 || !active) continue;
+        if (step == 0) return;
 
-        // the chain's products for cell row step - 1, outputs staged for the next pass
-        T bv[KS];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bv[ks] = sh.tsum[(lane & 15) * TSZ + tb[ks]];
-        typename MF::vec acc = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) acc = MF::mac(ta[ks], bv[ks], acc);
+        // the class's products for cell row step - 1 over this wave's K half, partial
+        // outputs staged for the next pass
         const int cell = lane & 15;
+        const T* bsrc = sh.tsum + cell * TSZ + q * TL + 4 * h * KH + (lane >> 4);
+        T* odst = sh.out[h] + cell * OS;
+        // (with KS odd the second half has one K-step fewer: h and the bound are uniform).
+        // Where registers are short (FP64, two chains of 22 K-steps) the B operands are read
+        // in chunks of 4 K-steps, the next chunk's reads issued before the current chunk's
+        // products; the empty asm keeps the reads from being hoisted further.
+        constexpr int BC = (sizeof(T) == 8 && KH > 8) ? 4 : KH, NCH = (KH + BC - 1) / BC;
+        T bv[KH];
+        auto bload = [&](int c) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sh.out[cell * OS + rdst[r]] = acc[r];
+            for (int j = c * BC; j < (c + 1) * BC && j < KH; ++j)
+                if (h * KH + j < KS) bv[j] = bsrc[4 * j];
+        };
+        typename MF::vec acc0 = {T(0), T(0), T(0), T(0)};
+        bload(0);
+        if (CPC > 1 && two) {
+            typename MF::vec acc1 = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                if constexpr (NCH > 1) {
+                    if (c + 1 < NCH) bload(c + 1);
+                    asm volatile("" ::: "memory");
+                }
+#pragma unroll
+                for (int j = c * BC; j < (c + 1) * BC && j < KH; ++j) {
+                    if (h * KH + j < KS) {
+                        acc0 = MF::mac(ta[0][j], bv[j], acc0);
+                        acc1 = MF::mac(ta[CPC - 1][j], bv[j], acc1);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) odst[rdst[CPC - 1][r]] = acc1[r];
+        } else {
+#pragma unroll
+            for (int c = 1; c < NCH; ++c) bload(c);
+#pragma unroll
+            for (int j = 0; j < KH; ++j)
+                if (h * KH + j < KS) acc0 = MF::mac(ta[0][j], bv[j], acc0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) odst[rdst[0][r]] = acc0[r];
+    };
+    fetch(std::integral_constant<int, 0>{}, cy0 + off);
+    if constexpr (PD == 2) {
+        fetch(std::integral_constant<int, PD - 1>{}, cy0 + off + 1); // nrows >= 2
+        for (int step = 0; step < nrows; step += 2) {
+            pass(std::integral_constant<int, 0>{}, step);
+            if (step + 1 < nrows) pass(std::integral_constant<int, PD - 1>{}, step + 1);
+        }
+    } else {
+        for (int step = 0; step < nrows; ++step) pass(std::integral_constant<int, 0>{}, step);
     }
     __syncthreads();
     store_row(cy0 + nrows - 2);
 }
 
+// (at least 4 waves per SIMD: two workgroups of 8 waves per CU)
 template <typename T, int MU, bool CONS, int NT>
-__global__ void __launch_bounds__(NT) k_cmap2d(DenseArgs a, int ry)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_cmap2d(DenseArgs a, int ry)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int x0 = blockIdx.x * CX, cy0 = blockIdx.y * ry, cy1 = min(cy0 + ry, a.ext_to[1]);
     strip<T, MU, CONS, NT>(a, static_cast<const C2Tables<T, MU, CONS>*>(a.cm2), x0, cy0, cy1, smem_raw);
 }
 
-// many problems of one (m, method): a persistent grid walks a work list of strips
-// {problem, x0, cy0, cy1}; workgroup b runs on XCD b mod 8 and takes a contiguous part
+// many problems of one (m, method): one workgroup per item of a work list of strips
+// {problem, x0, cy0, cy1} (a persistent loop over items costs registers: the loop-invariant
+// values of a strip are then held across items); workgroup b runs on XCD b mod 8, and the
+// workgroups of one XCD take a contiguous part of the list (neighbouring strips share
+// their edge nodes in that XCD's L2)
 template <typename T, int MU, bool CONS, int NT>
-__global__ void __launch_bounds__(NT) k_cmap2d_list(const DenseArgs* __restrict__ probs, const int4* __restrict__ items,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) k_cmap2d_list(const DenseArgs* __restrict__ probs, const int4* __restrict__ items,
                                                     int n_items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int b = blockIdx.x, nb = gridDim.x;
-    const int nx = nb < 8 ? nb : 8;
-    const int xcd = b % nx, slot = b / nx;
-    const int per_xcd = (nb + nx - 1 - xcd) / nx;
-    const int chunk = (n_items + nx - 1) / nx;
-    const int t0 = xcd * chunk, t1 = min(n_items, t0 + chunk);
-    for (int t = t0 + slot; t < t1; t += per_xcd) {
-        const int4 it = items[t];
-        const int pi = __builtin_amdgcn_readfirstlane(it.x);
-        const int x0 = __builtin_amdgcn_readfirstlane(it.y);
-        const int cy0 = __builtin_amdgcn_readfirstlane(it.z), cy1 = __builtin_amdgcn_readfirstlane(it.w);
-        const DenseArgs a = probs[pi];
-        strip<T, MU, CONS, NT>(a, static_cast<const C2Tables<T, MU, CONS>*>(a.cm2), x0, cy0, cy1, smem_raw);
-        __syncthreads(); // the next strip's stash overwrites the LDS
-    }
+    const int b = blockIdx.x;
+    const int per_xcd = (n_items + 7) / 8;
+    const int t = (b % 8) * per_xcd + b / 8;
+    if (t >= n_items) return; // whole workgroup
+    const int4 it = items[t];
+    const int pi = __builtin_amdgcn_readfirstlane(it.x), x0 = __builtin_amdgcn_readfirstlane(it.y);
+    const int cy0 = __builtin_amdgcn_readfirstlane(it.z), cy1 = __builtin_amdgcn_readfirstlane(it.w);
+    const DenseArgs a = probs[pi];
+    strip<T, MU, CONS, NT>(a, static_cast<const C2Tables<T, MU, CONS>*>(a.cm2), x0, cy0, cy1, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,7 +489,12 @@ hipError_t create(const std::vector<double>& G0, void** out)
             return hipErrorInvalidValue;
         }
     }
-    int nch = 0;
+    for (int k = 0; k < TL; ++k) {
+        const int l = h->kl[k];
+        int lx = 0, ly = 0;
+        if (l < NI) coef2<MU>(l, lx, ly);
+        h->pk[k] = l < NI ? (lx & 1) + 2 * (ly & 1) : 0;
+    }
     for (int q = 0; q < 4; ++q) {
         const int qx = q & 1, qy = q >> 1;
         std::vector<int> rows; // outputs of the class: u block, then v block
@@ -429,32 +503,25 @@ hipError_t create(const std::vector<double>& G0, void** out)
         if (!CONS)
             for (int ay = qy; ay < MV; ay += 2)
                 for (int ax = qx; ax < MV; ax += 2) rows.push_back(NU + ax + MV * ay);
-        for (size_t r0 = 0; r0 < rows.size(); r0 += 16, ++nch) {
-            if (nch >= MAXCH) {
-                delete h;
-                return hipErrorInvalidValue;
-            }
-            const int nr = (int)std::min<size_t>(16, rows.size() - r0);
-            for (int i = 0; i < 16; ++i) h->tr[nch][i] = i < nr ? rows[r0 + i] : -1;
-            for (int ks = 0; ks < KS; ++ks) {
-                for (int g = 0; g < 4; ++g) {
-                    const int k = 4 * ks + g, l = h->kl[k];
-                    int p = 0; // padding: the (zero) sums of p = 0
-                    if (l < NI) {
-                        int lx, ly;
-                        coef2<MU>(l, lx, ly);
-                        p = ((qx + lx) & 1) + 2 * ((qy + ly) & 1);
-                    }
-                    h->tb[nch][ks][g] = p * TL + k;
-                }
+        const int ncl = (int)(rows.size() + 15) / 16;
+        if (ncl < 1 || ncl > S::CPC) {
+            delete h;
+            return hipErrorInvalidValue;
+        }
+        h->ncl[q] = ncl;
+        for (int c = 0; c < S::CPC; ++c) {
+            const int r0 = 16 * c, nr = std::max(0, std::min(16, (int)rows.size() - r0));
+            for (int i = 0; i < 16; ++i) h->tr[q][c][i] = i < nr ? rows[r0 + i] : -1;
+            // the selected sum of input l for class q sits at K position k of the class's
+            // block (the butterflies write S_{q xor pi(l)} there), so A holds G0 itself
+            for (int ks = 0; ks < KS; ++ks)
                 for (int lanei = 0; lanei < 64; ++lanei) {
                     const int i = lanei & 15, k = 4 * ks + (lanei >> 4), l = h->kl[k];
-                    h->ta[nch][ks][lanei] = (i < nr && l < NI) ? (T)G0[(size_t)l * NI + rows[r0 + i]] : T(0);
+                    h->ta[q][c][ks][lanei] = (i < nr && l < NI) ? (T)G0[(size_t)l * NI + rows[r0 + i]] : T(0);
                 }
-            }
         }
     }
-    h->nch = nch;
+
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, sizeof(Tab));
     if (e == hipSuccess) e = hipMemcpy(p, h, sizeof(Tab), hipMemcpyHostToDevice);
@@ -468,24 +535,9 @@ hipError_t create(const std::vector<double>& G0, void** out)
 }
 
 template <typename T, int MU, bool CONS>
-constexpr int threads()
-{
-    using S = Shape2<T, MU, CONS>;
-    // chains: per class ceil(rows / 16); at most 8
-    int n = 0;
-    for (int q = 0; q < 4; ++q) {
-        const int qx = q & 1, qy = q >> 1;
-        const int ru = ((MU - qx + 1) / 2) * ((MU - qy + 1) / 2);
-        const int rv = CONS ? 0 : ((S::MV - qx + 1) / 2) * ((S::MV - qy + 1) / 2);
-        n += (ru + rv + 15) / 16;
-    }
-    return n <= 4 ? 256 : 512;
-}
-
-template <typename T, int MU, bool CONS>
 hipError_t launch1(const DenseArgs& a, int ry, hipStream_t st)
 {
-    constexpr int NT = threads<T, MU, CONS>();
+    constexpr int NT = NT2;
     const size_t lds = sizeof(C2Shared<T, MU, CONS>);
     auto kern = k_cmap2d<T, MU, CONS, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -498,12 +550,13 @@ hipError_t launch1(const DenseArgs& a, int ry, hipStream_t st)
 template <typename T, int MU, bool CONS>
 hipError_t launch_list(const DenseArgs* probs, const int4* items, int n_items, int grid, hipStream_t st)
 {
-    constexpr int NT = threads<T, MU, CONS>();
+    constexpr int NT = NT2;
     const size_t lds = sizeof(C2Shared<T, MU, CONS>);
     auto kern = k_cmap2d_list<T, MU, CONS, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, probs, items, n_items);
+    (void)grid; // one workgroup per item, 8 x ceil(n / 8) of them
+    hipLaunchKernelGGL(kern, dim3(8 * ((n_items + 7) / 8)), dim3(NT), lds, st, probs, items, n_items);
     return hipGetLastError();
 }
 
