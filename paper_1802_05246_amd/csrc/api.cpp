@@ -80,7 +80,6 @@ struct hw_solver {
         DenseArgs* args = nullptr;         // device [phase 0..1][slot parity 0..1][class member]
         int4* tiles[2] = {nullptr, nullptr}; // work list per phase: {member, x0, y0, 0}
         int ntiles[2] = {0, 0};
-        int grid = 0;
         int tx = 64;                       // tile code (see set_tile)
     };
     std::vector<BatchClass> bclasses;
@@ -323,11 +322,11 @@ hipError_t launch_dense_any(const DenseArgs& a, int d, int m, bool cons, bool fp
 }
 
 // one batched launch over a class's work list in the form its tile code names
-hipError_t launch_list_any(const DenseArgs* args, const int4* items, int n, int grid, int m, bool cons, bool fp64,
+hipError_t launch_list_any(const DenseArgs* args, const int4* items, int n, int m, bool cons, bool fp64,
                            int code, hipStream_t st)
 {
-    if (staged_form(code) == 3) return hw_launch_cmap2d_list(args, items, n, grid, m, cons, fp64, st);
-    return hw_launch_dense_list(args, items, n, grid, m, cons, fp64, staged_width(code), st);
+    if (staged_form(code) == 3) return hw_launch_cmap2d_list(args, items, n, m, cons, fp64, st);
+    return hw_launch_dense_list(args, items, n, m, cons, fp64, staged_width(code), st);
 }
 
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
@@ -336,8 +335,8 @@ hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
     if (s->use_batch2d) {
         for (const auto& C : s->bclasses) {
             const size_t n = C.probs.size();
-            HIP_TRY(launch_list_any(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.grid,
-                                    C.m, C.cons, s->fp64, C.tx, st));
+            HIP_TRY(launch_list_any(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.m,
+                                    C.cons, s->fp64, C.tx, st));
         }
         return HW_OK;
     }
@@ -535,9 +534,8 @@ hw_status setup_batch_classes(hw_solver* s)
                 if (hipMalloc((void**)&dt, tl.size() * sizeof(int4)) != hipSuccess ||
                     hipMemcpy(dt, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
                     return -1.0;
-                const int grid = (int)std::min<size_t>(tl.size(), 2048);
                 return time_launches([&](hipStream_t ts) {
-                    return launch_list_any(C.args, dt, (int)tl.size(), grid, C.m, C.cons, s->fp64, cand, ts);
+                    return launch_list_any(C.args, dt, (int)tl.size(), C.m, C.cons, s->fp64, cand, ts);
                 });
             };
             C.tx = hw_tune_choose("dense_list", 2, C.m, C.cons ? HW_CONSERVATIVE : HW_DISS_FULL, s->fp64,
@@ -557,7 +555,6 @@ hw_status setup_batch_classes(hw_solver* s)
                 hipMemcpy(C.tiles[ph], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
                 return fail(HW_EHIP, "batch work list upload failed");
         }
-        C.grid = (int)std::min(std::max(C.ntiles[0], C.ntiles[1]), 2048);
     }
     return HW_OK;
 }

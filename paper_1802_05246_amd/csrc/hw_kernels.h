@@ -69,27 +69,28 @@ bool hw_dense_supported(int d, int m, int method, int precision);
 void hw_fill_weights(const hw_problem& p, const double h[3], ProblemDesc& D);
 void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
-// Persistent launch over the tiles of many 2-D problems of one (m, method): probs[i] are
-// their descriptors, tiles {problem i, x0, y0, 0} of tile_x x (256 / tile_x) cells;
+// One launch over the tiles of many 2-D problems of one (m, method), one workgroup per
+// tile: probs[i] are their descriptors, tiles {problem i, x0, y0, 0} of tile_x x
+// (256 / tile_x) cells;
 // staged_tx = 32 or 64 selects the LDS-staged form (whole node records) with tiles of
 // that width, 1032 or 1064 the row-chunked staged form with tiles 32 or 64 wide, 0 the
 // per-lane gather form.
-hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
-                                bool fp64, int staged_tx, hipStream_t st);
+hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int m, bool cons, bool fp64,
+                                int staged_tx, hipStream_t st);
 // whether staged form `form` (1 or 2) with tiles tx cells wide fits a CU's LDS for
 // (m, method, precision)
 bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form);
 
 // Composed-map MFMA kernel for 2-D problems, m = 3..6, both methods (kernel_cmap2d.hip):
 // tables from corner 0's rows of the cell matrix (G0: [NI][NI], input-major, FP64); single
-// problems in strips of 16 cells walking chunks of ry cell rows, or a persistent launch
-// over a work list of strips {problem, x0, cy0, cy1} of many problems of one (m, method)
-// (the descriptors' cm2 fields name each problem's tables).
+// problems in strips of 16 cells walking chunks of ry cell rows, or one launch over a work
+// list of strips {problem, x0, cy0, cy1} of many problems of one (m, method), one
+// workgroup per strip (the descriptors' cm2 fields name each problem's tables).
 bool hw_cmap2d_supported(int m);
 hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool cons, bool fp64, void** out);
 hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int ry, hipStream_t st);
-hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int grid, int m, bool cons,
-                                 bool fp64, hipStream_t st);
+hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int m, bool cons, bool fp64,
+                                 hipStream_t st);
 
 // Composed-map MFMA kernel for the 3-D dissipative and conservative methods, m = 3 (kernel_cmap3d.hip):
 // the tables come from the problem's descriptor (cell matrix, hw_cell_map) and are

@@ -548,14 +548,13 @@ hipError_t launch1(const DenseArgs& a, int ry, hipStream_t st)
 }
 
 template <typename T, int MU, bool CONS>
-hipError_t launch_list(const DenseArgs* probs, const int4* items, int n_items, int grid, hipStream_t st)
+hipError_t launch_list(const DenseArgs* probs, const int4* items, int n_items, hipStream_t st)
 {
     constexpr int NT = NT2;
     const size_t lds = sizeof(C2Shared<T, MU, CONS>);
     auto kern = k_cmap2d_list<T, MU, CONS, NT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    (void)grid; // one workgroup per item, 8 x ceil(n / 8) of them
     hipLaunchKernelGGL(kern, dim3(8 * ((n_items + 7) / 8)), dim3(NT), lds, st, probs, items, n_items);
     return hipGetLastError();
 }
@@ -603,15 +602,15 @@ hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int
     return cons ? go(float(), std::true_type{}) : go(float(), std::false_type{});
 }
 
-hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int grid, int m, bool cons,
-                                 bool fp64, hipStream_t st)
+hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int m, bool cons, bool fp64,
+                                 hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    if (grid < 1) grid = 1;
+    if (n_items > INT32_MAX - 7) return hipErrorInvalidValue;
     auto go = [&](auto T_tag, auto c_tag) {
         using T = decltype(T_tag);
         constexpr bool C = decltype(c_tag)::value;
-        return by_m<T, C>(m, [&](auto mu) { return launch_list<T, decltype(mu)::value, C>(probs, items, n_items, grid, st); });
+        return by_m<T, C>(m, [&](auto mu) { return launch_list<T, decltype(mu)::value, C>(probs, items, n_items, st); });
     };
     if (fp64) return cons ? go(double(), std::true_type{}) : go(double(), std::false_type{});
     return cons ? go(float(), std::true_type{}) : go(float(), std::false_type{});

@@ -582,55 +582,51 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged(DenseArgs a)
     else dense_tile_chunked<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
 }
 
+// The batched launches run one workgroup per item of a work list (launched as 8 x
+// ceil(n / 8) workgroups): workgroup b runs on XCD b mod 8, and the workgroups of one XCD
+// take a contiguous part of the list (the items of a problem are contiguous), so items
+// that share halo rows of input nodes share that XCD's L2.  (A persistent loop over items
+// holds an item's loop-invariant values across items: up to a hundred more registers.)
+__device__ inline int list_item(int n_items)
+{
+    const int b = blockIdx.x;
+    return (b % 8) * ((n_items + 7) / 8) + b / 8;
+}
+
 template <typename T, int MU, bool CONS, int TX, int FORM>
 __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_staged_list(const DenseArgs* __restrict__ probs,
                                                                    const int4* __restrict__ tiles, int n_tiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int b = blockIdx.x, nb = gridDim.x;
-    const int nx = nb < 8 ? nb : 8;
-    const int xcd = b % nx, slot = b / nx;
-    const int per_xcd = (nb + nx - 1 - xcd) / nx;
-    const int chunk = (n_tiles + nx - 1) / nx;
-    const int t0 = xcd * chunk, t1 = min(n_tiles, t0 + chunk);
-    for (int t = t0 + slot; t < t1; t += per_xcd) {
-        const int4 tl = tiles[t];
-        const int pi = __builtin_amdgcn_readfirstlane(tl.x);
-        const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
-        const DenseArgs a = probs[pi];
-        if constexpr (FORM == 1) dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
-        else dense_tile_chunked<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
-        __syncthreads(); // the next tile's staging overwrites the LDS
-    }
+    const int t = list_item(n_tiles);
+    if (t >= n_tiles) return; // whole workgroup
+    const int4 tl = tiles[t];
+    const int pi = __builtin_amdgcn_readfirstlane(tl.x);
+    const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
+    const DenseArgs a = probs[pi];
+    if constexpr (FORM == 1) dense_tile_staged<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
+    else dense_tile_chunked<T, MU, CONS, TX>(a, x0, y0, reinterpret_cast<T*>(smem_raw));
 }
 
-// many 2-D problems of one (m, method): a persistent grid walks a work list of tiles
-// (problem, x0, y0) of TX x (256 / TX) cells (TX = that problem's tile_x).  Workgroup b
-// runs on XCD b mod 8 and takes a contiguous part of the list (the tiles of a problem
-// are contiguous), so tiles that share halo rows of input nodes share that XCD's L2.
+// many 2-D problems of one (m, method): one workgroup per item of a work list of tiles
+// (problem, x0, y0) of TX x (256 / TX) cells (TX = that problem's tile_x).
 template <typename T, int MU, bool CONS>
 __global__ void __launch_bounds__(DENSE_BLOCK) k_dense_list(const DenseArgs* __restrict__ probs,
                                                             const int4* __restrict__ tiles, int n_tiles)
 {
-    const int b = blockIdx.x, nb = gridDim.x;
-    const int nx = nb < 8 ? nb : 8;
-    const int xcd = b % nx, slot = b / nx;
-    const int per_xcd = (nb + nx - 1 - xcd) / nx;
-    const int chunk = (n_tiles + nx - 1) / nx;
-    const int t0 = xcd * chunk, t1 = min(n_tiles, t0 + chunk);
-    for (int t = t0 + slot; t < t1; t += per_xcd) {
-        // the tile and its problem are the same for the whole workgroup: read them as
-        // wave-uniform values, so that the descriptor and the cell map G stay on the scalar
-        // unit as in the single-problem kernel
-        const int4 tl = tiles[t];
-        const int pi = __builtin_amdgcn_readfirstlane(tl.x);
-        const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
-        const DenseArgs a = probs[pi];
-        const int tx = a.tile_x;
-        const int x = x0 + (int)threadIdx.x % tx;
-        const int y = y0 + (int)threadIdx.x / tx;
-        if (x < a.ext_to[0] && y < a.ext_to[1]) dense_cell<T, 2, MU, CONS>(a, x + (int64_t)a.ext_to[0] * y);
-    }
+    const int t = list_item(n_tiles);
+    if (t >= n_tiles) return; // whole workgroup
+    // the tile and its problem are the same for the whole workgroup: read them as
+    // wave-uniform values, so that the descriptor and the cell map G stay on the scalar
+    // unit as in the single-problem kernel
+    const int4 tl = tiles[t];
+    const int pi = __builtin_amdgcn_readfirstlane(tl.x);
+    const int x0 = __builtin_amdgcn_readfirstlane(tl.y), y0 = __builtin_amdgcn_readfirstlane(tl.z);
+    const DenseArgs a = probs[pi];
+    const int tx = a.tile_x;
+    const int x = x0 + (int)threadIdx.x % tx;
+    const int y = y0 + (int)threadIdx.x / tx;
+    if (x < a.ext_to[0] && y < a.ext_to[1]) dense_cell<T, 2, MU, CONS>(a, x + (int64_t)a.ext_to[0] * y);
 }
 
 // the staged form's LDS: at most the 160 KB of a CU
@@ -679,55 +675,55 @@ hipError_t launch(const DenseArgs& a, hipStream_t st)
 }
 
 template <typename T, int MU, bool CONS, int TX, int FORM>
-hipError_t launch_staged_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, hipStream_t st)
+hipError_t launch_staged_list(const DenseArgs* probs, const int4* tiles, int n_tiles, hipStream_t st)
 {
     const size_t lds = staged_lds<T, MU, CONS, FORM>(TX);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_dense_staged_list<T, MU, CONS, TX, FORM>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(DENSE_BLOCK), lds, st, probs, tiles, n_tiles);
+    hipLaunchKernelGGL(kern, dim3(8 * ((n_tiles + 7) / 8)), dim3(DENSE_BLOCK), lds, st, probs, tiles, n_tiles);
     return hipGetLastError();
 }
 
 template <typename T, int MU, bool CONS>
-hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int staged_tx,
-                       hipStream_t st)
+hipError_t launch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int staged_tx, hipStream_t st)
 {
     switch (staged_tx) {
     case 0: break;
-    case 32: return launch_staged_list<T, MU, CONS, 32, 1>(probs, tiles, n_tiles, grid, st);
-    case 64: return launch_staged_list<T, MU, CONS, 64, 1>(probs, tiles, n_tiles, grid, st);
-    case 1032: return launch_staged_list<T, MU, CONS, 32, 2>(probs, tiles, n_tiles, grid, st);
-    case 1064: return launch_staged_list<T, MU, CONS, 64, 2>(probs, tiles, n_tiles, grid, st);
+    case 32: return launch_staged_list<T, MU, CONS, 32, 1>(probs, tiles, n_tiles, st);
+    case 64: return launch_staged_list<T, MU, CONS, 64, 1>(probs, tiles, n_tiles, st);
+    case 1032: return launch_staged_list<T, MU, CONS, 32, 2>(probs, tiles, n_tiles, st);
+    case 1064: return launch_staged_list<T, MU, CONS, 64, 2>(probs, tiles, n_tiles, st);
     default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_dense_list<T, MU, CONS>), dim3(grid), dim3(DENSE_BLOCK), 0, st, probs, tiles, n_tiles);
+    hipLaunchKernelGGL((k_dense_list<T, MU, CONS>), dim3(8 * ((n_tiles + 7) / 8)), dim3(DENSE_BLOCK), 0, st, probs, tiles,
+                       n_tiles);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t dispatch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
-                         int staged_tx, hipStream_t st)
+hipError_t dispatch_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int m, bool cons, int staged_tx,
+                         hipStream_t st)
 {
     if (cons) {
         switch (m) {
-        case 0: return launch_list<T, 1, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 1: return launch_list<T, 2, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 2: return launch_list<T, 3, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 3: return launch_list<T, 4, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 4: return launch_list<T, 5, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 5: return launch_list<T, 6, true>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 6: return launch_list<T, 7, true>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 0: return launch_list<T, 1, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 1: return launch_list<T, 2, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 2: return launch_list<T, 3, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 3: return launch_list<T, 4, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 4: return launch_list<T, 5, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 5: return launch_list<T, 6, true>(probs, tiles, n_tiles, staged_tx, st);
+        case 6: return launch_list<T, 7, true>(probs, tiles, n_tiles, staged_tx, st);
         }
     } else {
         switch (m) {
-        case 1: return launch_list<T, 2, false>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 2: return launch_list<T, 3, false>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 3: return launch_list<T, 4, false>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 4: return launch_list<T, 5, false>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 5: return launch_list<T, 6, false>(probs, tiles, n_tiles, grid, staged_tx, st);
-        case 6: return launch_list<T, 7, false>(probs, tiles, n_tiles, grid, staged_tx, st);
+        case 1: return launch_list<T, 2, false>(probs, tiles, n_tiles, staged_tx, st);
+        case 2: return launch_list<T, 3, false>(probs, tiles, n_tiles, staged_tx, st);
+        case 3: return launch_list<T, 4, false>(probs, tiles, n_tiles, staged_tx, st);
+        case 4: return launch_list<T, 5, false>(probs, tiles, n_tiles, staged_tx, st);
+        case 5: return launch_list<T, 6, false>(probs, tiles, n_tiles, staged_tx, st);
+        case 6: return launch_list<T, 7, false>(probs, tiles, n_tiles, staged_tx, st);
         }
     }
     return hipErrorInvalidValue;
@@ -798,13 +794,13 @@ bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form)
     return words * (fp64 ? 8 : 4) <= kMaxLds;
 }
 
-hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int grid, int m, bool cons,
-                                bool fp64, int staged_tx, hipStream_t st)
+hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n_tiles, int m, bool cons, bool fp64,
+                                int staged_tx, hipStream_t st)
 {
     if (n_tiles <= 0) return hipSuccess;
-    if (grid < 1) grid = 1;
-    return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, grid, m, cons, staged_tx, st)
-                : dispatch_list<float>(probs, tiles, n_tiles, grid, m, cons, staged_tx, st);
+    if (n_tiles > INT32_MAX - 7) return hipErrorInvalidValue;
+    return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, m, cons, staged_tx, st)
+                : dispatch_list<float>(probs, tiles, n_tiles, m, cons, staged_tx, st);
 }
 
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
