@@ -31,7 +31,9 @@
 //      the outputs are staged in LDS for the coalesced stores of step 1.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "hw_kernels.h"
@@ -80,6 +82,41 @@ struct Mf<double> {
     typedef double vec __attribute__((ext_vector_type(4)));
     static __device__ inline vec mac(double a, double b, vec c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+// Buffer loads and stores of one element at a 32-bit byte offset from a buffer resource
+// (a wave-uniform 64-bit base and a size, in scalar registers): the per-lane address is the
+// offset alone, with no 64-bit vector arithmetic per access.  Offsets past the size read
+// zero and drop stores.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    // gfx9 resource word 3: raw (untyped) 32-bit elements
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+struct BufIO;
+template <>
+struct BufIO<float> {
+    static __device__ inline float load(__amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+    }
+    static __device__ inline void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, 0, 0);
+    }
+};
+template <>
+struct BufIO<double> {
+    typedef unsigned int W __attribute__((ext_vector_type(2)));
+    static __device__ inline double load(__amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+    }
+    static __device__ inline void store(double v, __amdgpu_buffer_rsrc_t r, uint32_t o)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, o, 0, 0);
+    }
 };
 
 // Tables per problem (lambda and tau are inside the composed map):
@@ -159,7 +196,11 @@ __host__ __device__ inline void coef3(int c, int& lx, int& ly, int& lz)
 // workgroups of 8 waves per CU, i.e. 4 waves per SIMD, which caps the registers at 128
 // per lane (the LDS footprint allows two workgroups); FP64: one workgroup, 2 waves per
 // SIMD (at most 256 registers)
-template <typename T, int CY, int NT, bool CONS>
+// OFF: type of the per-thread byte offsets within a layer of the node arrays -- uint32_t
+// when a layer of u fits 4 GB (the loads and stores then go through buffer resources made
+// per layer from its wave-uniform base: no per-layer vector address arithmetic), else
+// int64_t (global loads and stores at base + offset)
+template <typename T, int CY, int NT, bool CONS, typename OFF>
 __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs a, int tz, const CTables<T, CONS>* __restrict__ tabs)
 {
     using MF = Mf<T>;
@@ -175,14 +216,24 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
     static_assert(NW == 4 || (NW % 8 == 0 && (NC / 16) % (NW / 8) == 0), "waves must tile the products");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SH& sh = *reinterpret_cast<SH*>(smem_raw);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     const int tiles_x = (a.ext_to[0] + CX - 1) / CX;
     const int x0 = (blockIdx.x % tiles_x) * CX, y0 = (blockIdx.x / tiles_x) * CY;
     const int cz0 = blockIdx.y * tz, cz1 = min(cz0 + tz, a.ext_to[2]);
     const int off = (a.to_grid == 1) ? 0 : -1; // input node of corner s = cell + off + s
-    const T* __restrict__ gu = (const T*)a.u_in;
-    const T* __restrict__ gv = (const T*)a.v_in;
+    typedef const __attribute__((address_space(1))) T* GIn;
+    typedef __attribute__((address_space(1))) T* GOut;
+    const GIn gu = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_in));
+    const GIn gv = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.v_in));
+    // element at byte offset o from a (wave-uniform) base
+    auto at = [](auto base, OFF o) {
+        using P = decltype(base);
+        typedef typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
+                                          const __attribute__((address_space(1))) char*,
+                                          __attribute__((address_space(1))) char*>::type C;
+        return reinterpret_cast<P>(reinterpret_cast<C>(base) + o);
+    };
 
     constexpr int TSZ = S::TSZ, SX = S::SX, SY = S::SY;
     // dissipative: slot 91 of every node (the padding input) holds zero, so the
@@ -210,40 +261,60 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
         }
     }
 
-    // ---- node loads: slot i of this thread = element tid + i NT of the layer's
-    //      NNODE x 91 block; the xy part and the xy ghost signs are fixed per column ----
+    // ---- node loads: slot i of this thread = element tid + i NT of the layer's block of
+    //      the NNODE u records (64 each) followed by the NNODE v records (27 each); NNODE x
+    //      64 is a multiple of 64, so every wave's slot reads one of the two arrays, whose
+    //      layer base is then wave-uniform.  The xy part, the xy ghost signs and the LDS
+    //      slot are fixed per column ----
     const long long plane = (long long)a.ext_from[0] * a.ext_from[1];
-    int ld_off[NLOAD], ld_msk[NLOAD];
+    constexpr int NUE = NNODE * 64; // u elements of a layer
+    OFF ld_off[NLOAD];              // byte offset within the layer of u or v
+    int ld_msk[NLOAD];              // bit 1: negate (xy ghost), bit 3: l_z odd, bits 4..: LDS slot
     T rl[NLOAD];
 #pragma unroll
     for (int i = 0; i < NLOAD; ++i) {
         const int e = tid + i * NT;
         ld_off[i] = 0;
-        ld_msk[i] = 4; // idle slot: reads u of node 0 of the layer, never stashed
+        ld_msk[i] = -1; // idle slot: reads node 0 of the layer, never stashed
         if (e >= NNODE * NI) continue;
-        const int node = e / NI, c = e % NI;
+        const bool isu = e < NUE;
+        const int node = isu ? e >> 6 : (e - NUE) / 27, c = isu ? e & 63 : 64 + (e - NUE) % 27;
         int lx, ly, lz;
         coef3(c, lx, ly, lz);
         const Map1 mx = map_node(x0 + off + node % NXL, a.ext_from[0], a.bc[0]);
         const Map1 my = map_node(y0 + off + node / NXL, a.ext_from[1], a.bc[1]);
-        const int nxy = mx.j + a.ext_from[0] * my.j;
-        ld_off[i] = c < 64 ? nxy * 64 + c : nxy * 27 + (c - 64);
+        const long long nxy = mx.j + (long long)a.ext_from[0] * my.j;
+        ld_off[i] = (OFF)((isu ? nxy * 64 + c : nxy * 27 + (c - 64)) * (long long)sizeof(T));
         bool neg = false;
         if (mx.ghost && flips(a.bc[0], lx)) neg = !neg;
         if (my.ghost && flips(a.bc[1], ly)) neg = !neg;
-        ld_msk[i] = 1 | (neg ? 2 : 0) | (c < 64 ? 4 : 0) | ((lz & 1) << 3);
+        const int slot = (node % NXL) * SX + (node / NXL) * SY + c;
+        ld_msk[i] = (neg ? 2 : 0) | ((lz & 1) << 3) | (slot << 4);
     }
+    constexpr bool BUF = std::is_same<OFF, uint32_t>::value;
+    const uint32_t ubytes = (uint32_t)(plane * 64 * sizeof(T)), vbytes = (uint32_t)(plane * 27 * sizeof(T));
     int zghost = 0;
     auto fetch = [&](int layer_gz) {
         const Map1 mz = map_node(layer_gz, a.ext_from[2], a.bc[2]);
         zghost = mz.ghost;
         const long long zn = plane * mz.j;
-        // every slot loads (idle slots from node 0 of u): no branches, so the loads
-        // stay in flight until the stash of the next pass
+        const GIn lu = gu + zn * 64, lv = CONS ? lu : gv + zn * 27;
+        // every slot loads (idle slots from node 0): no branches, so the loads stay in
+        // flight until the stash of the next pass
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t ru = make_rsrc((const void*)lu, ubytes);
+            const __amdgpu_buffer_rsrc_t rv = CONS ? ru : make_rsrc((const void*)lv, vbytes);
 #pragma unroll
-        for (int i = 0; i < NLOAD; ++i) {
-            const T* src = (CONS || (ld_msk[i] & 4)) ? gu + zn * 64 : gv + zn * 27;
-            rl[i] = src[ld_off[i]];
+            for (int i = 0; i < NLOAD; ++i) {
+                const bool isu = CONS || i * NT + 64 * wave < NUE; // wave-uniform
+                rl[i] = BufIO<T>::load(isu ? ru : rv, (uint32_t)ld_off[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NLOAD; ++i) {
+                const bool isu = CONS || i * NT + 64 * wave < NUE; // wave-uniform
+                rl[i] = *at(isu ? lu : lv, ld_off[i]);
+            }
         }
     };
     auto stash = [&]() {
@@ -256,62 +327,86 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
             const int m = ld_msk[i];
             bool neg = (m & 2) != 0;
             if (zghost && (((m >> 3) & 1) != 0) == zflip_odd) neg = !neg;
-            const int n = e / NI;
-            sh.nd[(n % NXL) * SX + (n / NXL) * SY + e % NI] = neg ? -rl[i] : rl[i];
+            sh.nd[m >> 4] = neg ? -rl[i] : rl[i];
         }
     };
 
-    // ---- staged outputs of a cell layer, stored coalesced ----
+    // ---- staged outputs of a cell layer, stored coalesced: per thread, output slot k
+    //      (element tid + k NT of the layer's NC u or v records) at a byte offset within
+    //      the output layer fixed per column; bit k of s_ok: the cell is inside the grid ----
     const int nlayers = cz1 - cz0 + 1;
+    constexpr int NSU = (NC * 64 + NT - 1) / NT, NSV = CONS ? 1 : (NC * 27 + NT - 1) / NT;
+    OFF su_off[NSU], sv_off[NSV];
+    int s_ok = 0;
+#pragma unroll
+    for (int k = 0; k < NSU; ++k) {
+        const int i = tid + k * NT, c = (i >> 6) % NC, coef = i & 63;
+        const int gx = x0 + c % CX, gy = y0 + c / CX;
+        su_off[k] = (OFF)(((gx + (long long)a.ext_to[0] * gy) * 64 + coef) * (long long)sizeof(T));
+        if (i < NC * 64 && gx < a.ext_to[0] && gy < a.ext_to[1]) s_ok |= 1 << k;
+    }
+#pragma unroll
+    for (int k = 0; k < NSV; ++k) {
+        const int i = tid + k * NT, c = (i / 27) % NC, coef = i % 27;
+        const int gx = x0 + c % CX, gy = y0 + c / CX;
+        sv_off[k] = (OFF)(((gx + (long long)a.ext_to[0] * gy) * 27 + coef) * (long long)sizeof(T));
+        if (!CONS && i < NC * 27 && gx < a.ext_to[0] && gy < a.ext_to[1]) s_ok |= 1 << (16 + k);
+    }
+    const long long plane_to = (long long)a.ext_to[0] * a.ext_to[1];
     // conservative: the old level of the cell layer stored in the next pass, loaded at the
     // end of this pass's loads so that its latency overlaps the layer's work
-    constexpr int NSU = CONS ? (NC * 64 + NT - 1) / NT : 1;
-    T ov[NSU];
-    long long ogi[NSU];
+    T ov[CONS ? NSU : 1];
+    const uint32_t uobytes = (uint32_t)(plane_to * 64 * sizeof(T)), vobytes = (uint32_t)(plane_to * 27 * sizeof(T));
     auto old_fetch = [&](int cz) {
-        const T* __restrict__ old_u = (const T*)a.u_old;
+        if constexpr (CONS) {
+            const GIn old_l = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old)) + plane_to * cz * 64;
+            if constexpr (BUF) {
+                const __amdgpu_buffer_rsrc_t r = make_rsrc((const void*)old_l, uobytes);
 #pragma unroll
-        for (int k = 0; k < NSU; ++k) {
-            const int i = tid + k * NT, c = i >> 6, coef = i & 63;
-            const int gx = x0 + c % CX, gy = y0 + c / CX;
-            ogi[k] = -1;
-            if (i >= NC * 64 || gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
-            ogi[k] = (gx + (long long)a.ext_to[0] * gy + (long long)a.ext_to[0] * a.ext_to[1] * cz) * 64 + coef;
-            ov[k] = old_u[ogi[k]];
+                for (int k = 0; k < NSU; ++k)
+                    if (s_ok & (1 << k)) ov[k] = BufIO<T>::load(r, (uint32_t)su_off[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NSU; ++k)
+                    if (s_ok & (1 << k)) ov[k] = *at(old_l, su_off[k]);
+            }
         }
     };
     T* const ou_base = sh.out;
     T* const ov_base = sh.out + NC * OUS;
-    const long long plane_to = (long long)a.ext_to[0] * a.ext_to[1];
     auto store_layer = [&](int cz) {
-        T* __restrict__ out_u = (T*)a.u_out;
-        T* __restrict__ out_v = (T*)a.v_out;
-        if constexpr (CONS) {
-            // u_new = 2 S - u_old, the old values loaded one pass earlier (old_fetch)
-            (void)cz;
+        const GOut out_u = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + plane_to * cz * 64;
+        const GOut out_v = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + plane_to * cz * 27;
+        // (unused where BUF is false)
+        const __amdgpu_buffer_rsrc_t ru = make_rsrc((const void*)out_u, uobytes);
+        const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void*)out_v, vobytes);
+        auto put = [&](GOut base, __amdgpu_buffer_rsrc_t r, OFF o, T v) {
+            if constexpr (BUF) BufIO<T>::store(v, r, (uint32_t)o);
+            else *at(base, o) = v;
+        };
 #pragma unroll
-            for (int k = 0; k < NSU; ++k) {
-                const int i = tid + k * NT, c = i >> 6, coef = i & 63;
-                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * ou_base[c * OUS + coef] - ov[k];
+        for (int k = 0; k < NSU; ++k) {
+            const int i = tid + k * NT, c = i >> 6, coef = i & 63;
+            if (!(s_ok & (1 << k))) continue;
+            // conservative: u_new = 2 S - u_old, the old values loaded one pass earlier
+            if constexpr (CONS) put(out_u, ru, su_off[k], T(2) * ou_base[c * OUS + coef] - ov[k]);
+            else put(out_u, ru, su_off[k], ou_base[c * OUS + coef]);
+        }
+        if constexpr (!CONS) {
+#pragma unroll
+            for (int k = 0; k < NSV; ++k) {
+                const int i = tid + k * NT;
+                if (s_ok & (1 << (16 + k))) put(out_v, rv, sv_off[k], ov_base[i]);
             }
-            return;
-        }
-        for (int i = tid; i < NC * 64; i += NT) {
-            const int c = i >> 6, coef = i & 63;
-            const int gx = x0 + c % CX, gy = y0 + c / CX;
-            if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
-            out_u[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 64 + coef] = ou_base[c * OUS + coef];
-        }
-        for (int i = tid; i < NC * 27; i += NT) {
-            const int c = i / 27, coef = i % 27;
-            const int gx = x0 + c % CX, gy = y0 + c / CX;
-            if (gx >= a.ext_to[0] || gy >= a.ext_to[1]) continue;
-            out_v[(gx + (long long)a.ext_to[0] * gy + plane_to * cz) * 27 + coef] = ov_base[c * 27 + coef];
         }
     };
 
     constexpr int NBF = (NC * TL + NT - 1) / NT; // butterfly slots per thread
-    T prev[NBF][4];                              // T_pxy of the lower node layer
+    // T_pxy of the lower node layer: with two sets (where the registers allow: not in the
+    // FP32 dissipative kernel, which would spill), the pass over layer `step` writes its
+    // own into set step & 1 and reads the lower layer's from the other (no copies)
+    constexpr int NPS = (sizeof(T) == 8 || CONS) ? 2 : 1;
+    T prev[NPS][NBF][4];
     int bkp[NBF], bl[NBF];                       // K position and input of each slot
 #pragma unroll
     for (int k = 0; k < NBF; ++k) {
@@ -319,8 +414,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
         bkp[k] = t < NC * TL ? tabs->bk[2 * ((t >> 5) / (NC / 16)) + ((t >> 4) & 1)] : 0;
         bl[k] = tabs->kl[bkp[k]];
     }
-    fetch(cz0 + off);
-    for (int step = 0; step < nlayers; ++step) {
+    auto pass = [&](auto B, int step) {
+        constexpr int CUR = NPS == 2 ? decltype(B)::value : 0, LO = NPS == 2 ? 1 - CUR : 0;
         stash();
         __syncthreads();
         if (step >= 2) store_layer(cz0 + step - 2);
@@ -347,15 +442,15 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
                 T* dst = sh.tsum + cell * TSZ + kp;
 #pragma unroll
                 for (int pxy = 0; pxy < 4; ++pxy) {
-                    dst[pxy * TL] = prev[k][pxy] + cur[pxy];
-                    dst[(4 + pxy) * TL] = prev[k][pxy] - cur[pxy];
+                    dst[pxy * TL] = prev[LO][k][pxy] + cur[pxy];
+                    dst[(4 + pxy) * TL] = prev[LO][k][pxy] - cur[pxy];
                 }
             }
 #pragma unroll
-            for (int pxy = 0; pxy < 4; ++pxy) prev[k][pxy] = cur[pxy];
+            for (int pxy = 0; pxy < 4; ++pxy) prev[CUR][k][pxy] = cur[pxy];
         }
         __syncthreads();
-        if (step == 0) continue; // the first layer only primes the sums
+        if (step == 0) return; // the first layer only primes the sums
 
         // ---- 3. class products for the cell layer between the two node layers ----
         T bv[CPW][GPW][KS];
@@ -403,6 +498,11 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
                     ou_base[o] = acc[c][g][r];
                 }
             }
+    };
+    fetch(cz0 + off);
+    for (int step = 0; step < nlayers; step += 2) {
+        pass(std::integral_constant<int, 0>{}, step);
+        if (step + 1 < nlayers) pass(std::integral_constant<int, 1>{}, step + 1);
     }
     if (nlayers >= 2) {
         __syncthreads();
@@ -505,11 +605,11 @@ hipError_t create(const ProblemDesc& D, void** out)
     return hipSuccess;
 }
 
-template <typename T, int CY, int NT, bool CONS>
+template <typename T, int CY, int NT, bool CONS, typename OFF>
 hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
     const size_t lds = sizeof(CShared<T, CY, CONS>);
-    auto kern = k_cmap3d<T, CY, NT, CONS>;
+    auto kern = k_cmap3d<T, CY, NT, CONS, OFF>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // z-chunks of 64 cell layers, doubled while at least 2048 workgroups remain (each
@@ -544,6 +644,14 @@ hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
     // FP32: 62 KB (dissipative) / 46 KB (conservative) of LDS and at most 128 registers:
     // two workgroups per CU, four waves per SIMD; FP64: 123 / 92 KB, one workgroup per CU
     // (two waves per SIMD)
-    if (a.cons) return fp64 ? launch<double, 4, 512, true>(a, st) : launch<float, 4, 512, true>(a, st);
-    return fp64 ? launch<double, 4, 512, false>(a, st) : launch<float, 4, 512, false>(a, st);
+    // 32-bit offsets within a layer where a layer of u (64 coefficients per node) of either
+    // grid fits 4 GB
+    const double layer = 64.0 * (fp64 ? 8 : 4) * std::max((double)a.ext_from[0] * a.ext_from[1],
+                                                           (double)a.ext_to[0] * a.ext_to[1]);
+    if (layer < 4294967296.0) {
+        if (a.cons) return fp64 ? launch<double, 4, 512, true, uint32_t>(a, st) : launch<float, 4, 512, true, uint32_t>(a, st);
+        return fp64 ? launch<double, 4, 512, false, uint32_t>(a, st) : launch<float, 4, 512, false, uint32_t>(a, st);
+    }
+    if (a.cons) return fp64 ? launch<double, 4, 512, true, int64_t>(a, st) : launch<float, 4, 512, true, int64_t>(a, st);
+    return fp64 ? launch<double, 4, 512, false, int64_t>(a, st) : launch<float, 4, 512, false, int64_t>(a, st);
 }
