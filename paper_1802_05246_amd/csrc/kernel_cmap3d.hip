@@ -49,9 +49,10 @@ constexpr int NXL = CX + 1;
 //     SX = 2, SY = 8 (mod 32), so that a corner's 16 nodes fall on the 16 even banks
 //     (2 (x + 4 y) mod 32) and the second input of the pass, whose index has the other
 //     parity, on the odd ones; FP64: SX = 1, SY = 4 (mod 16), one input per pass;
-//   * butterfly sums [cell][p][k] (k: the K position of the input): cell stride = 2
-//     (mod 32) in FP32 (K positions 4 ks and 4 ks + 1 of a product's operand pass on the
-//     even and odd banks), odd in FP64
+//   * butterfly sums [cell][ks][p][k mod 4] (k = 4 ks + k mod 4: the K position of the
+//     input), so that the 8 sums of one input lie within 29 words of each other (one base
+//     address for the butterfly's writes): cell stride = 2 (mod 32) in FP32 (K positions
+//     4 ks and 4 ks + 1 of a product's operand pass on the even and odd banks), odd in FP64
 // Dissipative method: 91 inputs per node (u 64, v 27) in 23 K-steps (K position 91 reads
 // a zero slot of every node), 91 outputs; conservative method (Sec. 4.1): the even time
 // sum S of the u inputs, 64 inputs in 16 K-steps, 64 outputs, u_new = 2 S - u_old.
@@ -123,9 +124,9 @@ struct BufIO<double> {
 //   ta[8][KS][64]  A operand of class q: entry (row i = lane % 16, K position 4 ks + lane / 16,
 //                  which holds input perm[4 ks + lane / 16], see create())
 //   tb[8][KS][4]   per (class, K-step, lane / 16): offset of the selected butterfly sum in a
-//                  cell's block, p * TL + k with p = p_x + 2 p_y + 4 p_z of the input at
-//                  K position k = 4 ks + lane / 16; the padding position k = 91 reads the
-//                  zero sums of the zero node slot 91
+//                  cell's block, 32 ks + 4 p + lane / 16 with p = p_x + 2 p_y + 4 p_z of the
+//                  input at K position k = 4 ks + lane / 16; the padding position k = 91
+//                  reads the zero sums of the zero node slot 91
 //   kl[4 KS]       input at K position k (91 for the padding position)
 //   bk[4 KS]       K positions of the butterfly passes, two per pass of 16 cells: an even
 //                  and an odd position whose inputs have indices of opposite parity
@@ -145,9 +146,11 @@ template <typename T, int CY, bool CONS>
 struct CShared {
     using S = Shape<T, CONS>;
     static constexpr int NC = CX * CY, NNODE = NXL * (CY + 1);
+    // the node layer first: its reads then take the per-thread slot address with small
+    // immediate offsets
+    alignas(16) T nd[(CY * S::SY + NXL * S::SX + 3) / 4 * 4];
     alignas(16) T tsum[NC * S::TSZ];
     alignas(16) T out[NC * (OUS + S::NV)];
-    T nd[CY * S::SY + NXL * S::SX];
 };
 
 struct Map1 {
@@ -403,9 +406,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
 
     constexpr int NBF = (NC * TL + NT - 1) / NT; // butterfly slots per thread
     // T_pxy of the lower node layer: with two sets (where the registers allow: not in the
-    // FP32 dissipative kernel, which would spill), the pass over layer `step` writes its
-    // own into set step & 1 and reads the lower layer's from the other (no copies)
-    constexpr int NPS = (sizeof(T) == 8 || CONS) ? 2 : 1;
+    // FP32 dissipative kernel with 64-bit offsets, which would spill), the pass over layer
+    // `step` writes its own into set step & 1 and reads the lower layer's from the other
+    // (no copies)
+    constexpr int NPS = (sizeof(T) == 8 || CONS || BUF) ? 2 : 1;
     T prev[NPS][NBF][4];
     int bkp[NBF], bl[NBF];                       // K position and input of each slot
 #pragma unroll
@@ -439,11 +443,11 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
             const T p = x00 + x10, q = x00 - x10, r = x01 + x11, s = x01 - x11;
             const T cur[4] = {p + r, q + s, p - r, q - s};
             if (step > 0) {
-                T* dst = sh.tsum + cell * TSZ + kp;
+                T* dst = sh.tsum + cell * TSZ + 32 * (kp >> 2) + (kp & 3);
 #pragma unroll
                 for (int pxy = 0; pxy < 4; ++pxy) {
-                    dst[pxy * TL] = prev[LO][k][pxy] + cur[pxy];
-                    dst[(4 + pxy) * TL] = prev[LO][k][pxy] - cur[pxy];
+                    dst[4 * pxy] = prev[LO][k][pxy] + cur[pxy];
+                    dst[4 * (4 + pxy)] = prev[LO][k][pxy] - cur[pxy];
                 }
             }
 #pragma unroll
@@ -517,7 +521,7 @@ template <typename T, bool CONS>
 hipError_t create(const ProblemDesc& D, void** out)
 {
     using S = Shape<T, CONS>;
-    constexpr int NI = S::NI, KS = S::KS, TL = S::TL;
+    constexpr int NI = S::NI, KS = S::KS;
     using Tab = CTables<T, CONS>;
     std::vector<double> G;
     int n_in = 0, n_out = 0;
@@ -579,13 +583,13 @@ hipError_t create(const ProblemDesc& D, void** out)
             for (int g = 0; g < 4; ++g) {
                 const int l = perm[4 * ks + g];
                 if (l < 0) {
-                    h->tb[q][ks][g] = 4 * ks + g; // p = 0: the sums of the zero node slot
+                    h->tb[q][ks][g] = 32 * ks + g; // p = 0: the sums of the zero node slot
                     continue;
                 }
                 int lx, ly, lz;
                 coef3(l, lx, ly, lz);
                 const int px = (qx + lx) & 1, py = (qy + ly) & 1, pz = (qz + lz) & 1;
-                h->tb[q][ks][g] = (px + 2 * py + 4 * pz) * TL + 4 * ks + g;
+                h->tb[q][ks][g] = 32 * ks + 4 * (px + 2 * py + 4 * pz) + g;
             }
             for (int lanei = 0; lanei < 64; ++lanei) {
                 const int i = lanei & 15, l = perm[4 * ks + (lanei >> 4)];
