@@ -7,6 +7,7 @@
 #include "hw_device.h"
 #include "../../include/hermite_wave.h"
 
+#include <atomic>
 #include <functional>
 #include <string>
 #include <vector>
@@ -27,6 +28,26 @@ hipError_t hw_launch_convert(const void* src, bool src64, void* dst, bool dst64,
 // array.  hipErrorInvalidValue for a grid outside 1..HW_ENERGY_MAX_GROUPS.
 constexpr int HW_ENERGY_MAX_GROUPS = 2048;
 constexpr int HW_MAX_DEVICES = 64;
+
+// Raises kernel K's dynamic LDS limit (hipFuncSetAttribute) only when a launch needs more than
+// the limit already set for K on the current device, so that launches in a loop or while a
+// graph is captured do not repeat the call.
+template <auto K>
+inline hipError_t hw_lds_limit(size_t bytes)
+{
+    static std::atomic<int> set_bytes[HW_MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= HW_MAX_DEVICES)
+        return hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if ((int)bytes <= set_bytes[dev].load(std::memory_order_acquire)) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) {
+        int cur = set_bytes[dev].load(std::memory_order_relaxed);
+        while ((int)bytes > cur && !set_bytes[dev].compare_exchange_weak(cur, (int)bytes)) {
+        }
+    }
+    return e;
+}
 hipError_t hw_launch_energy_noalloc(int d, bool fp64, const EnergyDesc& E0, int grid0, const EnergyDesc& E1,
                                     int grid1, const double* dops, double* e_out, hipStream_t st);
 

@@ -540,7 +540,7 @@ hipError_t launch1(const DenseArgs& a, int ry, hipStream_t st)
     constexpr int NT = NT2;
     const size_t lds = sizeof(C2Shared<T, MU, CONS>);
     auto kern = k_cmap2d<T, MU, CONS, NT>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_cmap2d<T, MU, CONS, NT>>(lds);
     if (e != hipSuccess) return e;
     const dim3 grid((a.ext_to[0] + CX - 1) / CX, (a.ext_to[1] + ry - 1) / ry);
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, st, a, ry);
@@ -553,7 +553,7 @@ hipError_t launch_list(const DenseArgs* probs, const int4* items, int n_items, h
     constexpr int NT = NT2;
     const size_t lds = sizeof(C2Shared<T, MU, CONS>);
     auto kern = k_cmap2d_list<T, MU, CONS, NT>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_cmap2d_list<T, MU, CONS, NT>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(8 * ((n_items + 7) / 8)), dim3(NT), lds, st, probs, items, n_items);
     return hipGetLastError();

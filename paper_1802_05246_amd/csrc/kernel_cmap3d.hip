@@ -614,7 +614,7 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
 {
     const size_t lds = sizeof(CShared<T, CY, CONS>);
     auto kern = k_cmap3d<T, CY, NT, CONS, OFF>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_cmap3d<T, CY, NT, CONS, OFF>>(lds);
     if (e != hipSuccess) return e;
     // z-chunks of 64 cell layers, doubled while at least 2048 workgroups remain (each
     // chunk re-reads one node layer below it: longer chunks waste less)

@@ -644,7 +644,7 @@ hipError_t launch_staged(const DenseArgs& a, hipStream_t st)
     const size_t lds = staged_lds<T, MU, CONS, FORM>(TX);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_dense_staged<T, MU, CONS, TX, FORM>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_dense_staged<T, MU, CONS, TX, FORM>>(lds);
     if (e != hipSuccess) return e;
     const int blocks = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + DENSE_BLOCK / TX - 1) / (DENSE_BLOCK / TX));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(DENSE_BLOCK), lds, st, a);
@@ -680,7 +680,7 @@ hipError_t launch_staged_list(const DenseArgs* probs, const int4* tiles, int n_t
     const size_t lds = staged_lds<T, MU, CONS, FORM>(TX);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     auto kern = k_dense_staged_list<T, MU, CONS, TX, FORM>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_dense_staged_list<T, MU, CONS, TX, FORM>>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(8 * ((n_tiles + 7) / 8)), dim3(DENSE_BLOCK), lds, st, probs, tiles, n_tiles);
     return hipGetLastError();

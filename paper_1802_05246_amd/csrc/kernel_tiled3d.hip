@@ -896,7 +896,7 @@ hipError_t launch(const TiledArgs& a, hipStream_t st)
     const Tables<T>* tabs = static_cast<const Tables<T>*>(a.tables);
     const size_t lds = sizeof(Shared<T, TY>);
     auto kern = k_tiled3d_m3<T, TY, BF>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hw_lds_limit<k_tiled3d_m3<T, TY, BF>>(lds);
     if (e != hipSuccess) return e;
     const int tz = 64;
     const int tiles = ((a.ext_to[0] + TX - 1) / TX) * ((a.ext_to[1] + TY - 1) / TY);

@@ -756,8 +756,7 @@ static hipError_t launch_hs(const ProblemDesc* descs, const int64_t* prefix, int
 {
     auto kern = k_half_step<T, D>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hw_lds_limit<k_half_step<T, D>>(lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(GW), lds, st, descs, prefix, nprob, total,
@@ -788,8 +787,7 @@ static hipError_t launch_en(const EnergyDesc& E, const double* dops, double* par
     const size_t lds = hw_energy_lds_bytes(D, E.m);
     auto kern = k_energy<T, D>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hw_lds_limit<k_energy<T, D>>(lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(GW), lds, st, E, dops, partials);
