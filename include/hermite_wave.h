@@ -265,7 +265,9 @@ const char* hw_last_error(void);
  * 64 cells wide, c = -2016 (m = 3..6 only) the composed-map form on the matrix cores
  * (strips of 16 cells walking their cell rows; the four corner sums of each cell formed
  * in LDS, the cell matrix applied as 16x16x4 products).  HW_TUNE_LOG=1 prints every
- * candidate's time to stderr while it is measured.  The text is
+ * candidate's time to stderr while it is measured; "cmap3d_offsets=64" makes the 3-D
+ * composed-map kernel use 64-bit per-lane offsets, the form otherwise taken only for layers
+ * over 4 GB.  The text is
  * thread-local and valid until the next call from the same thread.  This is about the
  * implementation's launch configuration, not the method of the paper. */
 const char* hw_tuning_report(void);

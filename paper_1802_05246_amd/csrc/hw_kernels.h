@@ -131,6 +131,9 @@ hipError_t hw_launch_tiled(const TiledArgs& a, int precision, hipStream_t st);
 // timed once per process (or read from the HW_TUNE_CACHE file) and cached.
 bool hw_tune_enabled();
 int hw_tune_size_class(int64_t cells);
+// the choice HW_TUNE_FORCE imposes on `kernel`, if any (also used to select a code path in
+// tests, e.g. "cmap3d_offsets=64")
+bool hw_tune_forced(const char* kernel, int& choice);
 int hw_tune_choose(const char* kernel, int d, int m, int method, bool fp64, int size_class,
                    const std::vector<int>& candidates, const std::function<double(int)>& time_us);
 std::string hw_tune_report_text();

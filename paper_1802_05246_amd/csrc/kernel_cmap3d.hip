@@ -649,10 +649,13 @@ hipError_t hw_launch_cmap3d(const TiledArgs& a, bool fp64, hipStream_t st)
     // two workgroups per CU, four waves per SIMD; FP64: 123 / 92 KB, one workgroup per CU
     // (two waves per SIMD)
     // 32-bit offsets within a layer where a layer of u (64 coefficients per node) of either
-    // grid fits 4 GB
+    // grid fits 4 GB (HW_TUNE_FORCE="cmap3d_offsets=64" imposes the 64-bit form, so that
+    // tests reach it on small grids)
     const double layer = 64.0 * (fp64 ? 8 : 4) * std::max((double)a.ext_from[0] * a.ext_from[1],
                                                            (double)a.ext_to[0] * a.ext_to[1]);
-    if (layer < 4294967296.0) {
+    int forced = 0;
+    const bool wide = hw_tune_forced("cmap3d_offsets", forced) && forced == 64;
+    if (layer < 4294967296.0 && !wide) {
         if (a.cons) return fp64 ? launch<double, 4, 512, true, uint32_t>(a, st) : launch<float, 4, 512, true, uint32_t>(a, st);
         return fp64 ? launch<double, 4, 512, false, uint32_t>(a, st) : launch<float, 4, 512, false, uint32_t>(a, st);
     }

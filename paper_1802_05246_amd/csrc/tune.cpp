@@ -78,6 +78,8 @@ bool forced_choice(const char* kernel, int& choice)
 
 } // namespace
 
+bool hw_tune_forced(const char* kernel, int& choice) { return forced_choice(kernel, choice); }
+
 bool hw_tune_enabled()
 {
     const char* e = std::getenv("HW_AUTOTUNE");

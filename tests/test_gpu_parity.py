@@ -505,6 +505,15 @@ def test_composed_3d_m3_matches_oracle(n, bc, meth, stages, prec):
     s.close()
 
 
+@pytest.mark.parametrize("meth", [W.DISS_FULL, W.CONSERVATIVE])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_composed_3d_m3_wide_offsets_match_oracle(meth, prec, monkeypatch):
+    """The composed-map kernel's 64-bit-offset form (taken on its own only for layers over
+    4 GB) imposed on a small ragged grid with walls, against the oracle."""
+    monkeypatch.setenv("HW_TUNE_FORCE", "cmap3d_offsets=64")
+    test_composed_3d_m3_matches_oracle([6, 5, 7], [W.DIRICHLET, W.NEUMANN, W.PERIODIC], meth, 0, prec)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_tiled_equals_generic(prec):
     """Same problem through both kernels: FP64 agree to round-off, FP32 to the
