@@ -92,11 +92,11 @@ typedef enum {
                               (HW_EUNSUPPORTED otherwise) */
     HW_KERNEL_BATCH = 6    /* 2-D, FP64 or FP32, any m and method, batches or single problems:
                               the problems grouped by (m, method); per group and half step one
-                              persistent launch of the dense kernel walks a work list of tiles
-                              of every problem of the group (at most one launch per group,
-                              all of them in the captured graph); tile shapes chosen by the
-                              autotuner (HW_EUNSUPPORTED otherwise; the default for 2-D
-                              batches) */
+                              launch of the dense kernel runs one workgroup per item of a work
+                              list of tiles (or strips) of every problem of the group (at most
+                              one launch per group, all of them in the captured graph); form
+                              and tile shape chosen by the autotuner (HW_EUNSUPPORTED
+                              otherwise; the default for 2-D batches) */
 } hw_kernel;
 
 typedef enum { HW_PRIMAL = 0, HW_DUAL = 1 } hw_grid;
@@ -297,8 +297,9 @@ hw_status hw_probe_coexec(double ms_out[3]);
  * together.  All problems of a batch share d and precision.  hw_batch_advance captures
  * the step loop in a hipGraph.  How a half step of the batch is launched depends on
  * the kernel selector: HW_KERNEL_GENERIC runs one grid-stride launch over a work list
- * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_BATCH for 2-D batches run one persistent
- * dense launch per (m, method) group over the tiles of all its problems; HW_KERNEL_DENSE
+ * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_BATCH for 2-D batches run one dense
+ * launch per (m, method) group, one workgroup per tile (or strip) of all its problems, in
+ * the form the autotuner chose for the group; HW_KERNEL_DENSE
  * runs one dense launch per problem the dense kernel serves and one generic launch over
  * the remaining problems.
  * hw_batch_layout, hw_batch_set_state, hw_batch_cons_startup and hw_batch_get_state
