@@ -524,7 +524,10 @@ hw_status setup_batch_classes(hw_solver* s)
                 if (s->probs[C.probs[j]].nodes[1] > s->probs[C.probs[rep]].nodes[1]) rep = j;
             zero_state(s, C.probs[rep]);
             int4* dt = nullptr;
+            bool all_cm2 = true; // every member has composed-map tables
+            for (int j = 0; j < n; ++j) all_cm2 = all_cm2 && s->cm2_tabs[C.probs[j]] != nullptr;
             auto time_us = [&](int cand) -> double {
+                if (staged_form(cand) == 3 && !all_cm2) return -1.0;
                 std::vector<int4> tl;
                 class_tiles(s, 0, std::vector<int>{C.probs[rep]}, cand, tl);
                 for (auto& t : tl) t.x = rep;  // the list names the member's own descriptor
@@ -543,6 +546,8 @@ hw_status setup_batch_classes(hw_solver* s)
             if (dt) (void)hipFree(dt);
             const hw_status st = check_tile(C.tx, C.m, C.cons, s->fp64);
             if (st != HW_OK) return st;
+            if (staged_form(C.tx) == 3 && !all_cm2)
+                return fail(HW_EUNSUPPORTED, "composed-map form: a row of a problem exceeds 4 GB");
         }
         if (upload_args(C.tx) != hipSuccess) return fail(HW_EHIP, "batch descriptor upload failed");
         for (int ph = 0; ph < 2; ++ph) {
@@ -786,7 +791,9 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
             hw_cell_map(s->h_descs[i], G, n_in, n_out);
             // the kernel uses corner 0's rows; the others follow by reflection symmetry
             G.resize((size_t)(n_in >> s->d) * n_out);
-            if (s->d == 2 && hw_cmap2d_supported(s->probs[i].p.m)) {
+            if (s->d == 2 && hw_cmap2d_supported(s->probs[i].p.m) &&
+                hw_cmap2d_rows_fit(s->probs[i].p.m, s->probs[i].p.method == HW_CONSERVATIVE, s->fp64,
+                                   std::max(s->probs[i].ext[0][0], s->probs[i].ext[1][0]))) {
                 // tables of the composed-map form (its autotuner candidate)
                 auto it2 = made2.find(G);
                 if (it2 != made2.end()) {

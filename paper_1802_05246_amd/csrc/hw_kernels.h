@@ -108,6 +108,8 @@ bool hw_dense_staged_fits(int m, bool cons, bool fp64, int tx, int form);
 // list of strips {problem, x0, cy0, cy1} of many problems of one (m, method), one
 // workgroup per strip (the descriptors' cm2 fields name each problem's tables).
 bool hw_cmap2d_supported(int m);
+// whether a row of ext nodes of either grid fits the kernel's 32-bit byte offsets
+bool hw_cmap2d_rows_fit(int m, bool cons, bool fp64, int64_t ext);
 hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool cons, bool fp64, void** out);
 hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int ry, hipStream_t st);
 hipError_t hw_launch_cmap2d_list(const DenseArgs* probs, const int4* items, int n_items, int m, bool cons, bool fp64,

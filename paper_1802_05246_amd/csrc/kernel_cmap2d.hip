@@ -42,6 +42,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "buffer_io.h"
 #include "hw_kernels.h"
 
 namespace {
@@ -124,14 +125,15 @@ struct Map1 {
     int j, ghost;
 };
 
+// node gi of a grid of ext nodes along a direction with wall type bc (0 periodic: wrapped,
+// gi in [-ext, 2 ext) -- the rows a strip reads lie in [-1, ext]; else clamped to the wall
+// node, a ghost image)
 __device__ inline Map1 map_node(int gi, int ext, int bc)
 {
     Map1 m;
     m.ghost = 0;
     if (bc == 0) {
-        int j = gi % ext;
-        if (j < 0) j += ext;
-        m.j = j;
+        m.j = gi < 0 ? gi + ext : (gi >= ext ? gi - ext : gi);
     } else if (gi < 0) {
         m.j = 0;
         m.ghost = 1;
@@ -172,7 +174,10 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
     using MF = Mf2<T>;
     constexpr int NI = S::NI, NU = S::NU, NV = S::NV, KS = S::KS, KH = S::KH, TL = S::TL, CPC = S::CPC;
     constexpr int SX = S::SX, TSZ = S::TSZ, OS = S::OS;
-    constexpr int NLOAD = (NXN * NI + NT - 1) / NT;
+    constexpr int UE = (NXN * NU + 63) / 64 * 64; // u elements of a row, padded to whole waves
+    constexpr int NVD = NV > 0 ? NV : 1;          // (divisor; no v records in the conservative method)
+    constexpr int NE = UE + NXN * NV;
+    constexpr int NLOAD = (NE + NT - 1) / NT;
     constexpr int NBF = (CX * TL + NT - 1) / NT;
     SH& sh = *reinterpret_cast<SH*>(smem_raw);
     static_assert(NT == NT2, "one wave per (class, K half)");
@@ -192,7 +197,7 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
     const int q = wave >> 1, h = wave & 1;
     const int two = CPC > 1 ? tabs->ncl[q] > 1 : 0;
     T ta[CPC][KH];
-    int rdst[CPC][4];
+    int rdst[CPC][2]; // output slots of rows r and r + 2 packed as r | r + 2 << 16
 #pragma unroll
     for (int c = 0; c < CPC; ++c) {
 #pragma unroll
@@ -203,14 +208,21 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int o = tabs->tr[q][c][MF::row(lane, r)];
-            rdst[c][r] = o < 0 ? NI : o; // unused rows write the spare slot NI of the cell
+            // unused rows write the spare slot NI of the cell
+            const int slot = o < 0 ? NI : o;
+            if (r < 2) rdst[c][r] = slot;
+            else rdst[c][r - 2] |= slot << 16;
         }
     }
 
-    // node loads: slot i = element tid + i NT of the row's 17 x NI block; the x part and
-    // the x ghost sign are fixed per strip
+    // node loads: slot i = element tid + i NT of the row's block of the 17 u records,
+    // padded to whole waves, followed by the 17 v records, so that every wave's slot reads
+    // one array through a buffer resource made per row from its wave-uniform base; the byte
+    // offset within the row, the x ghost sign and the LDS slot are fixed per strip (x
+    // positions past the periodic wrap of a narrow grid are mapped with the modulo)
     const int ex0 = a.ext_from[0], ex1 = a.ext_from[1];
-    int ld_off[NLOAD], ld_msk[NLOAD];
+    uint32_t ld_off[NLOAD];
+    int ld_msk[NLOAD]; // -1: idle; bit 1: negate (x ghost), bit 3: l_y odd, bits 4..: LDS slot
     // node rows in flight: PD ahead of the row being stashed (two ahead, with the registers
     // to hold them, measured no faster)
     constexpr int PD = 1;
@@ -219,25 +231,38 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
     for (int i = 0; i < NLOAD; ++i) {
         const int e = tid + i * NT;
         ld_off[i] = 0;
-        ld_msk[i] = 4; // idle slot: reads u of node 0 of the row, never stashed
-        if (e >= NXN * NI) continue;
-        const int node = e / NI, c = e % NI;
+        ld_msk[i] = -1; // idle slot: reads the row's first element, never stashed
+        int node, c;
+        if (e < NXN * NU) {
+            node = e / NU;
+            c = e % NU;
+        } else if (e >= UE && e < NE) {
+            node = (e - UE) / NVD;
+            c = NU + (e - UE) % NVD;
+        } else {
+            continue;
+        }
         int lx, ly;
         coef2<MU>(c, lx, ly);
-        const Map1 mx = map_node(x0 + off + node, ex0, a.bc[0]);
-        ld_off[i] = c < NU ? mx.j * NU + c : mx.j * NV + (c - NU);
+        int gx = x0 + off + node;
+        if (a.bc[0] == 0) gx = ((gx % ex0) + ex0) % ex0;
+        const Map1 mx = map_node(gx, ex0, a.bc[0]);
+        ld_off[i] = (uint32_t)((c < NU ? (int64_t)mx.j * NU + c : (int64_t)mx.j * NV + (c - NU)) * (int64_t)sizeof(T));
         const bool neg = mx.ghost && flips(a.bc[0], lx);
-        ld_msk[i] = 1 | (neg ? 2 : 0) | (c < NU ? 4 : 0) | ((ly & 1) << 3);
+        ld_msk[i] = (neg ? 2 : 0) | ((ly & 1) << 3) | ((node * SX + c) << 4);
     }
+    const uint32_t ubytes = (uint32_t)((int64_t)ex0 * NU * sizeof(T)), vbytes = (uint32_t)((int64_t)ex0 * NV * sizeof(T));
     int yghost[PD] = {};
     auto fetch = [&](auto B, int gy) {
         const Map1 my = map_node(gy, ex1, a.bc[1]);
         yghost[B] = my.ghost;
         const int64_t rn = (int64_t)ex0 * my.j;
+        const __amdgpu_buffer_rsrc_t ru = make_rsrc((const void*)(gu + rn * NU), ubytes);
+        const __amdgpu_buffer_rsrc_t rv = CONS ? ru : make_rsrc((const void*)(gv + rn * NV), vbytes);
 #pragma unroll
         for (int i = 0; i < NLOAD; ++i) {
-            const GIn src = (CONS || (ld_msk[i] & 4)) ? gu + rn * NU : gv + rn * NV;
-            rl[B][i] = src[ld_off[i]];
+            const bool isu = CONS || i * NT + 64 * wave < UE; // wave-uniform
+            rl[B][i] = BufIO<T>::load(isu ? ru : rv, ld_off[i]);
         }
     };
     auto stash = [&](auto B) {
@@ -245,53 +270,99 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
         const bool yflip_odd = a.bc[1] != 1;
 #pragma unroll
         for (int i = 0; i < NLOAD; ++i) {
-            const int e = tid + i * NT;
-            if (e >= NXN * NI) break;
             const int m = ld_msk[i];
+            if (m < 0) continue;
             bool neg = (m & 2) != 0;
             if (yghost[B] && (((m >> 3) & 1) != 0) == yflip_odd) neg = !neg;
-            sh.nd[(e / NI) * SX + e % NI] = neg ? -rl[B][i] : rl[B][i];
+            sh.nd[m >> 4] = neg ? -rl[B][i] : rl[B][i];
         }
     };
 
     // staged outputs of a cell row, stored coalesced (a strip's row of cells is contiguous)
     const int nrows = cy1 - cy0 + 1; // node rows
-    constexpr int NSU = (CX * NU + NT - 1) / NT;
+    // output slots: element tid + k NT of the strip's 16 u (v) records, its byte offset
+    // within the output row fixed per strip; bit k (16 + k) of s_ok: the u (v) slot has an
+    // output inside the grid
+    constexpr int NSU = (CX * NU + NT - 1) / NT, NSV = CONS ? 1 : (CX * NV + NT - 1) / NT;
+    // (the FP64 dissipative m = 6 kernel, short of registers, recomputes them per row)
+    constexpr bool LEAN = sizeof(T) == 8 && !CONS && MU == 7;
+    constexpr int NSUK = LEAN ? 1 : NSU, NSVK = LEAN ? 1 : NSV;
+    uint32_t su_keep[NSUK], sv_keep[NSVK];
+    int s_keep = 0;
+    auto slot_u = [&](int k, bool& ok) {
+        const int i = tid + k * NT, c = i / NU, o = i % NU;
+        ok = i < CX * NU && x0 + c < a.ext_to[0];
+        return (uint32_t)(((int64_t)(x0 + c) * NU + o) * (int64_t)sizeof(T));
+    };
+    auto slot_v = [&](int k, bool& ok) {
+        const int i = tid + k * NT, c = i / NVD, o = i % NVD;
+        ok = !CONS && i < CX * NV && x0 + c < a.ext_to[0];
+        return (uint32_t)(((int64_t)(x0 + c) * NV + o) * (int64_t)sizeof(T));
+    };
+    if constexpr (!LEAN) {
+#pragma unroll
+        for (int k = 0; k < NSU; ++k) {
+            bool ok;
+            su_keep[k] = slot_u(k, ok);
+            if (ok) s_keep |= 1 << k;
+        }
+#pragma unroll
+        for (int k = 0; k < NSV; ++k) {
+            bool ok;
+            sv_keep[k] = slot_v(k, ok);
+            if (ok) s_keep |= 1 << (16 + k);
+        }
+    }
+    // byte offset of u (v) output slot k within the row; whether it has an output
+    auto su_off = [&](int k, bool& ok) {
+        if constexpr (LEAN) return slot_u(k, ok);
+        ok = (s_keep >> k) & 1;
+        return su_keep[k];
+    };
+    auto sv_off = [&](int k, bool& ok) {
+        if constexpr (LEAN) return slot_v(k, ok);
+        ok = (s_keep >> (16 + k)) & 1;
+        return sv_keep[k];
+    };
+    const uint32_t uobytes = (uint32_t)((int64_t)a.ext_to[0] * NU * sizeof(T));
+    const uint32_t vobytes = (uint32_t)((int64_t)a.ext_to[0] * NV * sizeof(T));
     T ov[CONS ? NSU : 1];
-    int64_t ogi[CONS ? NSU : 1];
     auto old_fetch = [&](int cy) {
         if constexpr (CONS) {
-            const GIn old_u = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old));
+            const GIn old_u = reinterpret_cast<GIn>(reinterpret_cast<uintptr_t>(a.u_old)) + (int64_t)a.ext_to[0] * cy * NU;
+            const __amdgpu_buffer_rsrc_t r = make_rsrc((const void*)old_u, uobytes);
 #pragma unroll
             for (int k = 0; k < NSU; ++k) {
-                const int i = tid + k * NT, c = i / NU, o = i % NU;
-                ogi[k] = -1;
-                if (i >= CX * NU || x0 + c >= a.ext_to[0]) continue;
-                ogi[k] = ((int64_t)a.ext_to[0] * cy + x0 + c) * NU + o;
-                ov[k] = old_u[ogi[k]];
+                bool ok;
+                const uint32_t o = su_off(k, ok);
+                if (ok) ov[k] = BufIO<T>::load(r, o);
             }
         }
     };
     auto store_row = [&](int cy) {
-        const GOut out_u = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out));
-        if constexpr (CONS) {
-            (void)cy;
+        const GOut out_u = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.u_out)) + (int64_t)a.ext_to[0] * cy * NU;
+        const __amdgpu_buffer_rsrc_t ru = make_rsrc((const void*)out_u, uobytes);
 #pragma unroll
-            for (int k = 0; k < NSU; ++k) {
-                const int i = tid + k * NT, c = i / NU, o = i % NU;
-                if (ogi[k] >= 0) out_u[ogi[k]] = T(2) * (sh.out[0][c * OS + o] + sh.out[1][c * OS + o]) - ov[k];
-            }
-        } else {
-            const GOut out_v = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out));
-            const int64_t rb = (int64_t)a.ext_to[0] * cy + x0;
-            for (int i = tid; i < CX * NU; i += NT) {
-                const int c = i / NU, o = i % NU;
-                if (x0 + c < a.ext_to[0]) out_u[(rb + c) * NU + o] = sh.out[0][c * OS + o] + sh.out[1][c * OS + o];
-            }
-            for (int i = tid; i < CX * NV; i += NT) {
-                const int c = i / NV, o = i % NV;
-                if (x0 + c < a.ext_to[0])
-                    out_v[(rb + c) * NV + o] = sh.out[0][c * OS + NU + o] + sh.out[1][c * OS + NU + o];
+        for (int k = 0; k < NSU; ++k) {
+            bool ok;
+            const uint32_t o = su_off(k, ok);
+            if (!ok) continue;
+            const int i = tid + k * NT, li = (i / NU) * OS + i % NU;
+            const T s2 = sh.out[0][li] + sh.out[1][li];
+            // conservative: u_new = 2 S - u_old, the old values loaded one pass earlier
+            if constexpr (CONS) BufIO<T>::store(T(2) * s2 - ov[k], ru, o);
+            else BufIO<T>::store(s2, ru, o);
+        }
+        if constexpr (!CONS) {
+            const GOut out_v = reinterpret_cast<GOut>(reinterpret_cast<uintptr_t>(a.v_out)) + (int64_t)a.ext_to[0] * cy * NV;
+            const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void*)out_v, vobytes);
+#pragma unroll
+            for (int k = 0; k < NSV; ++k) {
+                bool ok;
+                const uint32_t o = sv_off(k, ok);
+                if (!ok) continue;
+                const int i = tid + k * NT, li = (i / NVD) * OS + NU + i % NVD;
+                BufIO<T>::store(sh.out[0][li] + sh.out[1][li], rv, o);
             }
         }
     };
@@ -349,9 +420,9 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
         T* odst = sh.out[h] + cell * OS;
         // (with KS odd the second half has one K-step fewer: h and the bound are uniform).
         // Where registers are short (FP64, two chains of 22 K-steps) the B operands are read
-        // in chunks of 4 K-steps, the next chunk's reads issued before the current chunk's
+        // in chunks of 2 K-steps, the next chunk's reads issued before the current chunk's
         // products; the empty asm keeps the reads from being hoisted further.
-        constexpr int BC = (sizeof(T) == 8 && KH > 8) ? 4 : KH, NCH = (KH + BC - 1) / BC;
+        constexpr int BC = (sizeof(T) == 8 && KH > 8) ? 2 : KH, NCH = (KH + BC - 1) / BC;
         T bv[KH];
         auto bload = [&](int c) {
 #pragma unroll
@@ -377,7 +448,7 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
                 }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) odst[rdst[CPC - 1][r]] = acc1[r];
+            for (int r = 0; r < 4; ++r) odst[(rdst[CPC - 1][r & 1] >> (16 * (r >> 1))) & 0xffff] = acc1[r];
         } else {
 #pragma unroll
             for (int c = 1; c < NCH; ++c) bload(c);
@@ -386,7 +457,7 @@ __device__ void strip(const DenseArgs& a, const C2Tables<T, MU, CONS>* __restric
                 if (h * KH + j < KS) acc0 = MF::mac(ta[0][j], bv[j], acc0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) odst[rdst[0][r]] = acc0[r];
+        for (int r = 0; r < 4; ++r) odst[(rdst[0][r & 1] >> (16 * (r >> 1))) & 0xffff] = acc0[r];
     };
     fetch(std::integral_constant<int, 0>{}, cy0 + off);
     if constexpr (PD == 2) {
@@ -575,6 +646,13 @@ hipError_t by_m(int m, F f)
 
 bool hw_cmap2d_supported(int m) { return m >= 3 && m <= 6; }
 
+bool hw_cmap2d_rows_fit(int m, bool cons, bool fp64, int64_t ext)
+{
+    const int64_t nu = (int64_t)(m + 1) * (m + 1);
+    (void)cons; // the u records are the larger ones in both methods
+    return ext >= 0 && ext * nu * (fp64 ? 8 : 4) < ((int64_t)1 << 32);
+}
+
 hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool cons, bool fp64, void** out)
 {
     *out = nullptr;
@@ -592,6 +670,7 @@ hipError_t hw_cmap2d_tables_create(const std::vector<double>& G0, int m, bool co
 hipError_t hw_launch_cmap2d(const DenseArgs& a, int m, bool cons, bool fp64, int ry, hipStream_t st)
 {
     if (!a.cm2 || ry < 1) return hipErrorInvalidValue;
+    if (!hw_cmap2d_rows_fit(m, cons, fp64, std::max(a.ext_from[0], a.ext_to[0]))) return hipErrorInvalidValue;
     if (a.ext_to[0] < 1 || a.ext_to[1] < 1 || a.ext_from[0] < 1 || a.ext_from[1] < 1) return hipErrorInvalidValue;
     auto go = [&](auto T_tag, auto c_tag) {
         using T = decltype(T_tag);
