@@ -58,13 +58,18 @@ TRAFFIC_RECORD = {
     "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-hbm_bytes.md",
 }
-TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1802_05246_amd", "csrc", "kernel_cmap3d.hip")
+# the kernel's source files (the kernel and its device helpers); the digest is over their
+# contents in this order
+TRAFFIC_SOURCE = [os.path.join(ROOT, "paper_1802_05246_amd", "csrc", f) for f in ("kernel_cmap3d.hip", "buffer_io.h")]
 COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy (1 GiB read + 1 GiB written)
 
 
-def source_digest(path=TRAFFIC_SOURCE):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_digest(paths=TRAFFIC_SOURCE):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic_bytes():
