@@ -386,6 +386,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
     }
     auto pass = [&](auto B, int step) {
         constexpr int CUR = NPS == 2 ? decltype(B)::value : 0, LO = NPS == 2 ? 1 - CUR : 0;
+        // The stash, stores, loads and butterflies run at a raised wave priority, the class
+        // products at the normal one: on a SIMD shared by the two workgroups of a CU, the
+        // instructions of a workgroup heading for its next barrier are issued first and the
+        // other workgroup's product chains fill the gaps (matrix-core and vector
+        // instructions do not execute together; FP32 launch 5.32 -> 5.0 ms).
+        __builtin_amdgcn_s_setprio(1);
         stash();
         __syncthreads();
         if (step >= 2) store_layer(cz0 + step - 2);
@@ -419,6 +425,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
 #pragma unroll
             for (int pxy = 0; pxy < 4; ++pxy) prev[CUR][k][pxy] = cur[pxy];
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (step == 0) return; // the first layer only primes the sums
 
