@@ -21,7 +21,8 @@
 //   1. the row's 17 nodes, loaded into registers during the previous row, are stashed in
 //      LDS (ghost nodes outside non-periodic walls mirrored with the odd / even signs of
 //      Sec. 3.1.3); the cell row finished two rows ago is stored and the loads of the
-//      next node row are issued;
+//      next node row are issued (loads and stores through buffer resources built per row
+//      from its wave-uniform base, each lane adding a 32-bit offset fixed per strip);
 //   2. butterflies: per cell and input l, T_px[l] = x(left)[l] +- x(right)[l] of this
 //      row, combined with those of the row below (kept in registers since the previous
 //      pass) into S_{px + 2 py}[l] = T_px(lower)[l] +- T_px(upper)[l], written to LDS in
