@@ -9,8 +9,10 @@ flop and byte rates from the per-cell-update counts of the survey's counting rul
 (read one node and write one node per dissipative cell-update; read the other grid's
 node, the old node and write the new one per conservative cell-update).
 
-Run:  python -m paper_1802_05246_amd.config_rates [--only c2,c3]
-(one JSON line per (workload, precision) on stdout, a table on stderr)
+Run:  python -m paper_1802_05246_amd.config_rates [--only c2,c3] [--copy-calibration]
+(one JSON line per (workload, precision) on stdout, a table on stderr; --copy-calibration
+first runs a plain copy of 2^28 float32 values three times, the reference kernel that
+scales the FETCH_SIZE / WRITE_SIZE counters of a profiling pass)
 """
 from __future__ import annotations
 
@@ -88,11 +90,28 @@ def workloads(name, device):
     return W.c5_batch(), 4
 
 
+def copy_calibration(torch, elems=1 << 28):
+    """A plain elementwise copy of `elems` float32 values, three times (each reads 4 B and
+    writes 4 B per element)."""
+    a = torch.ones(elems, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--only", default="c1,c2,c3,c4,c5", help="comma-separated workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run the counter-calibration copy before the workloads")
     args = ap.parse_args(argv)
+    if args.copy_calibration:
+        copy_calibration(torch)
     rows = []
     for name in args.only.split(","):
         works, steps = workloads(name, "cuda")
