@@ -299,7 +299,8 @@ hw_status hw_probe_coexec(double ms_out[3]);
  * the kernel selector: HW_KERNEL_GENERIC runs one grid-stride launch over a work list
  * of (problem, cell); HW_KERNEL_AUTO / HW_KERNEL_BATCH for 2-D batches run one dense
  * launch per (m, method) group, one workgroup per tile (or strip) of all its problems, in
- * the form the autotuner chose for the group; HW_KERNEL_DENSE
+ * the form the autotuner chose for the group (in the captured graph each group's chain of
+ * launches is a branch of its own, so the groups may run concurrently); HW_KERNEL_DENSE
  * runs one dense launch per problem the dense kernel serves and one generic launch over
  * the remaining problems.
  * hw_batch_layout, hw_batch_set_state, hw_batch_cons_startup and hw_batch_get_state

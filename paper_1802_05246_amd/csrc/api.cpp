@@ -119,6 +119,10 @@ struct hw_solver {
     ProblemDesc* split_descs = nullptr; // [phase][stage 1, 2]
     int energy_grid = 0;
     hipStream_t cap_stream = nullptr;
+    // batched 2-D solvers: one capture stream per further class and fork / join events, so
+    // that each class's chain of launches is a branch of its own in the captured graph
+    std::vector<hipStream_t> class_streams;
+    std::vector<hipEvent_t> class_events;   // [0]: fork, [c]: join of class c
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<ProblemDesc> h_descs;
 };
@@ -329,14 +333,22 @@ hipError_t launch_list_any(const DenseArgs* args, const int4* items, int n, int 
     return hw_launch_dense_list(args, items, n, m, cons, fp64, staged_width(code), st);
 }
 
+// one half step of the problems of batch class C (phase: direction, q: conservative slot parity)
+hw_status launch_class_half(const hw_solver* s, const hw_solver::BatchClass& C, int phase, int q, hipStream_t st)
+{
+    const size_t n = C.probs.size();
+    HIP_TRY(launch_list_any(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.m, C.cons,
+                            s->fp64, C.tx, st));
+    return HW_OK;
+}
+
 hw_status launch_half(hw_solver* s, int phase, int q, hipStream_t st)
 {
     const int np = (int)s->probs.size();
     if (s->use_batch2d) {
         for (const auto& C : s->bclasses) {
-            const size_t n = C.probs.size();
-            HIP_TRY(launch_list_any(C.args + (size_t)(phase * 2 + q) * n, C.tiles[phase], C.ntiles[phase], C.m,
-                                    C.cons, s->fp64, C.tx, st));
+            const hw_status r = launch_class_half(s, C, phase, q, st);
+            if (r != HW_OK) return r;
         }
         return HW_OK;
     }
@@ -863,6 +875,22 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
     }
     if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail(HW_EHIP, "stream creation failed"));
+    if (s->use_batch2d && s->bclasses.size() > 1) {
+        // default-priority streams, used only while a graph is captured
+        const size_t nb = s->bclasses.size() - 1;
+        for (size_t c = 0; c < nb; ++c) {
+            hipStream_t st = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+                return cleanup(fail(HW_EHIP, "stream creation failed"));
+            s->class_streams.push_back(st);
+        }
+        for (size_t c = 0; c <= nb; ++c) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+                return cleanup(fail(HW_EHIP, "event creation failed"));
+            s->class_events.push_back(ev);
+        }
+    }
     *out = s;
     return HW_OK;
 }
@@ -979,6 +1007,8 @@ void hw_destroy(hw_solver* s)
     if (s->gen_prefix) (void)hipFree(s->gen_prefix);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
+    for (hipEvent_t ev : s->class_events) (void)hipEventDestroy(ev);
+    for (hipStream_t st : s->class_streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
 }
@@ -1140,9 +1170,33 @@ static hw_status graph_for(hw_solver* s, int n, hipGraphExec_t* out)
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     hw_status r = HW_OK;
-    int64_t hs = s->half_steps;
-    for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
-        r = launch_half(s, (int)(hs & 1), (int)((hs >> 1) & 1), s->cap_stream);
+    const int nb = (int)s->class_streams.size();
+    if (nb > 0) {
+        // batched 2-D problems: a class's half steps depend only on the class's own previous
+        // half step, so each class runs its whole chain as a branch of the graph (class 0
+        // on the capture stream, class c on class_streams[c - 1]), forked from one event and
+        // joined back before the capture ends; branches may then run concurrently
+        bool ok = hipEventRecord(s->class_events[0], s->cap_stream) == hipSuccess;
+        for (int c = 0; c < nb; ++c)
+            ok = ok && hipStreamWaitEvent(s->class_streams[c], s->class_events[0], 0) == hipSuccess;
+        if (!ok) r = fail(HW_EHIP, "graph fork failed");
+        for (int c = 0; c <= nb && r == HW_OK; ++c) {
+            hipStream_t st = c == 0 ? s->cap_stream : s->class_streams[c - 1];
+            int64_t hs = s->half_steps;
+            for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
+                r = launch_class_half(s, s->bclasses[c], (int)(hs & 1), (int)((hs >> 1) & 1), st);
+        }
+        // the joins are made whatever happened above, so that no stream is left capturing
+        for (int c = 0; c < nb; ++c) {
+            const bool j = hipEventRecord(s->class_events[c + 1], s->class_streams[c]) == hipSuccess &&
+                           hipStreamWaitEvent(s->cap_stream, s->class_events[c + 1], 0) == hipSuccess;
+            if (!j && r == HW_OK) r = fail(HW_EHIP, "graph join failed");
+        }
+    } else {
+        int64_t hs = s->half_steps;
+        for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)
+            r = launch_half(s, (int)(hs & 1), (int)((hs >> 1) & 1), s->cap_stream);
+    }
     hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
     if (r != HW_OK) {
         if (graph) (void)hipGraphDestroy(graph);
