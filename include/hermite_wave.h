@@ -147,7 +147,9 @@ hw_status hw_cons_startup(hw_solver* s, const double* u0, const double* v0_or_nu
                           void* stream);
 
 /* Advance n full steps (2n half steps, Sec. 3.1.2 / Sec. 4.1).  The step loop is
- * captured once per (n, buffer parity) in a hipGraph and replayed on `stream`.
+ * captured once per (n, buffer parity) in a hipGraph and replayed on `stream`; for a
+ * single 1-D problem of at most 512 cells the graph is one single-workgroup launch that
+ * runs all 2n half steps (the same per-cell arithmetic as one launch per half step).
  * Dissipative: requires the state on the primal grid. */
 hw_status hw_advance(hw_solver* s, int n_full_steps, void* stream);
 

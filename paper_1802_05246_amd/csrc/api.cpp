@@ -123,6 +123,9 @@ struct hw_solver {
     // that each class's chain of launches is a branch of its own in the captured graph
     std::vector<hipStream_t> class_streams;
     std::vector<hipEvent_t> class_events;   // [0]: fork, [c]: join of class c
+    // a small single 1-D problem: its dense arguments per half step k mod 4 on the device, for
+    // the one-launch step graph (null otherwise)
+    DenseArgs* d1_args = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<ProblemDesc> h_descs;
 };
@@ -873,6 +876,20 @@ hw_status create_impl(const hw_problem* ps, int count, hw_solver** out)
         if (hw_tiled_tables_create(s->precision, D.lam2, D.tau, &s->tiled_tables) != hipSuccess)
             return cleanup(fail(HW_EHIP, "tiled kernel table setup failed"));
     }
+    if (s->d == 1 && count == 1 && !s->dense.empty() && s->dense[0] && !s->any_generic) {
+        // a 1-D problem of at most 512 cells: a launch per half step costs more than its cells'
+        // work, so the step graph runs all its half steps in one single-workgroup launch
+        int64_t cells = 0;
+        for (int k = 0; k < 4; ++k) cells = std::max<int64_t>(cells, s->h_descs[k].n_out);
+        if (cells <= 512) {
+            DenseArgs h[4];
+            for (int k = 0; k < 4; ++k) h[k] = dense_args(s, k, 0);
+            if (hipMalloc((void**)&s->d1_args, sizeof h) != hipSuccess)
+                return cleanup(fail(HW_ENOMEM, "argument allocation failed"));
+            if (hipMemcpy(s->d1_args, h, sizeof h, hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(HW_EHIP, "argument upload failed"));
+        }
+    }
     if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return cleanup(fail(HW_EHIP, "stream creation failed"));
     if (s->use_batch2d && s->bclasses.size() > 1) {
@@ -1007,6 +1024,7 @@ void hw_destroy(hw_solver* s)
     if (s->gen_prefix) (void)hipFree(s->gen_prefix);
     if (s->work) (void)hipFree(s->work);
     if (s->split_descs) (void)hipFree(s->split_descs);
+    if (s->d1_args) (void)hipFree(s->d1_args);
     for (hipEvent_t ev : s->class_events) (void)hipEventDestroy(ev);
     for (hipStream_t st : s->class_streams) (void)hipStreamDestroy(st);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -1192,6 +1210,13 @@ static hw_status graph_for(hw_solver* s, int n, hipGraphExec_t* out)
                            hipStreamWaitEvent(s->cap_stream, s->class_events[c + 1], 0) == hipSuccess;
             if (!j && r == HW_OK) r = fail(HW_EHIP, "graph join failed");
         }
+    } else if (s->d1_args) {
+        // a small 1-D problem: all 2n half steps in one launch (the first one's index mod 4
+        // is 2 q, or any even value for the dissipative method, whose steps ignore q)
+        const Prob& P = s->probs[0];
+        if (hw_launch_dense1d_steps(s->d1_args, (int)(s->half_steps & 3), 2 * n, P.p.m,
+                                    P.p.method == HW_CONSERVATIVE, s->fp64, s->cap_stream) != hipSuccess)
+            r = fail(HW_EHIP, "one-launch 1-D step failed");
     } else {
         int64_t hs = s->half_steps;
         for (int k = 0; k < 2 * n && r == HW_OK; ++k, ++hs)

@@ -90,6 +90,11 @@ bool hw_dense_supported(int d, int m, int method, int precision);
 void hw_fill_weights(const hw_problem& p, const double h[3], ProblemDesc& D);
 void hw_cell_map(const ProblemDesc& D, std::vector<double>& G, int& n_in, int& n_out);
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st);
+// n_half consecutive half steps of one 1-D problem in one launch of one workgroup, half step
+// k0 + j (k0 = the first one's index mod 4) with the device arguments
+// args[((k0 + j) & 1) * 2 + (((k0 + j) >> 1) & 1)]; for problems of a few hundred cells
+hipError_t hw_launch_dense1d_steps(const DenseArgs* args, int k0, int n_half, int m, bool cons, bool fp64,
+                                   hipStream_t st);
 // One launch over the tiles of many 2-D problems of one (m, method), one workgroup per
 // tile: probs[i] are their descriptors, tiles {problem i, x0, y0, 0} of tile_x x
 // (256 / tile_x) cells;

@@ -217,6 +217,55 @@ __global__ void __launch_bounds__(DENSE_BLOCK) k_dense(DenseArgs a)
     dense_cell<T, D, MU, CONS>(a, cell);
 }
 
+// Many half steps of one small 1-D problem in one launch of one workgroup (a launch per half
+// step of a few dozen cells costs more than the cells' work): half step k takes its arguments
+// from args[(k & 1) * 2 + ((k >> 1) & 1)] (direction, conservative slot parity), its lanes loop
+// over the cells, and a barrier separates it from the next, whose inputs are this one's
+// outputs.  The waves of a workgroup share one CU and its vector L1, so the barrier (which
+// waits for the stores) is all the visibility the next half step's loads need.
+template <typename T, int MU, bool CONS>
+__global__ void __launch_bounds__(DENSE_BLOCK) k_dense1d_steps(const DenseArgs* __restrict__ args, int k0, int n_half)
+{
+    for (int k = k0; k < k0 + n_half; ++k) {
+        const DenseArgs a = args[(k & 1) * 2 + ((k >> 1) & 1)];
+        for (int64_t cell = threadIdx.x; cell < a.n_cells; cell += DENSE_BLOCK) dense_cell<T, 1, MU, CONS>(a, cell);
+        __syncthreads();
+    }
+}
+
+template <typename T, int MU, bool CONS>
+hipError_t launch_1d_steps(const DenseArgs* args, int k0, int n_half, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_dense1d_steps<T, MU, CONS>), dim3(1), dim3(DENSE_BLOCK), 0, st, args, k0, n_half);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_1d_steps(const DenseArgs* args, int k0, int n_half, int m, bool cons, hipStream_t st)
+{
+    if (cons) {
+        switch (m) {
+        case 0: return launch_1d_steps<T, 1, true>(args, k0, n_half, st);
+        case 1: return launch_1d_steps<T, 2, true>(args, k0, n_half, st);
+        case 2: return launch_1d_steps<T, 3, true>(args, k0, n_half, st);
+        case 3: return launch_1d_steps<T, 4, true>(args, k0, n_half, st);
+        case 4: return launch_1d_steps<T, 5, true>(args, k0, n_half, st);
+        case 5: return launch_1d_steps<T, 6, true>(args, k0, n_half, st);
+        case 6: return launch_1d_steps<T, 7, true>(args, k0, n_half, st);
+        }
+    } else {
+        switch (m) {
+        case 1: return launch_1d_steps<T, 2, false>(args, k0, n_half, st);
+        case 2: return launch_1d_steps<T, 3, false>(args, k0, n_half, st);
+        case 3: return launch_1d_steps<T, 4, false>(args, k0, n_half, st);
+        case 4: return launch_1d_steps<T, 5, false>(args, k0, n_half, st);
+        case 5: return launch_1d_steps<T, 6, false>(args, k0, n_half, st);
+        case 6: return launch_1d_steps<T, 7, false>(args, k0, n_half, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
 // ---------------------------------------------------------------------------------
 // LDS-staged 2-D form: a workgroup's tile of TX x TY cells (TX TY = 256) first copies the
 // (TX+1) x (TY+1) input nodes it needs into LDS with coalesced loads (a row of nodes is
@@ -801,6 +850,15 @@ hipError_t hw_launch_dense_list(const DenseArgs* probs, const int4* tiles, int n
     if (n_tiles > INT32_MAX - 7) return hipErrorInvalidValue;
     return fp64 ? dispatch_list<double>(probs, tiles, n_tiles, m, cons, staged_tx, st)
                 : dispatch_list<float>(probs, tiles, n_tiles, m, cons, staged_tx, st);
+}
+
+hipError_t hw_launch_dense1d_steps(const DenseArgs* args, int k0, int n_half, int m, bool cons, bool fp64,
+                                   hipStream_t st)
+{
+    if (!args || k0 < 0 || k0 > 3 || n_half < 0 || n_half > INT32_MAX - 4) return hipErrorInvalidValue;
+    if (n_half == 0) return hipSuccess;
+    return fp64 ? dispatch_1d_steps<double>(args, k0, n_half, m, cons, st)
+                : dispatch_1d_steps<float>(args, k0, n_half, m, cons, st);
 }
 
 hipError_t hw_launch_dense(const DenseArgs& a, int d, int m, bool cons, bool fp64, hipStream_t st)
