@@ -40,7 +40,7 @@ EXECUTED_FLOPS_PER_CELL = 2 * 11776 + 1460
 # matrix-core busy fraction of the same kernel from its counters (SQ_BUSY_CYCLES /
 # SQ_VALU_MFMA_BUSY_CYCLES pass), tied to the source it was measured on like the traffic
 MFMA_BUSY_RECORD = {
-    "source_sha256": "f3e94aeb45d8402f65da3676dfc6be6f84afd821aea5f7c7f9371a77adb03ef0",
+    "source_sha256": "c24eced0708b2188e9e287d4ea0e7c271b541b19c1ab5ddf97d7f121387893c0",
     "busy_frac": 0.50,
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-sq_counters.md",
 }
@@ -53,8 +53,8 @@ MFMA_BUSY_RECORD = {
 # tied to the source it was measured on: after any change of that file the traffic
 # is reported as null until the counters are taken again.
 TRAFFIC_RECORD = {
-    "source_sha256": "f3e94aeb45d8402f65da3676dfc6be6f84afd821aea5f7c7f9371a77adb03ef0",
-    "fetch_bytes": 8899749506,  # FETCH_SIZE 4345705.0 KiB x 1048576/524303.0 (copy: 1 GiB read)
+    "source_sha256": "c24eced0708b2188e9e287d4ea0e7c271b541b19c1ab5ddf97d7f121387893c0",
+    "fetch_bytes": 8931630032,  # FETCH_SIZE 4361270.3 KiB x 1048576/524302.8 (copy: 1 GiB read)
     "write_bytes": 6174015488,  # WRITE_SIZE 6029312.0 KiB x 1048576/1048576.0 (copy: 1 GiB written)
     "profile": "profiles/k_cmap3d-diss3d_m3_256cube-hbm_bytes.md",
 }

@@ -353,19 +353,50 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2) k_cmap3d(TiledArgs
             if constexpr (BUF) BufIO<T>::store(v, r, (uint32_t)o);
             else *at(base, o) = v;
         };
+        if constexpr (sizeof(T) == 8) {
+            // FP64 (one workgroup per CU): every slot's staged value read first, indices
+            // clamped into the staging area, so that one wait covers the reads (the empty asm
+            // statements keep the compiler from sinking the reads into the stores' branches);
+            // in FP32 the same order measured slower
+            T su[NSU], sv[NSV];
 #pragma unroll
-        for (int k = 0; k < NSU; ++k) {
-            const int i = tid + k * NT, c = i >> 6, coef = i & 63;
-            if (!(s_ok & (1 << k))) continue;
-            // conservative: u_new = 2 S - u_old, the old values loaded one pass earlier
-            if constexpr (CONS) put(out_u, ru, su_off[k], T(2) * ou_base[c * OUS + coef] - ov[k]);
-            else put(out_u, ru, su_off[k], ou_base[c * OUS + coef]);
-        }
-        if constexpr (!CONS) {
+            for (int k = 0; k < NSU; ++k) {
+                const int i = min(tid + k * NT, NC * 64 - 1);
+                su[k] = ou_base[(i >> 6) * OUS + (i & 63)];
+            }
+            if constexpr (!CONS) {
 #pragma unroll
-            for (int k = 0; k < NSV; ++k) {
-                const int i = tid + k * NT;
-                if (s_ok & (1 << (16 + k))) put(out_v, rv, sv_off[k], ov_base[i]);
+                for (int k = 0; k < NSV; ++k) sv[k] = ov_base[min(tid + k * NT, NC * 27 - 1)];
+            }
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) asm volatile("" ::"v"(su[k]));
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) {
+                if (!(s_ok & (1 << k))) continue;
+                // conservative: u_new = 2 S - u_old, the old values loaded one pass earlier
+                if constexpr (CONS) put(out_u, ru, su_off[k], T(2) * su[k] - ov[k]);
+                else put(out_u, ru, su_off[k], su[k]);
+            }
+            if constexpr (!CONS) {
+#pragma unroll
+                for (int k = 0; k < NSV; ++k)
+                    if (s_ok & (1 << (16 + k))) put(out_v, rv, sv_off[k], sv[k]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NSU; ++k) {
+                const int i = tid + k * NT, c = i >> 6, coef = i & 63;
+                if (!(s_ok & (1 << k))) continue;
+                // conservative: u_new = 2 S - u_old, the old values loaded one pass earlier
+                if constexpr (CONS) put(out_u, ru, su_off[k], T(2) * ou_base[c * OUS + coef] - ov[k]);
+                else put(out_u, ru, su_off[k], ou_base[c * OUS + coef]);
+            }
+            if constexpr (!CONS) {
+#pragma unroll
+                for (int k = 0; k < NSV; ++k) {
+                    const int i = tid + k * NT;
+                    if (s_ok & (1 << (16 + k))) put(out_v, rv, sv_off[k], ov_base[i]);
+                }
             }
         }
     };
