@@ -1239,7 +1239,7 @@ static hw_status graph_for(hw_solver* s, int n, hipGraphExec_t* out)
 hw_status hw_prepare_advance(hw_solver* s, int n)
 {
     if (check_solver(s)) return HW_EINVAL;
-    if (n < 1) return fail(HW_EINVAL, "step count must be >= 1");
+    if (n < 1 || n > INT32_MAX / 2) return fail(HW_EINVAL, "step count %d outside 1..%d", n, INT32_MAX / 2);
     if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
     hipGraphExec_t exec = nullptr;
     return graph_for(s, n, &exec);
@@ -1248,7 +1248,7 @@ hw_status hw_prepare_advance(hw_solver* s, int n)
 hw_status hw_batch_advance(hw_solver* s, int n, void* stream)
 {
     if (check_solver(s)) return HW_EINVAL;
-    if (n < 0) return fail(HW_EINVAL, "negative step count");
+    if (n < 0 || n > INT32_MAX / 2) return fail(HW_EINVAL, "step count %d outside 0..%d", n, INT32_MAX / 2);
     if (!s->state_set) return fail(HW_ESTATE, "state not set");
     if (s->half_steps & 1) return fail(HW_ESTATE, "advance needs whole steps (odd half-step count)");
     if (n == 0) return HW_OK;
